@@ -1,0 +1,105 @@
+/*
+ * ns_oracle.h -- plain, slow CPU oracle for the explicit hyperbolic (Euler)
+ * step of Guermond, Kronbichler, Maier, Popov, Tomas (arXiv:2106.02159).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link
+ * or call this code: it exists so that the test-suite, the smoke check and
+ * the CPU-baseline leg of the benchmark have an independent reference.  It
+ * shares no source with the HIP library (its own graph assembly by Gauss
+ * quadrature, its own flux, wave-speed and limiter code).
+ *
+ * All floating point is IEEE double.  State vectors are structure-of-arrays:
+ * U[c*N + i] is component c of node i, with c = 0 density, 1..dim momentum,
+ * dim+1 total energy.
+ */
+#ifndef NS_ORACLE_H
+#define NS_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc_graph {
+  int dim;              /* 2 or 3 */
+  long n[3];            /* nodes per direction */
+  int periodic[3];      /* 1 = periodic direction */
+  double lo[3], hi[3];  /* box */
+  double h[3];          /* mesh size per direction */
+  long N;               /* number of nodes */
+  long nnz;             /* number of stencil entries (diagonal included) */
+  long *row_ptr;        /* N+1 */
+  long *col;            /* nnz, ascending within each row */
+  long *tr;             /* nnz: position of entry (j,i) for entry (i,j) */
+  double *mij;          /* nnz: consistent mass  int phi_i phi_j */
+  double *cij;          /* dim*nnz: cij[k*nnz+e] = int phi_i d_k phi_j */
+  double *bpair;        /* dim*nnz: int_{dOmega} phi_i phi_j n_k */
+  double *mi;           /* N: lumped mass int phi_i */
+  double *bnd;          /* dim*N: int_{dOmega} phi_i n_k */
+  int *on_wall;         /* N: 1 if the node lies on a non-periodic wall */
+} orc_graph;
+
+enum { ORC_IND_ENTROPY = 0, ORC_IND_ONE = 1, ORC_IND_ZERO = 2 };
+enum { ORC_LIM_CONVEX = 0, ORC_LIM_LOW = 1, ORC_LIM_HIGH = 2 };
+
+typedef struct orc_params {
+  double gamma;
+  double cfl;
+  int indicator;      /* ORC_IND_* */
+  int limiter;        /* ORC_LIM_* */
+  int passes;         /* limiter passes for ORC_LIM_CONVEX (1 or 2) */
+  double relax;       /* bound relaxation factor r0 (0 = strict bounds) */
+} orc_params;
+
+/* Optional per-stage intermediate results (any pointer may be NULL). */
+typedef struct orc_debug {
+  double *d;       /* nnz: d^L_ij (diagonal holds d^L_ii) */
+  double *alpha;   /* N */
+  double *UL;      /* nc*N low-order update */
+  double *FH;      /* nc*N high-order flux F^H_i */
+  double *bounds;  /* 3*N: rho_min, rho_max, Phi_min */
+  double *lt1;     /* nnz: pass-1 limiter before symmetrisation */
+  double *l1;      /* nnz: pass-1 limiter after symmetrisation */
+  double *lt2;     /* nnz: pass-2 limiter before symmetrisation */
+  double *l2;      /* nnz */
+  double *U1;      /* nc*N state after pass 1 */
+} orc_debug;
+
+int orc_graph_build(int dim, const long *n, const double *lo, const double *hi,
+                    const int *periodic, orc_graph **out);
+void orc_graph_free(orc_graph *g);
+long orc_graph_N(const orc_graph *g);
+long orc_graph_nnz(const orc_graph *g);
+/* Copies the graph out into caller-owned arrays (any may be NULL). */
+void orc_graph_export(const orc_graph *g, long *row_ptr, long *col, long *tr,
+                      double *mij, double *cij, double *bpair, double *mi,
+                      double *bnd, int *on_wall);
+
+double orc_pressure(double gamma, int dim, const double *u);
+double orc_lambda_max(double gamma, int dim, const double *ui, const double *uj,
+                      const double *nij);
+double orc_line_search(double gamma, int dim, const double *u, const double *P,
+                       double rho_min, double rho_max, double phi_min);
+
+/* tau = cfl * min_i(-m_i / (2 d_ii)); returns 0. */
+int orc_compute_dt(const orc_graph *g, const orc_params *p, const double *U,
+                   double *tau);
+/* One forward-Euler stage (no boundary post-processing).  Returns 0, or 1 if
+ * tau exceeds min_i(-m_i/(2 d_ii)) (the stage CFL limit at c_cfl = 1); the
+ * output is computed either way. */
+int orc_fe_stage(const orc_graph *g, const orc_params *p, const double *U,
+                 double tau, double *Uout, orc_debug *dbg);
+/* Slip post-processing at every wall node, in place. */
+void orc_slip_bc(const orc_graph *g, double *U);
+/* One SSPRK(3,3) step with slip post-processing after every stage.
+ * Returns 0, or 1 if any stage violated its CFL limit. */
+int orc_ssprk3_step(const orc_graph *g, const orc_params *p, const double *U,
+                    double tau, double *Uout);
+/* Unlimited high-order update computed directly from M_L (U^H - U) =
+ * tau (I + B) F^H, used to check the limiter's l = 1 special case. */
+int orc_high_order_direct(const orc_graph *g, const orc_params *p,
+                          const double *U, double tau, double *UH);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,205 @@
+"""Python handle on the plain C oracle (``ns_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py``; never by the product package.
+
+``build()`` compiles ``libns_oracle.so`` with gcc (``-O2``, no fast-math, no
+FMA contraction).  ``Graph`` wraps the oracle's quadrature-assembled graph and
+exposes the stage, step and time-step routines on NumPy arrays in the same
+structure-of-arrays layout the library uses: ``U[c, i]``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "ns_oracle.c")
+LIB = os.path.join(HERE, "libns_oracle.so")
+
+IND_ENTROPY, IND_ONE, IND_ZERO = 0, 1, 2
+LIM_CONVEX, LIM_LOW, LIM_HIGH = 0, 1, 2
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle shared library (plain C, gcc)."""
+    if force or not os.path.exists(LIB):
+        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
+               "-fno-fast-math", "-Wall", "-o", LIB, SRC, "-lm"]
+        subprocess.check_call(cmd)
+    return LIB
+
+
+class _Params(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("cfl", C.c_double),
+                ("indicator", C.c_int), ("limiter", C.c_int),
+                ("passes", C.c_int), ("relax", C.c_double)]
+
+
+class _Debug(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in
+                ("d", "alpha", "UL", "FH", "bounds", "lt1", "l1", "lt2", "l2",
+                 "U1")]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build(force=False)
+        L = C.CDLL(LIB)
+        dp = C.POINTER(C.c_double)
+        lp = C.POINTER(C.c_long)
+        L.orc_graph_build.argtypes = [C.c_int, lp, dp, dp, C.POINTER(C.c_int),
+                                      C.POINTER(C.c_void_p)]
+        L.orc_graph_free.argtypes = [C.c_void_p]
+        L.orc_graph_N.argtypes = [C.c_void_p]
+        L.orc_graph_N.restype = C.c_long
+        L.orc_graph_nnz.argtypes = [C.c_void_p]
+        L.orc_graph_nnz.restype = C.c_long
+        L.orc_graph_export.argtypes = [C.c_void_p] + [C.c_void_p] * 9
+        L.orc_pressure.argtypes = [C.c_double, C.c_int, dp]
+        L.orc_pressure.restype = C.c_double
+        L.orc_lambda_max.argtypes = [C.c_double, C.c_int, dp, dp, dp]
+        L.orc_lambda_max.restype = C.c_double
+        L.orc_line_search.argtypes = [C.c_double, C.c_int, dp, dp, C.c_double,
+                                      C.c_double, C.c_double]
+        L.orc_line_search.restype = C.c_double
+        L.orc_compute_dt.argtypes = [C.c_void_p, C.POINTER(_Params), dp, dp]
+        L.orc_fe_stage.argtypes = [C.c_void_p, C.POINTER(_Params), dp,
+                                   C.c_double, dp, C.POINTER(_Debug)]
+        L.orc_slip_bc.argtypes = [C.c_void_p, dp]
+        L.orc_ssprk3_step.argtypes = [C.c_void_p, C.POINTER(_Params), dp,
+                                      C.c_double, dp]
+        L.orc_high_order_direct.argtypes = [C.c_void_p, C.POINTER(_Params), dp,
+                                            C.c_double, dp]
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def params(gamma=1.4, cfl=0.5, indicator=IND_ENTROPY, limiter=LIM_CONVEX,
+           passes=2, relax=1.0) -> _Params:
+    return _Params(gamma, cfl, indicator, limiter, passes, relax)
+
+
+def lambda_max(gamma, ui, uj, n) -> float:
+    ui = np.ascontiguousarray(ui, np.float64)
+    uj = np.ascontiguousarray(uj, np.float64)
+    n = np.ascontiguousarray(n, np.float64)
+    return lib().orc_lambda_max(gamma, len(n), _dp(ui), _dp(uj), _dp(n))
+
+
+def line_search(gamma, u, P, rho_min, rho_max, phi_min) -> float:
+    u = np.ascontiguousarray(u, np.float64)
+    P = np.ascontiguousarray(P, np.float64)
+    return lib().orc_line_search(gamma, len(u) - 2, _dp(u), _dp(P), rho_min,
+                                 rho_max, phi_min)
+
+
+def pressure(gamma, u) -> float:
+    u = np.ascontiguousarray(u, np.float64)
+    return lib().orc_pressure(gamma, len(u) - 2, _dp(u))
+
+
+class Graph:
+    """Oracle graph of a uniform Q1 mesh on a box (Gauss-quadrature assembly)."""
+
+    def __init__(self, dim, n, lo, hi, periodic):
+        L = lib()
+        self.dim = dim
+        nn = (C.c_long * 3)(*(list(n) + [1] * (3 - len(n))))
+        lo3 = (C.c_double * 3)(*(list(lo) + [0.0] * (3 - len(lo))))
+        hi3 = (C.c_double * 3)(*(list(hi) + [0.0] * (3 - len(hi))))
+        pp = (C.c_int * 3)(*([int(bool(x)) for x in periodic] +
+                             [0] * (3 - len(periodic))))
+        h = C.c_void_p()
+        rc = L.orc_graph_build(dim, nn, lo3, hi3, pp, C.byref(h))
+        if rc != 0:
+            raise ValueError("oracle graph build failed")
+        self.h = h
+        self.N = L.orc_graph_N(h)
+        self.nnz = L.orc_graph_nnz(h)
+        self.nc = dim + 2
+        self._export()
+
+    def _export(self):
+        N, nnz, dim = self.N, self.nnz, self.dim
+        self.row_ptr = np.empty(N + 1, np.int64)
+        self.col = np.empty(nnz, np.int64)
+        self.tr = np.empty(nnz, np.int64)
+        self.mij = np.empty(nnz, np.float64)
+        self.cij = np.empty((dim, nnz), np.float64)
+        self.bpair = np.empty((dim, nnz), np.float64)
+        self.mi = np.empty(N, np.float64)
+        self.bnd = np.empty((dim, N), np.float64)
+        self.on_wall = np.empty(N, np.int32)
+        lib().orc_graph_export(self.h, *[a.ctypes.data for a in (
+            self.row_ptr, self.col, self.tr, self.mij, self.cij, self.bpair,
+            self.mi, self.bnd, self.on_wall)])
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().orc_graph_free(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def compute_dt(self, prm, U) -> float:
+        U = np.ascontiguousarray(U, np.float64)
+        tau = C.c_double()
+        lib().orc_compute_dt(self.h, C.byref(prm), _dp(U), C.byref(tau))
+        return tau.value
+
+    def fe_stage(self, prm, U, tau, debug=False):
+        U = np.ascontiguousarray(U, np.float64)
+        out = np.empty_like(U)
+        if not debug:
+            st = lib().orc_fe_stage(self.h, C.byref(prm), _dp(U), tau, _dp(out),
+                                    None)
+            return out, st
+        N, nnz, nc = self.N, self.nnz, self.nc
+        dbg = {"d": np.zeros(nnz), "alpha": np.zeros(N),
+               "UL": np.zeros((nc, N)), "FH": np.zeros((nc, N)),
+               "bounds": np.zeros((3, N)), "lt1": np.zeros(nnz),
+               "l1": np.zeros(nnz), "lt2": np.zeros(nnz), "l2": np.zeros(nnz),
+               "U1": np.zeros((nc, N))}
+        D = _Debug(*[dbg[k].ctypes.data for k in
+                     ("d", "alpha", "UL", "FH", "bounds", "lt1", "l1", "lt2",
+                      "l2", "U1")])
+        st = lib().orc_fe_stage(self.h, C.byref(prm), _dp(U), tau, _dp(out),
+                                C.byref(D))
+        return out, st, dbg
+
+    def slip_bc(self, U):
+        U = np.array(U, np.float64, order="C", copy=True)
+        lib().orc_slip_bc(self.h, _dp(U))
+        return U
+
+    def ssprk3_step(self, prm, U, tau):
+        U = np.ascontiguousarray(U, np.float64)
+        out = np.empty_like(U)
+        st = lib().orc_ssprk3_step(self.h, C.byref(prm), _dp(U), tau, _dp(out))
+        return out, st
+
+    def high_order_direct(self, prm, U, tau):
+        U = np.ascontiguousarray(U, np.float64)
+        out = np.empty_like(U)
+        lib().orc_high_order_direct(self.h, C.byref(prm), _dp(U), tau, _dp(out))
+        return out
+
+    # -- helpers for tests -------------------------------------------------
+    def rows(self):
+        for i in range(self.N):
+            yield i, range(self.row_ptr[i], self.row_ptr[i + 1])
