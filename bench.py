@@ -1,0 +1,170 @@
+"""Throughput of the explicit hyperbolic step (SSPRK(3,3) with convex
+limiting) on one MI355X.
+
+One benchmark step = one SSPRK(3,3) step of the whole hot path: the time
+step computed on the device from the first stage's graph viscosity, three
+forward-Euler stages (graph viscosity, indicator, low-order update, bounds,
+high-order flux, two limiter passes) and the slip post-processing after
+each stage.  Workload: 2D Euler, gamma = 1.4, Q1 on a 4096x4096-node uniform
+mesh of [0,1]^2 with reflecting walls, seeded four-quadrant Riemann data, FP64.
+Metric: DoF-updates per second per SSP-RK stage = nodes x 3 x steps / time.
+
+Prints one JSON line.  --gpus above 1 is not supported (one GPU per run).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2106_02159_amd import abi, workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per node per launch of each kernel (FP64, slot-major ELL
+# with int32 columns and uint8 transpose slots; every array a kernel touches
+# counted once; W = 3^d slots, nc = d + 2 components).
+def kernel_bytes(name: str, dim: int) -> float:
+    Wd = 3 ** dim
+    nc = dim + 2
+    na = dim + 5
+    col, trk, edge = 4 * Wd, 1 * Wd, 8 * Wd
+    cvec = 8 * dim * Wd
+    node = 8
+    table = {
+        "prim": nc * node + na * node,
+        "visc": col + cvec + trk / 2 + nc * node + (na - 1) * node + 1 + edge + node,
+        "visc_dt": col + cvec + trk / 2 + (dim + 3) * node + 1 + edge,
+        "dt_partial": col + edge + node,
+        "lo": col + cvec + edge + nc * node + (dim + 2) * node + node + 3 * node
+              + 2 * nc * node + 3 * node,
+        "lim1": col + 2 * edge + 3 * nc * node + 3 * node + 3 * node + edge,
+        "lim2": col + trk + 3 * edge + 3 * nc * node + 3 * node + 3 * node
+                + nc * node + edge,
+        "fin": col + trk + 4 * edge + 4 * nc * node + 3 * node + nc * node,
+        "combine": 2 * nc * node + nc * node,
+        "slip": 0.0,
+        "dt_final": 0.0,
+    }
+    return float(table.get(name, 0.0))
+
+
+def stage_algorithmic_bytes(dim: int) -> float:
+    """Bytes per node per forward-Euler stage if the graph (col, c_ij, m_ij,
+    m_i) and the state were each moved once: 345 B in 2D, 1087 B in 3D."""
+    Wd = 3 ** dim
+    nc = dim + 2
+    return 4 * Wd + 8 * dim * Wd + 8 * Wd + 8 + 2 * 8 * nc + 8 * nc * 2 / 3
+
+
+def cpu_baseline(n_sample: int, seed: int):
+    """The oracle, as it stands, on one SSPRK(3,3) step of the same workload
+    at n_sample x n_sample nodes (graph assembly not timed)."""
+    from oracle import oracle as O
+    O.build(force=False)
+    mesh, U = W.four_quadrant_state(n_sample, seed=seed)
+    og = O.Graph(2, mesh.n, mesh.lo, mesh.hi, mesh.periodic)
+    prm = O.params(cfl=0.5)
+    U = og.slip_bc(U)
+    t0 = time.perf_counter()
+    tau = og.compute_dt(prm, U)
+    og.ssprk3_step(prm, U, tau)
+    dt = time.perf_counter() - t0
+    return {"value": og.N * 3 / dt, "unit": "DoF-updates/s per SSP-RK stage",
+            "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"one SSPRK3 step (time step + 3 stages) of the four-quadrant "
+                      f"workload at {n_sample}x{n_sample} nodes, seed {seed}, "
+                      f"{dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=4096, help="nodes per direction")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-sample", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the hyperbolic step is benchmarked "
+              "on a single MI355X (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    n = args.n
+    t0 = time.perf_counter()
+    mesh, U = W.four_quadrant_state(n, seed=args.seed)
+    graph = abi.Graph(mesh)
+    solver = abi.Solver(graph, gamma=1.4, cfl=0.5)
+    solver.set_state(U)
+    del U
+    setup_s = time.perf_counter() - t0
+    for _ in range(args.warmup):
+        solver.step_cfl()
+    solver.sync()
+    solver.profile(True)
+    solver.sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        solver.step_cfl()
+    solver.sync()
+    elapsed = time.perf_counter() - t0
+    rep = solver.profile_report()
+    solver.profile(False)
+
+    N = graph.N
+    stages = 3 * args.steps
+    value = N * stages / elapsed
+    dim = 2
+    # dominant kernel by summed time
+    dom = max(rep.items(), key=lambda kv: kv[1][1])
+    dname, (dlaunch, dms) = dom
+    avg_s = dms / dlaunch * 1e-3
+    kb = kernel_bytes(dname, dim) * N
+    achieved = kb / avg_s / 1e9
+    kern = {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1),
+                "algorithmic_GBs": kernel_bytes(k, dim) * N / (v[1] / max(v[0], 1) * 1e-3) / 1e9
+                if kernel_bytes(k, dim) > 0 else None}
+            for k, v in rep.items()}
+    stage_frac = stage_algorithmic_bytes(dim) * value / (HBM_PEAK_GBS * 1e9)
+    out = {
+        "metric": "DoF-updates/s per SSP-RK stage",
+        "value": value,
+        "unit": "DoF-updates/s per SSP-RK stage",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"2D Euler gamma=1.4, Q1 {n}x{n} nodes on [0,1]^2, "
+                               f"reflecting walls, seeded four-quadrant Riemann data "
+                               f"(seed {args.seed}), SSPRK3 + 2-pass convex limiting, "
+                               f"CFL 0.5",
+                   "nodes": N, "stages_per_step": 3},
+        "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None},
+        "stage_algorithmic_frac": stage_frac,
+        "kernels": kern,
+        "setup_s": setup_s,
+        "device_bytes": solver.device_bytes(),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample, args.seed)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,199 @@
+/*
+ * ns.h -- C ABI of libns: the explicit hyperbolic (Euler) step of
+ * Guermond, Kronbichler, Maier, Popov, Tomas, "On the implementation of a
+ * robust and efficient finite element-based parallel solver for the
+ * compressible Navier-Stokes equations" (arXiv:2106.02159), on AMD MI355X.
+ *
+ * Scope: continuous Q1 elements on uniform box meshes (2D quadrilaterals,
+ * 3D hexahedra), ideal-gas Euler flux, graph viscosity from a guaranteed
+ * maximum wave speed, low-order update, local bounds, high-order flux with
+ * the approximate inverse mass matrix, convex limiting (Sec. 3, Algorithm 1),
+ * SSPRK(3,3) with slip post-processing after every stage (Sec. 4.1-4.2).
+ *
+ * Conventions shared by every call:
+ *   - Status codes: NS_OK (0) or a negative NS_E* value.  No call throws.
+ *   - A state is structure-of-arrays double precision: U[c*N + i] is
+ *     component c of node i; c = 0 density rho, 1..dim momentum m,
+ *     dim+1 total energy E; nc = dim+2 components.
+ *   - Nodes are numbered lexicographically, x fastest:
+ *     i = ix + nx*(iy + ny*iz).
+ *   - All device work of a solver is ordered on one HIP stream.  Calls on
+ *     one solver must not overlap (one solver per host thread).
+ *   - Host buffers passed in are read or written before the call returns;
+ *     device buffers (flag NS_ON_DEVICE) must be hipMalloc'ed on the
+ *     solver's device and hold nc*N doubles.
+ */
+#ifndef NS_H
+#define NS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define NS_OK 0
+#define NS_EINVAL (-1)          /* bad argument                              */
+#define NS_ENOMEM (-2)          /* device or host allocation failed          */
+#define NS_EHIP (-3)            /* a HIP runtime call failed                 */
+#define NS_ENOTADMISSIBLE (-4)  /* a state has rho <= 0, eps <= 0 or a NaN   */
+#define NS_ECFL (-5)            /* dt above the stage CFL limit (c_cfl = 1)  */
+#define NS_EBOUNDS (-6)         /* a stage produced an inadmissible state    */
+#define NS_ESTATE (-7)          /* no state has been set                     */
+
+/* ---- options ------------------------------------------------------------ */
+/* Entropy-production indicator alpha_i of Sec. 3.2 (d^H_ij = (alpha_i +
+ * alpha_j)/2 d^L_ij): the entropy-viscosity commutator, or the constants
+ * alpha = 1 (d^H = d^L) and alpha = 0 (d^H = 0). */
+enum { NS_IND_ENTROPY = 0, NS_IND_ONE = 1, NS_IND_ZERO = 2 };
+/* Limiter of Sec. 3.3: convex limiting; l = 0 (returns the low-order update
+ * U^L of eq. loworder); l = 1 (returns the unlimited high-order update of
+ * eq. highorderCompact). */
+enum { NS_LIM_CONVEX = 0, NS_LIM_LOW = 1, NS_LIM_HIGH = 2 };
+
+/* set_state / get_state flags */
+#define NS_ON_DEVICE 1   /* the buffer is a device pointer                    */
+#define NS_NO_PROJECT 2  /* set_state: skip the slip projection of wall nodes */
+
+/* ---- mesh and graph (Sec. 2.2) ----------------------------------------- */
+/* Uniform box mesh.  n[d] counts nodes in direction d.  A periodic direction
+ * has mesh size (hi-lo)/n and needs n >= 3; a direction bounded by walls has
+ * mesh size (hi-lo)/(n-1) and needs n >= 2.  Every non-periodic face is a
+ * slip (reflecting) wall for the hyperbolic step (Sec. 4.2, eq. slip_bc). */
+typedef struct ns_mesh_desc {
+  int dim;          /* 2 or 3 */
+  int64_t n[3];     /* nodes per direction (n[2] ignored when dim == 2) */
+  double lo[3];
+  double hi[3];
+  int periodic[3];  /* nonzero = periodic */
+} ns_mesh_desc;
+
+typedef struct ns_graph ns_graph;
+
+/* Builds the stencil graph I(i) of the Q1 space and the quantities of
+ * Sec. 2.2: m_i = int phi_i, m_ij = int phi_i phi_j, c_ij = int phi_i
+ * grad phi_j, and the boundary integrals int_{dOmega} phi_i n used for the
+ * slip normals (eq. unit_normal_vector).  The library owns the graph (host
+ * memory); it must outlive every solver created from it.
+ * Errors: NS_EINVAL for dim not in {2,3}, n below the limits above, lo >= hi,
+ * more than 2^31-1 nodes, or a NULL pointer; NS_ENOMEM. */
+int ns_graph_create(const ns_mesh_desc *mesh, ns_graph **out);
+void ns_graph_destroy(ns_graph *g);
+
+/* Sizes of the graph: N nodes, nnz stencil entries (diagonal included),
+ * spatial dimension and the row width W = 3^dim of its ELL storage. */
+int ns_graph_info(const ns_graph *g, int64_t *n_nodes, int64_t *nnz, int *dim,
+                  int *width);
+
+/* Copies the graph into caller-owned host arrays in slot-major ELL layout:
+ * entry (slot k, node i) sits at index k*N + i, k < W.  Missing entries
+ * (rows shorter than W at walls) have col = -1 and zero coefficients.
+ * col: W*N int32; mij: W*N; cij: dim*W*N (component-major, cij[(d*W+k)*N+i]);
+ * mi: N; bnd: dim*N (int_{dOmega} phi_i n_d).  Any pointer may be NULL. */
+int ns_graph_export(const ns_graph *g, int32_t *col, double *mij, double *cij,
+                    double *mi, double *bnd);
+
+/* ---- solver ------------------------------------------------------------ */
+typedef struct ns_params {
+  double gamma;   /* ratio of specific heats, 1 < gamma <= 5/3            */
+  double cfl;     /* c_cfl of eq. dtCfl, 0 < cfl <= 1                      */
+  int indicator;  /* NS_IND_*                                              */
+  int limiter;    /* NS_LIM_*                                              */
+  int passes;     /* limiter passes for NS_LIM_CONVEX: 1 or 2 (paper: 2)   */
+  double relax;   /* bound relaxation r0 >= 0: the line search accepts
+                     rho in [(1-r_i) rho_min, (1+r_i) rho_max] and
+                     Phi >= (1-r_i) Phi_min, r_i = r0 (m_i/|Omega|)^(3/(2d));
+                     0 = the strict bounds of Sec. 3.3                      */
+} ns_params;
+
+typedef struct ns_solver ns_solver;
+
+/* Creates a solver on the current HIP device.  `stream` is a hipStream_t to
+ * order all work on, or NULL for a stream the solver creates and owns.  All
+ * device memory (graph arrays, three state buffers, per-edge d_ij and
+ * limiter arrays, per-node scratch) is allocated here.
+ * Errors: NS_EINVAL for bad parameters; NS_ENOMEM if the device footprint
+ * does not fit; NS_EHIP. */
+int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
+                     ns_solver **out);
+void ns_solver_destroy(ns_solver *s);
+
+/* Copies a state in (host or, with NS_ON_DEVICE, device buffer of nc*N
+ * doubles).  The state is checked: NS_ENOTADMISSIBLE if any rho <= 0,
+ * eps = E - |m|^2/(2 rho) <= 0 or a value is not finite (ns_last_error
+ * names the first such node), and the previous state is kept.  Unless
+ * NS_NO_PROJECT is given the momentum of every wall node is projected on
+ * the wall (eq. slip_bc), so that the initial data satisfy the slip
+ * condition that the global-conservation lemma assumes. */
+int ns_set_state(ns_solver *s, const double *U, int flags);
+
+/* Copies the current state out (stream-ordered, synchronous). */
+int ns_get_state(ns_solver *s, double *U, int flags);
+
+/* tau = c_cfl * min_i(-m_i / (2 d^L_ii)) for the current state (Sec. 3.1,
+ * eq. dtCfl).  Synchronous; NS_ESTATE without a state. */
+int ns_compute_dt(ns_solver *s, double *dt);
+
+/* One SSPRK(3,3) step of size dt (Sec. 4.1, eq. SPPRK33): three
+ * forward-Euler stages with the same dt, each followed by the SSP
+ * combination and the slip post-processing.  Transactional: on any error
+ * the state is left unchanged.  NS_ECFL if dt exceeds min_i(-m_i/(2 d_ii))
+ * (the stage limit at c_cfl = 1) in any stage -- the caller restarts with a
+ * smaller dt; NS_EBOUNDS if a stage produced an inadmissible state. */
+int ns_step(ns_solver *s, double dt);
+
+/* Same, with dt = c_cfl * min_i(-m_i/(2 d_ii)) computed on the device in the
+ * first stage from that stage's own d_ij and reused by stages 2 and 3
+ * (Sec. 3.1).  The dt used is returned in *dt (may be NULL). */
+int ns_step_cfl(ns_solver *s, double *dt);
+
+/* Test access: one forward-Euler stage of size dt from the current state,
+ * without SSP combination or post-processing; the result and every
+ * intermediate are kept for ns_get_debug and the state is not changed.
+ * Returns NS_ECFL (after computing everything) if dt exceeds the stage
+ * limit, like the step. */
+int ns_fe_stage(ns_solver *s, double dt);
+
+/* Intermediates of the last stage run (ns_fe_stage, or the last stage of
+ * the last step).  Edge arrays use the ELL layout of ns_graph_export. */
+enum {
+  NS_DBG_STAGE_OUT = 0, /* nc*N   stage result                            */
+  NS_DBG_D = 1,         /* W*N    d^L_ij (off-diagonal entries)           */
+  NS_DBG_ALPHA = 2,     /* N      alpha_i                                 */
+  NS_DBG_UL = 3,        /* nc*N   low-order update U^L                    */
+  NS_DBG_FH = 4,        /* nc*N   high-order flux F^H_i                   */
+  NS_DBG_BOUNDS = 5,    /* 3*N    relaxed rho_min, rho_max, Phi_min       */
+  NS_DBG_LT1 = 6,       /* W*N    pass-1 limiter before symmetrisation    */
+  NS_DBG_LT2 = 7,       /* W*N    pass-2 limiter before symmetrisation    */
+  NS_DBG_U1 = 8         /* nc*N   state after limiter pass 1              */
+};
+int ns_get_debug(ns_solver *s, int what, double *out);
+
+/* ---- timing and diagnostics ------------------------------------------- */
+/* Waits for all work queued on the solver's stream. */
+int ns_sync(ns_solver *s);
+/* The hipStream_t the solver launches on. */
+void *ns_stream(ns_solver *s);
+/* Per-kernel timing: while enabled, every kernel launch is bracketed by a
+ * pair of HIP events on the solver's stream; enabling resets the counters. */
+int ns_profile_enable(ns_solver *s, int on);
+/* Number of distinct kernels timed so far. */
+int ns_profile_count(ns_solver *s);
+/* For the k-th timed kernel: its name, number of launches and summed
+ * duration in milliseconds.  Synchronises.  NS_EINVAL if k is out of range. */
+int ns_profile_get(ns_solver *s, int k, const char **name, int64_t *launches,
+                   double *total_ms);
+/* Device bytes allocated by the solver. */
+int64_t ns_device_bytes(const ns_solver *s);
+/* Message describing the last error of the solver (never NULL). */
+const char *ns_last_error(const ns_solver *s);
+/* Message of the last failed ns_graph_create / ns_solver_create on this
+ * thread. */
+const char *ns_create_error(void);
+const char *ns_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NS_H */

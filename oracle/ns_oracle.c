@@ -38,6 +38,9 @@
 #include "ns_oracle.h"
 
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -228,6 +231,14 @@ void orc_graph_free(orc_graph *g) {
 }
 
 long orc_graph_N(const orc_graph *g) { return g->N; }
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 long orc_graph_nnz(const orc_graph *g) { return g->nnz; }
 
 void orc_graph_export(const orc_graph *g, long *row_ptr, long *col, long *tr,

@@ -68,6 +68,8 @@ int orc_graph_build(int dim, const long *n, const double *lo, const double *hi,
                     const int *periodic, orc_graph **out);
 void orc_graph_free(orc_graph *g);
 long orc_graph_N(const orc_graph *g);
+/* Number of OpenMP threads the row loops use (1 without OpenMP). */
+int orc_num_threads(void);
 long orc_graph_nnz(const orc_graph *g);
 /* Copies the graph out into caller-owned arrays (any may be NULL). */
 void orc_graph_export(const orc_graph *g, long *row_ptr, long *col, long *tr,

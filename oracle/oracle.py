@@ -63,6 +63,7 @@ def lib():
         L.orc_graph_N.restype = C.c_long
         L.orc_graph_nnz.argtypes = [C.c_void_p]
         L.orc_graph_nnz.restype = C.c_long
+        L.orc_num_threads.restype = C.c_int
         L.orc_graph_export.argtypes = [C.c_void_p] + [C.c_void_p] * 9
         L.orc_pressure.argtypes = [C.c_double, C.c_int, dp]
         L.orc_pressure.restype = C.c_double
@@ -86,6 +87,10 @@ def lib():
 def _dp(a: np.ndarray):
     assert a.dtype == np.float64 and a.flags.c_contiguous
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()
 
 
 def params(gamma=1.4, cfl=0.5, indicator=IND_ENTROPY, limiter=LIM_CONVEX,

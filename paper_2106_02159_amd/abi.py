@@ -1,0 +1,249 @@
+"""Thin ctypes binding of libns (include/ns.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module only converts NumPy
+arrays and Python numbers to the C ABI.  Importing it does not touch the GPU.
+``lib()`` raises ``ImportError`` when ``libns.so`` has not been built: there
+is no fallback of any kind.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libns.so")
+
+# status codes (ns.h)
+NS_OK, NS_EINVAL, NS_ENOMEM, NS_EHIP = 0, -1, -2, -3
+NS_ENOTADMISSIBLE, NS_ECFL, NS_EBOUNDS, NS_ESTATE = -4, -5, -6, -7
+IND_ENTROPY, IND_ONE, IND_ZERO = 0, 1, 2
+LIM_CONVEX, LIM_LOW, LIM_HIGH = 0, 1, 2
+ON_DEVICE, NO_PROJECT = 1, 2
+DBG = {"stage_out": 0, "d": 1, "alpha": 2, "UL": 3, "FH": 4, "bounds": 5,
+       "lt1": 6, "lt2": 7, "U1": 8}
+
+EXPORTED = [
+    "ns_graph_create", "ns_graph_destroy", "ns_graph_info", "ns_graph_export",
+    "ns_solver_create", "ns_solver_destroy", "ns_set_state", "ns_get_state",
+    "ns_compute_dt", "ns_step", "ns_step_cfl", "ns_fe_stage", "ns_get_debug",
+    "ns_sync", "ns_stream", "ns_profile_enable", "ns_profile_count",
+    "ns_profile_get", "ns_device_bytes", "ns_last_error", "ns_create_error",
+    "ns_strerror",
+]
+
+
+class NSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int64 * 3), ("lo", C.c_double * 3),
+                ("hi", C.c_double * 3), ("periodic", C.c_int * 3)]
+
+
+class Params(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("cfl", C.c_double),
+                ("indicator", C.c_int), ("limiter", C.c_int), ("passes", C.c_int),
+                ("relax", C.c_double)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built: run "
+                              "`python -m paper_2106_02159_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, dp = C.c_void_p, C.POINTER(C.c_double)
+        i64p = C.POINTER(C.c_int64)
+        sig = {
+            "ns_graph_create": (C.c_int, [C.POINTER(MeshDesc), C.POINTER(vp)]),
+            "ns_graph_destroy": (None, [vp]),
+            "ns_graph_info": (C.c_int, [vp, i64p, i64p, C.POINTER(C.c_int),
+                                        C.POINTER(C.c_int)]),
+            "ns_graph_export": (C.c_int, [vp, vp, vp, vp, vp, vp]),
+            "ns_solver_create": (C.c_int, [vp, C.POINTER(Params), vp, C.POINTER(vp)]),
+            "ns_solver_destroy": (None, [vp]),
+            "ns_set_state": (C.c_int, [vp, vp, C.c_int]),
+            "ns_get_state": (C.c_int, [vp, vp, C.c_int]),
+            "ns_compute_dt": (C.c_int, [vp, dp]),
+            "ns_step": (C.c_int, [vp, C.c_double]),
+            "ns_step_cfl": (C.c_int, [vp, dp]),
+            "ns_fe_stage": (C.c_int, [vp, C.c_double]),
+            "ns_get_debug": (C.c_int, [vp, C.c_int, vp]),
+            "ns_sync": (C.c_int, [vp]),
+            "ns_stream": (vp, [vp]),
+            "ns_profile_enable": (C.c_int, [vp, C.c_int]),
+            "ns_profile_count": (C.c_int, [vp]),
+            "ns_profile_get": (C.c_int, [vp, C.c_int, C.POINTER(C.c_char_p), i64p, dp]),
+            "ns_device_bytes": (C.c_int64, [vp]),
+            "ns_last_error": (C.c_char_p, [vp]),
+            "ns_create_error": (C.c_char_p, []),
+            "ns_strerror": (C.c_char_p, [C.c_int]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.flags.c_contiguous
+    return a.ctypes.data
+
+
+def mesh_desc(mesh) -> MeshDesc:
+    """From any object with dim, n, lo, hi, periodic (workloads.Mesh)."""
+    d = MeshDesc()
+    d.dim = mesh.dim
+    for k in range(3):
+        d.n[k] = int(mesh.n[k]) if k < mesh.dim else 1
+        d.lo[k] = float(mesh.lo[k]) if k < mesh.dim else 0.0
+        d.hi[k] = float(mesh.hi[k]) if k < mesh.dim else 1.0
+        d.periodic[k] = int(bool(mesh.periodic[k])) if k < mesh.dim else 0
+    return d
+
+
+class Graph:
+    """ns_graph_create / ns_graph_info / ns_graph_export."""
+
+    def __init__(self, mesh):
+        L = lib()
+        h = C.c_void_p()
+        desc = mesh_desc(mesh)
+        rc = L.ns_graph_create(C.byref(desc), C.byref(h))
+        if rc != NS_OK:
+            raise NSError(rc, L.ns_create_error().decode())
+        self.h = h
+        N, nnz = C.c_int64(), C.c_int64()
+        dim, W = C.c_int(), C.c_int()
+        L.ns_graph_info(h, C.byref(N), C.byref(nnz), C.byref(dim), C.byref(W))
+        self.N, self.nnz, self.dim, self.W = N.value, nnz.value, dim.value, W.value
+
+    def export(self):
+        N, W, dim = self.N, self.W, self.dim
+        col = np.empty((W, N), np.int32)
+        mij = np.empty((W, N))
+        cij = np.empty((dim, W, N))
+        mi = np.empty(N)
+        bnd = np.empty((dim, N))
+        lib().ns_graph_export(self.h, _ptr(col), _ptr(mij), _ptr(cij), _ptr(mi),
+                              _ptr(bnd))
+        return dict(col=col, mij=mij, cij=cij, mi=mi, bnd=bnd)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ns_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Solver:
+    """ns_solver_create and the per-solver calls."""
+
+    def __init__(self, graph: Graph, gamma=1.4, cfl=0.5, indicator=IND_ENTROPY,
+                 limiter=LIM_CONVEX, passes=2, relax=1.0, stream=None):
+        L = lib()
+        self.graph = graph  # keep alive
+        self.prm = Params(gamma, cfl, indicator, limiter, passes, relax)
+        h = C.c_void_p()
+        rc = L.ns_solver_create(graph.h, C.byref(self.prm),
+                                C.c_void_p(stream) if stream else None, C.byref(h))
+        if rc != NS_OK:
+            raise NSError(rc, L.ns_create_error().decode())
+        self.h = h
+        self.N, self.dim, self.W = graph.N, graph.dim, graph.W
+        self.nc = self.dim + 2
+
+    def _check(self, rc):
+        if rc != NS_OK:
+            raise NSError(rc, lib().ns_last_error(self.h).decode())
+        return rc
+
+    def set_state(self, U, project=True):
+        U = np.ascontiguousarray(U, np.float64)
+        assert U.shape == (self.nc, self.N)
+        self._check(lib().ns_set_state(self.h, _ptr(U), 0 if project else NO_PROJECT))
+
+    def get_state(self):
+        out = np.empty((self.nc, self.N))
+        self._check(lib().ns_get_state(self.h, _ptr(out), 0))
+        return out
+
+    def compute_dt(self) -> float:
+        dt = C.c_double()
+        self._check(lib().ns_compute_dt(self.h, C.byref(dt)))
+        return dt.value
+
+    def step(self, dt: float):
+        return self._check(lib().ns_step(self.h, float(dt)))
+
+    def step_cfl(self) -> float:
+        dt = C.c_double()
+        self._check(lib().ns_step_cfl(self.h, C.byref(dt)))
+        return dt.value
+
+    def step_status(self, dt: float) -> int:
+        """ns_step returning the raw status instead of raising."""
+        return lib().ns_step(self.h, float(dt))
+
+    def fe_stage(self, dt: float) -> int:
+        return lib().ns_fe_stage(self.h, float(dt))
+
+    def debug(self, what: str):
+        N, W, nc = self.N, self.W, self.nc
+        shape = {"stage_out": (nc, N), "d": (W, N), "alpha": (N,), "UL": (nc, N),
+                 "FH": (nc, N), "bounds": (3, N), "lt1": (W, N), "lt2": (W, N),
+                 "U1": (nc, N)}[what]
+        out = np.empty(shape)
+        self._check(lib().ns_get_debug(self.h, DBG[what], _ptr(out)))
+        return out
+
+    def sync(self):
+        self._check(lib().ns_sync(self.h))
+
+    def stream(self) -> int:
+        return lib().ns_stream(self.h) or 0
+
+    def profile(self, on: bool):
+        self._check(lib().ns_profile_enable(self.h, 1 if on else 0))
+
+    def profile_report(self):
+        L = lib()
+        out = {}
+        for k in range(L.ns_profile_count(self.h)):
+            name = C.c_char_p()
+            n = C.c_int64()
+            ms = C.c_double()
+            self._check(L.ns_profile_get(self.h, k, C.byref(name), C.byref(n),
+                                         C.byref(ms)))
+            out[name.value.decode()] = (n.value, ms.value)
+        return out
+
+    def device_bytes(self) -> int:
+        return lib().ns_device_bytes(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ns_solver_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

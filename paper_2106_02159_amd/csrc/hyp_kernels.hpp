@@ -1,0 +1,87 @@
+// hyp_kernels.hpp -- HIP kernels of one forward-Euler stage of the
+// hyperbolic step (Algorithm 1 of arXiv:2106.02159), gfx950.
+//
+// Layout: node arrays are structure-of-arrays (component c of node i at
+// c*N + i); edge arrays are slot-major ELL (slot k of row i at k*N + i), so
+// lane i of a wavefront reading slot k of its row produces one coalesced
+// access per slot.  One lane owns one row; neighbour data are gathered
+// through the L1/L2 caches.  Sweeps, in dependency order (each needs the
+// previous one complete over the whole mesh):
+//   k_prim   per node: v, p, sound speed a, a p^(-(g-1)/(2g)), eta, Phi
+//   k_visc   d^L_ij for j > i (Sec. 3.1), written to (i,j) and (j,i);
+//            indicator alpha_i (Sec. 3.2)
+//   k_dt     (auto time step only) per-block min of m_i / (2 sum_j d_ij)
+//   k_lo     d_ii, stage CFL check, U^L (eq. loworder), local bounds from
+//            the bar states (eq. bar_state), F^H_i (Sec. 3.2)
+//   k_lim1   P_ij (Sec. 3.3) and the pass-1 line search l~_ij
+//   k_lim2   l_ij = min(l~_ij, l~_ji), U^(1) = U^L + lambda_i sum l P;
+//            pass-2 line search on (1 - l) P (or the final state for one pass)
+//   k_fin    l' symmetrised, U = U^(1) + lambda_i sum l' (1-l) P, SSP
+//            combination a U^n + b U and admissibility flag
+//   k_slip   slip post-processing at wall nodes (eq. slip_bc)
+#pragma once
+
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+#include "euler.hpp"
+
+namespace ns {
+
+constexpr int kBlock = 256;
+
+struct DevGraph {
+  int64_t N;
+  int W;
+  const int32_t *col;   // W*N
+  const uint8_t *trk;   // W*N: slot of the transposed entry in row col
+  const double *mij;    // W*N
+  const double *c0, *c1, *c2;  // W*N each (c2 unused in 2D)
+  const double *mi;     // N
+  const double *rmi;    // N: 1 / m_i
+  const double *lfac;   // N: |I(i)| - 1 = 1 / lambda_i
+  const double *rrel;   // N: bound relaxation r_i
+  const uint8_t *wall;  // N
+};
+
+struct StageArgs {
+  const double *U;   // stage input, nc*N
+  const double *Un;  // state at the start of the step (SSP combination)
+  double *out;       // stage output, nc*N
+  double *aux;       // (dim+5)*N
+  double *alpha;     // N
+  double *d;         // W*N
+  double *UL;        // nc*N
+  double *FH;        // nc*N
+  double *bnds;      // 3*N
+  double *lt1;       // W*N
+  double *lt2;       // W*N
+  double *U1;        // nc*N
+  double *partial;   // per-block minima for the time step
+  double *tau;       // device scalar
+  int *flags;        // [0] CFL violated, [1] inadmissible state
+  double sa, sb;     // SSP combination out = sa*Un + sb*E(U)
+  int check_cfl;
+};
+
+void launch_stage(int dim, const Gas &gas, const DevGraph &g,
+                  const StageArgs &a, int indicator, int limiter, int passes,
+                  bool auto_dt, double cfl, hipStream_t s,
+                  void (*before)(void *, const char *), void (*after)(void *),
+                  void *prof);
+
+// prim + graph viscosity + time-step reduction only (writes *a.tau).
+void launch_dt_only(int dim, const Gas &gas, const DevGraph &g,
+                    const StageArgs &a, double cfl, hipStream_t s,
+                    void (*before)(void *, const char *), void (*after)(void *),
+                    void *prof);
+
+void launch_slip(int dim, int64_t N, int nslip, const int32_t *idx,
+                 const double *nrm, double *U, hipStream_t s);
+void launch_set_scalar(double *p, double v, hipStream_t s);
+void launch_clear_flags(int *flags, hipStream_t s);
+void launch_check_state(int dim, int64_t N, const double *U, int *flags,
+                        hipStream_t s);
+
+}  // namespace ns

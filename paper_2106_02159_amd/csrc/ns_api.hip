@@ -1,0 +1,608 @@
+// ns_api.hip -- implementation of the C ABI declared in include/ns.h.
+//
+// Host side: graph construction (closed form, graph.cpp), device allocation,
+// state transfer and validation, the SSPRK(3,3) driver (Sec. 4.1, eq.
+// SPPRK33) with a device-resident time step, and per-kernel event timing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ns.h"
+#include "graph.hpp"
+#include "hyp_kernels.hpp"
+
+struct ns_graph {
+  ns::MeshGraph mg;
+};
+
+namespace {
+
+thread_local std::string g_create_error = "no error";
+
+struct Profiler {
+  bool on = false;
+  hipStream_t stream = nullptr;
+  std::vector<std::string> names;
+  std::map<std::string, int> ids;
+  std::vector<int64_t> launches;
+  std::vector<double> total_ms;
+  struct Pending { int id; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+  int cur_id = -1;
+  hipEvent_t cur_a = nullptr, cur_b = nullptr;
+
+  void reset() {
+    flush();
+    names.clear(); ids.clear(); launches.clear(); total_ms.clear();
+  }
+  void flush() {
+    for (auto &p : pending) {
+      (void)hipEventSynchronize(p.b);
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess && p.id >= 0) {
+        total_ms[p.id] += ms;
+        launches[p.id] += 1;
+      }
+      pool.emplace_back(p.a, p.b);
+    }
+    pending.clear();
+  }
+  void destroy() {
+    flush();
+    for (auto &e : pool) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    pool.clear();
+  }
+  static void before(void *self, const char *name) {
+    Profiler *P = static_cast<Profiler *>(self);
+    if (!P->on) return;
+    auto it = P->ids.find(name);
+    int id;
+    if (it == P->ids.end()) {
+      id = (int)P->names.size();
+      P->ids[name] = id;
+      P->names.emplace_back(name);
+      P->launches.push_back(0);
+      P->total_ms.push_back(0.0);
+    } else {
+      id = it->second;
+    }
+    if (P->pool.empty()) {
+      hipEvent_t a, b;
+      (void)hipEventCreate(&a);
+      (void)hipEventCreate(&b);
+      P->pool.emplace_back(a, b);
+    }
+    P->cur_a = P->pool.back().first;
+    P->cur_b = P->pool.back().second;
+    P->pool.pop_back();
+    P->cur_id = id;
+    (void)hipEventRecord(P->cur_a, P->stream);
+  }
+  static void after(void *self) {
+    Profiler *P = static_cast<Profiler *>(self);
+    if (!P->on) return;
+    (void)hipEventRecord(P->cur_b, P->stream);
+    P->pending.push_back({P->cur_id, P->cur_a, P->cur_b});
+    if (P->pending.size() > 8192) P->flush();
+  }
+};
+
+}  // namespace
+
+struct ns_solver {
+  ns::MeshGraph mg;
+  ns_params prm{};
+  ns::Gas gas{};
+  int dim = 0, nc = 0;
+  int64_t N = 0;
+  int W = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<void *> allocs;
+  int64_t bytes = 0;
+  // graph on the device
+  int32_t *col = nullptr;
+  uint8_t *trk = nullptr;
+  double *mij = nullptr, *c[3] = {nullptr, nullptr, nullptr};
+  double *mi = nullptr, *rmi = nullptr, *lfac = nullptr, *rrel = nullptr;
+  uint8_t *wall = nullptr;
+  int nslip = 0;
+  int32_t *slip_idx = nullptr;
+  double *slip_n = nullptr;
+  // state and scratch
+  double *S[3] = {nullptr, nullptr, nullptr};
+  int cur = 0;
+  bool has_state = false;
+  double *aux = nullptr, *alpha = nullptr, *d = nullptr, *UL = nullptr,
+         *FH = nullptr, *bnds = nullptr, *lt1 = nullptr, *lt2 = nullptr,
+         *U1 = nullptr, *partial = nullptr, *tau = nullptr;
+  int *flags = nullptr;
+  int *hflags = nullptr;   // pinned
+  double *htau = nullptr;  // pinned
+  int last_out = 1;        // buffer holding the last stage output
+  std::string err = "no error";
+  Profiler prof;
+
+  ns::DevGraph devgraph() const {
+    ns::DevGraph g;
+    g.N = N; g.W = W; g.col = col; g.trk = trk; g.mij = mij;
+    g.c0 = c[0]; g.c1 = c[1]; g.c2 = c[2] ? c[2] : c[1];
+    g.mi = mi; g.rmi = rmi; g.lfac = lfac; g.rrel = rrel; g.wall = wall;
+    return g;
+  }
+  ns::StageArgs args(int in, int out, double sa, double sb, int check) const {
+    ns::StageArgs a;
+    a.U = S[in]; a.Un = S[cur]; a.out = S[out];
+    a.aux = aux; a.alpha = alpha; a.d = d; a.UL = UL; a.FH = FH; a.bnds = bnds;
+    a.lt1 = lt1; a.lt2 = lt2; a.U1 = U1; a.partial = partial; a.tau = tau;
+    a.flags = flags; a.sa = sa; a.sb = sb; a.check_cfl = check;
+    return a;
+  }
+  int fail(int code, const std::string &msg) { err = msg; return code; }
+  int hipfail(hipError_t e, const char *what) {
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return NS_EHIP;
+  }
+  template <typename T> hipError_t alloc(T **p, size_t count) {
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, count * sizeof(T) > 0 ? count * sizeof(T) : 1);
+    if (e != hipSuccess) return e;
+    allocs.push_back(q);
+    bytes += (int64_t)(count * sizeof(T));
+    *p = static_cast<T *>(q);
+    return hipSuccess;
+  }
+};
+
+namespace {
+
+void release(ns_solver *s) {
+  if (!s) return;
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  s->prof.destroy();
+  for (void *p : s->allocs) (void)hipFree(p);
+  s->allocs.clear();
+  if (s->hflags) (void)hipHostFree(s->hflags);
+  if (s->htau) (void)hipHostFree(s->htau);
+  if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+}
+
+int others(int cur, int k) {  // k-th (0/1) buffer index different from cur
+  int r[2], n = 0;
+  for (int b = 0; b < 3; ++b)
+    if (b != cur) r[n++] = b;
+  return r[k];
+}
+
+int read_flags(ns_solver *s) {
+  hipError_t e = hipMemcpyAsync(s->hflags, s->flags, 4 * sizeof(int),
+                                hipMemcpyDeviceToHost, s->stream);
+  if (e != hipSuccess) return s->hipfail(e, "flag readback");
+  e = hipMemcpyAsync(s->htau, s->tau, sizeof(double), hipMemcpyDeviceToHost,
+                     s->stream);
+  if (e != hipSuccess) return s->hipfail(e, "dt readback");
+  e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return s->hipfail(e, "stream synchronize");
+  e = hipGetLastError();
+  if (e != hipSuccess) return s->hipfail(e, "kernel launch");
+  return NS_OK;
+}
+
+void run_stage(ns_solver *s, int in, int out, double sa, double sb, int check,
+               bool auto_dt) {
+  ns::launch_stage(s->dim, s->gas, s->devgraph(), s->args(in, out, sa, sb, check),
+                   s->prm.indicator, s->prm.limiter, s->prm.passes, auto_dt,
+                   s->prm.cfl, s->stream, &Profiler::before, &Profiler::after,
+                   &s->prof);
+}
+
+void run_slip(ns_solver *s, int buf) {
+  Profiler::before(&s->prof, "slip");
+  ns::launch_slip(s->dim, s->N, s->nslip, s->slip_idx, s->slip_n, s->S[buf],
+                  s->stream);
+  Profiler::after(&s->prof);
+}
+
+// One SSPRK(3,3) step; dt either given (auto_dt false) or computed in stage 1.
+int ssprk3(ns_solver *s, double dt, bool auto_dt, double *dt_out) {
+  if (!s->has_state) return s->fail(NS_ESTATE, "no state set");
+  const int o1 = others(s->cur, 0), o2 = others(s->cur, 1);
+  ns::launch_clear_flags(s->flags, s->stream);
+  if (!auto_dt) ns::launch_set_scalar(s->tau, dt, s->stream);
+  // w1 = E(u^n)
+  run_stage(s, s->cur, o1, 0.0, 1.0, auto_dt ? 0 : 1, auto_dt);
+  run_slip(s, o1);
+  // w2 = 3/4 u^n + 1/4 E(w1)
+  run_stage(s, o1, o2, 0.75, 0.25, 1, false);
+  run_slip(s, o2);
+  // u^{n+1} = 1/3 u^n + 2/3 E(w2)
+  run_stage(s, o2, o1, 1.0 / 3.0, 2.0 / 3.0, 1, false);
+  run_slip(s, o1);
+  s->last_out = o1;
+  int rc = read_flags(s);
+  if (rc != NS_OK) return rc;
+  if (dt_out) *dt_out = *s->htau;
+  if (s->hflags[0]) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "dt = %.17g exceeds the stage CFL limit", *s->htau);
+    return s->fail(NS_ECFL, buf);
+  }
+  if (s->hflags[1]) return s->fail(NS_EBOUNDS, "a stage produced an inadmissible state");
+  s->cur = o1;
+  return NS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ns_strerror(int code) {
+  switch (code) {
+    case NS_OK: return "ok";
+    case NS_EINVAL: return "invalid argument";
+    case NS_ENOMEM: return "out of memory";
+    case NS_EHIP: return "HIP runtime error";
+    case NS_ENOTADMISSIBLE: return "state not admissible";
+    case NS_ECFL: return "time step above the CFL limit";
+    case NS_EBOUNDS: return "inadmissible state produced";
+    case NS_ESTATE: return "no state set";
+    default: return "unknown status";
+  }
+}
+
+const char *ns_create_error(void) { return g_create_error.c_str(); }
+
+int ns_graph_create(const ns_mesh_desc *mesh, ns_graph **out) {
+  if (!mesh || !out) { g_create_error = "null argument"; return NS_EINVAL; }
+  ns_graph *g = new (std::nothrow) ns_graph;
+  if (!g) { g_create_error = "host allocation"; return NS_ENOMEM; }
+  const char *why = "";
+  if (ns::build_mesh_graph(mesh->dim, mesh->n, mesh->lo, mesh->hi,
+                           mesh->periodic, &g->mg, &why) != 0) {
+    g_create_error = why;
+    delete g;
+    return NS_EINVAL;
+  }
+  *out = g;
+  return NS_OK;
+}
+
+void ns_graph_destroy(ns_graph *g) { delete g; }
+
+int ns_graph_info(const ns_graph *g, int64_t *n_nodes, int64_t *nnz, int *dim,
+                  int *width) {
+  if (!g) return NS_EINVAL;
+  if (n_nodes) *n_nodes = g->mg.N;
+  if (nnz) *nnz = g->mg.nnz;
+  if (dim) *dim = g->mg.dim;
+  if (width) *width = g->mg.W;
+  return NS_OK;
+}
+
+int ns_graph_export(const ns_graph *g, int32_t *col, double *mij, double *cij,
+                    double *mi, double *bnd) {
+  if (!g) return NS_EINVAL;
+  const ns::MeshGraph &m = g->mg;
+  const int64_t N = m.N;
+  for (int k = 0; k < m.W; ++k) {
+    double *cp[3] = {nullptr, nullptr, nullptr};
+    if (cij)
+      for (int e = 0; e < m.dim; ++e) cp[e] = cij + ((int64_t)e * m.W + k) * N;
+    m.fill_slot(k, col ? col + (int64_t)k * N : nullptr, nullptr,
+                mij ? mij + (int64_t)k * N : nullptr, cij ? cp : nullptr);
+  }
+  if (mi || bnd) m.fill_nodes(mi, bnd, nullptr);
+  return NS_OK;
+}
+
+int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
+                     ns_solver **out) {
+  if (!g || !p || !out) { g_create_error = "null argument"; return NS_EINVAL; }
+  if (!(p->gamma > 1.0 && p->gamma <= 5.0 / 3.0 + 1e-12) ||
+      !(p->cfl > 0.0 && p->cfl <= 1.0) || p->indicator < 0 || p->indicator > 2 ||
+      p->limiter < 0 || p->limiter > 2 || (p->passes != 1 && p->passes != 2) ||
+      !(p->relax >= 0.0) || !std::isfinite(p->relax)) {
+    g_create_error = "invalid parameters (need 1 < gamma <= 5/3, 0 < cfl <= 1, "
+                     "indicator/limiter in range, passes 1 or 2, relax >= 0)";
+    return NS_EINVAL;
+  }
+  ns_solver *s = new (std::nothrow) ns_solver;
+  if (!s) { g_create_error = "host allocation"; return NS_ENOMEM; }
+  s->mg = g->mg;
+  s->prm = *p;
+  s->dim = g->mg.dim;
+  s->nc = s->dim + 2;
+  s->N = g->mg.N;
+  s->W = g->mg.W;
+  const double gm = p->gamma;
+  s->gas.gamma = gm;
+  s->gas.gm1 = gm - 1.0;
+  s->gas.ex = (gm - 1.0) / (2.0 * gm);
+  s->gas.inv_ex = 2.0 * gm / (gm - 1.0);
+  s->gas.cg = (gm + 1.0) / (2.0 * gm);
+  s->gas.seven = gm == 1.4 ? 1 : 0;
+
+  auto bail = [&](int code, const std::string &msg) {
+    g_create_error = msg;
+    release(s);
+    delete s;
+    return code;
+  };
+  hipError_t e;
+  if (stream) {
+    s->stream = static_cast<hipStream_t>(stream);
+  } else {
+    e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return bail(NS_EHIP, "hipStreamCreate failed");
+    s->own_stream = true;
+  }
+  s->prof.stream = s->stream;
+  const int64_t N = s->N, W = s->W, nc = s->nc, dim = s->dim;
+  const int64_t nblocks = (N + ns::kBlock - 1) / ns::kBlock;
+#define NS_ALLOC(ptr, count)                                                \
+  do {                                                                      \
+    e = s->alloc(&(ptr), (size_t)(count));                                  \
+    if (e != hipSuccess) {                                                  \
+      (void)hipGetLastError();                                              \
+      return bail(NS_ENOMEM, std::string("device allocation of ") + #ptr + \
+                                 " failed: " + hipGetErrorString(e));       \
+    }                                                                       \
+  } while (0)
+  NS_ALLOC(s->col, W * N);
+  NS_ALLOC(s->trk, W * N);
+  NS_ALLOC(s->mij, W * N);
+  for (int k = 0; k < dim; ++k) NS_ALLOC(s->c[k], W * N);
+  NS_ALLOC(s->mi, N);
+  NS_ALLOC(s->rmi, N);
+  NS_ALLOC(s->lfac, N);
+  NS_ALLOC(s->rrel, N);
+  NS_ALLOC(s->wall, N);
+  for (int b = 0; b < 3; ++b) NS_ALLOC(s->S[b], nc * N);
+  NS_ALLOC(s->aux, (dim + 5) * N);
+  NS_ALLOC(s->alpha, N);
+  NS_ALLOC(s->d, W * N);
+  NS_ALLOC(s->UL, nc * N);
+  NS_ALLOC(s->FH, nc * N);
+  NS_ALLOC(s->bnds, 3 * N);
+  NS_ALLOC(s->lt1, W * N);
+  NS_ALLOC(s->lt2, W * N);
+  NS_ALLOC(s->U1, nc * N);
+  NS_ALLOC(s->partial, nblocks);
+  NS_ALLOC(s->tau, 1);
+  NS_ALLOC(s->flags, 4);
+
+  // --- upload the graph slot by slot (host staging of one slot at a time)
+  {
+    std::vector<int32_t> col(N);
+    std::vector<uint8_t> trk(N);
+    std::vector<double> mij(N), cc((size_t)dim * N);
+    std::vector<int> cnt(N, 0);
+    for (int k = 0; k < W; ++k) {
+      double *cp[3] = {cc.data(), cc.data() + N, dim == 3 ? cc.data() + 2 * N : nullptr};
+      s->mg.fill_slot(k, col.data(), trk.data(), mij.data(), cp);
+      for (int64_t i = 0; i < N; ++i) cnt[i] += col[i] >= 0;
+      const size_t off = (size_t)k * N;
+      e = hipMemcpy(s->col + off, col.data(), N * sizeof(int32_t), hipMemcpyHostToDevice);
+      if (e == hipSuccess)
+        e = hipMemcpy(s->trk + off, trk.data(), N, hipMemcpyHostToDevice);
+      if (e == hipSuccess)
+        e = hipMemcpy(s->mij + off, mij.data(), N * sizeof(double), hipMemcpyHostToDevice);
+      for (int q = 0; q < dim && e == hipSuccess; ++q)
+        e = hipMemcpy(s->c[q] + off, cc.data() + (size_t)q * N, N * sizeof(double),
+                      hipMemcpyHostToDevice);
+      if (e != hipSuccess) return bail(NS_EHIP, "graph upload failed");
+    }
+    std::vector<double> mi(N), bnd((size_t)dim * N), rmi(N), lfac(N), rrel(N);
+    std::vector<uint8_t> wall(N);
+    s->mg.fill_nodes(mi.data(), bnd.data(), wall.data());
+    double vol = 0.0;
+    for (int64_t i = 0; i < N; ++i) vol += mi[i];
+    std::vector<int32_t> sidx;
+    std::vector<double> snrm;
+    for (int64_t i = 0; i < N; ++i) {
+      rmi[i] = 1.0 / mi[i];
+      lfac[i] = (double)(cnt[i] - 1);
+      rrel[i] = p->relax * std::pow(mi[i] / vol, 1.5 / dim);
+      if (wall[i]) sidx.push_back((int32_t)i);
+    }
+    s->nslip = (int)sidx.size();
+    snrm.resize((size_t)dim * s->nslip);
+    for (int t = 0; t < s->nslip; ++t) {
+      const int64_t i = sidx[t];
+      double nn = 0.0, v[3];
+      for (int q = 0; q < dim; ++q) { v[q] = bnd[(size_t)q * N + i]; nn += v[q] * v[q]; }
+      nn = std::sqrt(nn);
+      for (int q = 0; q < dim; ++q) snrm[(size_t)q * s->nslip + t] = v[q] / nn;
+    }
+    NS_ALLOC(s->slip_idx, s->nslip);
+    NS_ALLOC(s->slip_n, dim * s->nslip);
+    struct { void *dst; const void *src; size_t n; } ups[] = {
+        {s->mi, mi.data(), N * sizeof(double)},
+        {s->rmi, rmi.data(), N * sizeof(double)},
+        {s->lfac, lfac.data(), N * sizeof(double)},
+        {s->rrel, rrel.data(), N * sizeof(double)},
+        {s->wall, wall.data(), (size_t)N},
+        {s->slip_idx, sidx.data(), sidx.size() * sizeof(int32_t)},
+        {s->slip_n, snrm.data(), snrm.size() * sizeof(double)}};
+    for (auto &u : ups) {
+      if (u.n == 0) continue;
+      e = hipMemcpy(u.dst, u.src, u.n, hipMemcpyHostToDevice);
+      if (e != hipSuccess) return bail(NS_EHIP, "graph upload failed");
+    }
+  }
+  // zero the scratch edge arrays once: entries never written stay zero
+  for (double *z : {s->d, s->lt1, s->lt2}) {
+    e = hipMemset(z, 0, (size_t)W * N * sizeof(double));
+    if (e != hipSuccess) return bail(NS_EHIP, "memset failed");
+  }
+  e = hipHostMalloc(reinterpret_cast<void **>(&s->hflags), 4 * sizeof(int));
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void **>(&s->htau), sizeof(double));
+  if (e != hipSuccess) return bail(NS_ENOMEM, "pinned host allocation failed");
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) return bail(NS_EHIP, hipGetErrorString(e));
+#undef NS_ALLOC
+  *out = s;
+  return NS_OK;
+}
+
+void ns_solver_destroy(ns_solver *s) {
+  release(s);
+  delete s;
+}
+
+int ns_set_state(ns_solver *s, const double *U, int flags) {
+  if (!s || !U) return NS_EINVAL;
+  const int tgt = others(s->cur, 0);
+  const size_t bytes = (size_t)s->nc * s->N * sizeof(double);
+  hipError_t e = hipMemcpyAsync(s->S[tgt], U, bytes,
+                                (flags & NS_ON_DEVICE) ? hipMemcpyDeviceToDevice
+                                                       : hipMemcpyHostToDevice,
+                                s->stream);
+  if (e != hipSuccess) return s->hipfail(e, "state upload");
+  ns::launch_clear_flags(s->flags, s->stream);
+  ns::launch_check_state(s->dim, s->N, s->S[tgt], s->flags, s->stream);
+  int rc = read_flags(s);
+  if (rc != NS_OK) return rc;
+  if (s->hflags[1]) {
+    char buf[128];
+    snprintf(buf, sizeof buf, "state not admissible at node %d", s->hflags[2]);
+    return s->fail(NS_ENOTADMISSIBLE, buf);
+  }
+  if (!(flags & NS_NO_PROJECT)) {
+    ns::launch_slip(s->dim, s->N, s->nslip, s->slip_idx, s->slip_n, s->S[tgt],
+                    s->stream);
+    e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return s->hipfail(e, "slip projection");
+  }
+  s->cur = tgt;
+  s->has_state = true;
+  return NS_OK;
+}
+
+int ns_get_state(ns_solver *s, double *U, int flags) {
+  if (!s || !U) return NS_EINVAL;
+  if (!s->has_state) return s->fail(NS_ESTATE, "no state set");
+  const size_t bytes = (size_t)s->nc * s->N * sizeof(double);
+  hipError_t e = hipMemcpyAsync(U, s->S[s->cur], bytes,
+                                (flags & NS_ON_DEVICE) ? hipMemcpyDeviceToDevice
+                                                       : hipMemcpyDeviceToHost,
+                                s->stream);
+  if (e != hipSuccess) return s->hipfail(e, "state download");
+  e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return s->hipfail(e, "stream synchronize");
+  return NS_OK;
+}
+
+int ns_compute_dt(ns_solver *s, double *dt) {
+  if (!s || !dt) return NS_EINVAL;
+  if (!s->has_state) return s->fail(NS_ESTATE, "no state set");
+  // prim + graph viscosity + reduction, without the rest of the stage
+  const ns::DevGraph g = s->devgraph();
+  ns::StageArgs a = s->args(s->cur, others(s->cur, 0), 0.0, 1.0, 0);
+  ns::launch_clear_flags(s->flags, s->stream);
+  ns::launch_dt_only(s->dim, s->gas, g, a, s->prm.cfl, s->stream,
+                     &Profiler::before, &Profiler::after, &s->prof);
+  int rc = read_flags(s);
+  if (rc != NS_OK) return rc;
+  *dt = *s->htau;
+  return NS_OK;
+}
+
+int ns_step(ns_solver *s, double dt) {
+  if (!s) return NS_EINVAL;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return s->fail(NS_EINVAL, "dt must be positive");
+  return ssprk3(s, dt, false, nullptr);
+}
+
+int ns_step_cfl(ns_solver *s, double *dt) {
+  if (!s) return NS_EINVAL;
+  return ssprk3(s, 0.0, true, dt);
+}
+
+int ns_fe_stage(ns_solver *s, double dt) {
+  if (!s) return NS_EINVAL;
+  if (!s->has_state) return s->fail(NS_ESTATE, "no state set");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return s->fail(NS_EINVAL, "dt must be positive");
+  const int o1 = others(s->cur, 0);
+  ns::launch_clear_flags(s->flags, s->stream);
+  ns::launch_set_scalar(s->tau, dt, s->stream);
+  run_stage(s, s->cur, o1, 0.0, 1.0, 1, false);
+  s->last_out = o1;
+  int rc = read_flags(s);
+  if (rc != NS_OK) return rc;
+  if (s->hflags[0]) return s->fail(NS_ECFL, "dt exceeds the stage CFL limit");
+  if (s->hflags[1]) return s->fail(NS_EBOUNDS, "the stage produced an inadmissible state");
+  return NS_OK;
+}
+
+int ns_get_debug(ns_solver *s, int what, double *out) {
+  if (!s || !out) return NS_EINVAL;
+  const int64_t N = s->N, W = s->W, nc = s->nc;
+  const double *src = nullptr;
+  int64_t count = 0;
+  switch (what) {
+    case NS_DBG_STAGE_OUT: src = s->S[s->last_out]; count = nc * N; break;
+    case NS_DBG_D: src = s->d; count = W * N; break;
+    case NS_DBG_ALPHA: src = s->alpha; count = N; break;
+    case NS_DBG_UL: src = s->UL; count = nc * N; break;
+    case NS_DBG_FH: src = s->FH; count = nc * N; break;
+    case NS_DBG_BOUNDS: src = s->bnds; count = 3 * N; break;
+    case NS_DBG_LT1: src = s->lt1; count = W * N; break;
+    case NS_DBG_LT2: src = s->lt2; count = W * N; break;
+    case NS_DBG_U1: src = s->U1; count = nc * N; break;
+    default: return s->fail(NS_EINVAL, "unknown debug array");
+  }
+  hipError_t e = hipMemcpyAsync(out, src, count * sizeof(double),
+                                hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return s->hipfail(e, "debug download");
+  return NS_OK;
+}
+
+int ns_sync(ns_solver *s) {
+  if (!s) return NS_EINVAL;
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return s->hipfail(e, "stream synchronize");
+  return NS_OK;
+}
+
+void *ns_stream(ns_solver *s) { return s ? (void *)s->stream : nullptr; }
+
+int ns_profile_enable(ns_solver *s, int on) {
+  if (!s) return NS_EINVAL;
+  s->prof.reset();
+  s->prof.on = on != 0;
+  return NS_OK;
+}
+
+int ns_profile_count(ns_solver *s) {
+  if (!s) return 0;
+  return (int)s->prof.names.size();
+}
+
+int ns_profile_get(ns_solver *s, int k, const char **name, int64_t *launches,
+                   double *total_ms) {
+  if (!s) return NS_EINVAL;
+  s->prof.flush();
+  if (k < 0 || k >= (int)s->prof.names.size()) return NS_EINVAL;
+  if (name) *name = s->prof.names[k].c_str();
+  if (launches) *launches = s->prof.launches[k];
+  if (total_ms) *total_ms = s->prof.total_ms[k];
+  return NS_OK;
+}
+
+int64_t ns_device_bytes(const ns_solver *s) { return s ? s->bytes : 0; }
+
+const char *ns_last_error(const ns_solver *s) {
+  return s ? s->err.c_str() : "null solver";
+}
+
+}  // extern "C"

@@ -1,0 +1,104 @@
+"""Host-only checks of libns: the library loads and exports every symbol that
+include/ns.h declares; the closed-form graph (host code, no GPU) matches the
+oracle's quadrature-assembled graph; invalid arguments are rejected before any
+device work."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2106_02159_amd import abi, workloads as W
+from tests.helpers import ell_to_csr_index
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "ns.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ns_[a-z_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol():
+    L = abi.lib()
+    decl = declared_symbols()
+    assert len(decl) >= 20
+    for name in decl:
+        assert hasattr(L, name), name
+    assert sorted(abi.EXPORTED) == decl
+
+
+MESHES = [
+    W.Mesh(2, (7, 6), (0.0, 0.0), (1.2, 1.0), (False, False)),
+    W.Mesh(2, (5, 4), (0.0, -1.0), (1.0, 1.0), (True, False)),
+    W.Mesh(2, (6, 6), (-5.0, -5.0), (5.0, 5.0), (True, True)),
+    W.Mesh(2, (2, 2), (0.0, 0.0), (1.0, 1.0), (False, False)),
+    W.Mesh(3, (5, 4, 6), (0.0, 0.0, 0.0), (1.0, 1.0, 1.25), (False, True, False)),
+    W.Mesh(3, (3, 3, 3), (0.0,) * 3, (1.0,) * 3, (True, True, True)),
+    W.Mesh(3, (4, 2, 3), (0.0,) * 3, (1.0, 0.5, 2.0), (False, False, False)),
+]
+
+
+@pytest.mark.parametrize("mesh", MESHES, ids=lambda m: f"{m.dim}d{m.n}{m.periodic}")
+def test_graph_matches_oracle(mesh):
+    g = abi.Graph(mesh)
+    o = O.Graph(mesh.dim, mesh.n, mesh.lo, mesh.hi, mesh.periodic)
+    assert g.N == o.N and g.nnz == o.nnz
+    ex = g.export()
+    mask, idx = ell_to_csr_index(ex["col"], o.row_ptr, o.col)
+    assert mask.sum() == o.nnz
+    scale_c = np.abs(o.cij).max()
+    for k in range(mesh.dim):
+        assert np.abs(ex["cij"][k][mask] - o.cij[k][idx]).max() <= 1e-14 * scale_c
+    assert np.abs(ex["mij"][mask] - o.mij[idx]).max() <= 1e-14 * o.mij.max()
+    assert np.all(ex["mij"][~mask] == 0) and np.all(ex["cij"][:, ~mask] == 0)
+    assert np.allclose(ex["mi"], o.mi, rtol=1e-14, atol=0)
+    assert np.abs(ex["bnd"] - o.bnd).max() <= 1e-14 * max(np.abs(o.bnd).max(), 1e-300)
+
+
+def test_graph_exact_antisymmetry():
+    """The closed form gives c_ij = -c_ji bit for bit unless both nodes are on
+    the wall (where c_ij + c_ji = int phi_i phi_j n)."""
+    mesh = W.Mesh(2, (9, 7), (0.0, 0.0), (1.0, 0.75), (False, False))
+    g = abi.Graph(mesh)
+    ex = g.export()
+    col = ex["col"]
+    Wd, N = col.shape
+    o = O.Graph(2, mesh.n, mesh.lo, mesh.hi, mesh.periodic)
+    for k in range(Wd):
+        kt = Wd - 1 - k
+        for i in range(N):
+            j = col[k, i]
+            if j < 0 or o.on_wall[i] and o.on_wall[j]:
+                continue
+            assert col[kt, j] == i
+            assert np.array_equal(ex["cij"][:, k, i], -ex["cij"][:, kt, j])
+
+
+def test_invalid_graphs_rejected():
+    bad = [W.Mesh(1, (5,), (0,), (1,), (False,)),
+           W.Mesh(2, (2, 5), (0, 0), (1, 1), (True, False)),
+           W.Mesh(2, (1, 5), (0, 0), (1, 1), (False, False)),
+           W.Mesh(2, (4, 4), (0, 0), (0, 1), (False, False))]
+    for m in bad:
+        with pytest.raises(abi.NSError) as ei:
+            abi.Graph(m)
+        assert ei.value.code == abi.NS_EINVAL
+
+
+@pytest.mark.parametrize("kw", [dict(gamma=1.0), dict(gamma=1.8), dict(cfl=0.0),
+                                dict(cfl=1.5), dict(passes=3), dict(indicator=5),
+                                dict(limiter=-1), dict(relax=-1.0)])
+def test_invalid_params_rejected_before_device_work(kw):
+    g = abi.Graph(W.four_quadrant_mesh(8))
+    with pytest.raises(abi.NSError) as ei:
+        abi.Solver(g, **kw)
+    assert ei.value.code == abi.NS_EINVAL
+
+
+def test_strerror():
+    L = abi.lib()
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
+        assert L.ns_strerror(code)

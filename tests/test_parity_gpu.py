@@ -1,0 +1,240 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, element
+by element on the same seeded inputs and the same time step (the oracle's).
+
+Bars: time step 1e-14 relative; stage and step states 1e-12 relative
+(max-norm per component, momentum components sharing one scale);
+intermediates as stated per test.  Sizes span several 256-row blocks and a
+ragged tail; edge cases cover the smallest meshes the ABI accepts."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2106_02159_amd import abi, workloads as W
+from tests.helpers import ell_to_csr_index, rel_err, state_rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL_STATE = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rough(mesh, seed):
+    return mesh, W.random_rough_state(mesh, seed=seed)
+
+
+CASES = {
+    "vortex32": lambda: W.vortex_state(32),
+    "quad67": lambda: W.four_quadrant_state(67, seed=1),
+    "rough2d_37x29": lambda: rough(W.Mesh(2, (37, 29), (0, 0), (1.0, 0.8), (False, False)), 3),
+    "rough2d_per_x": lambda: rough(W.Mesh(2, (23, 17), (0, 0), (1.0, 1.0), (True, False)), 4),
+    "tube3d_12": lambda: W.shock_tube_state(12, seed=0),
+    "rough3d_7x5x6": lambda: rough(W.Mesh(3, (7, 5, 6), (0,) * 3, (1.0, 0.7, 0.9),
+                                         (False, True, False)), 5),
+    "tiny2d_2x2": lambda: rough(W.Mesh(2, (2, 2), (0, 0), (1, 1), (False, False)), 6),
+    "tiny2d_3x3per": lambda: rough(W.Mesh(2, (3, 3), (0, 0), (1, 1), (True, True)), 7),
+    "tiny3d_2x2x2": lambda: rough(W.Mesh(3, (2, 2, 2), (0,) * 3, (1,) * 3, (False,) * 3), 8),
+    "tiny3d_3x3x3per": lambda: rough(W.Mesh(3, (3, 3, 3), (0,) * 3, (1,) * 3, (True,) * 3), 9),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    mesh, U = CASES[request.param]()
+    og = O.Graph(mesh.dim, mesh.n, mesh.lo, mesh.hi, mesh.periodic)
+    U = og.slip_bc(U)
+    return request.param, mesh, og, abi.Graph(mesh), U
+
+
+def test_compute_dt(case):
+    name, mesh, og, g, U = case
+    say("compute_dt", name)
+    for cfl in (0.5, 1.0):
+        s = abi.Solver(g, cfl=cfl)
+        s.set_state(U, project=False)
+        t_gpu = s.compute_dt()
+        t_orc = og.compute_dt(O.params(cfl=cfl), U)
+        assert t_gpu == pytest.approx(t_orc, rel=1e-14, abs=0)
+
+
+MODES = {
+    "convex2": dict(),
+    "convex1": dict(passes=1),
+    "ind_one": dict(indicator=abi.IND_ONE),
+    "ind_zero": dict(indicator=abi.IND_ZERO),
+    "low": dict(limiter=abi.LIM_LOW),
+    "high": dict(limiter=abi.LIM_HIGH),
+    "relax3": dict(relax=3.0),
+}
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+def test_stage(case, mode):
+    """One forward-Euler stage and its intermediates."""
+    name, mesh, og, g, U = case
+    say("stage", name, mode)
+    kw = MODES[mode]
+    prm = O.params(cfl=0.9, **kw)
+    tau = og.compute_dt(prm, U)
+    ref, st, dbg = og.fe_stage(prm, U, tau, debug=True)
+    s = abi.Solver(g, cfl=0.9, **kw)
+    s.set_state(U, project=False)
+    rc = s.fe_stage(tau)
+    assert rc == abi.NS_OK, abi.lib().ns_last_error(s.h)
+    out = s.debug("stage_out")
+    err = state_rel_err(out, ref)
+    assert np.all(err <= TOL_STATE), (name, mode, err)
+    ex = g.export()
+    mask, idx = ell_to_csr_index(ex["col"], og.row_ptr, og.col)
+    rows = np.broadcast_to(np.arange(og.N), mask.shape)[mask]
+    off = og.col[idx] != rows
+    d = s.debug("d")[mask]
+    assert rel_err(d[off], dbg["d"][idx][off]) <= 1e-13
+    assert np.abs(s.debug("alpha") - dbg["alpha"]).max() <= 1e-10
+    assert np.all(state_rel_err(s.debug("UL"), dbg["UL"]) <= 1e-13)
+    assert np.all(state_rel_err(s.debug("FH"), dbg["FH"]) <= 1e-12)
+    r = kw.get("relax", 1.0) * (og.mi / og.mi.sum()) ** (1.5 / og.dim)
+    bref = dbg["bounds"] * np.array([1 - r, 1 + r, 1 - r])
+    assert np.all(rel_err(s.debug("bounds"), bref, axis=1) <= 1e-13)
+    if kw.get("limiter", abi.LIM_CONVEX) == abi.LIM_CONVEX:
+        lt1 = s.debug("lt1")[mask]
+        assert np.abs(lt1[off] - dbg["lt1"][idx][off]).max() <= 1e-10
+        if kw.get("passes", 2) == 2:
+            lt2 = s.debug("lt2")[mask]
+            assert np.abs(lt2[off] - dbg["lt2"][idx][off]).max() <= 1e-10
+            assert np.all(state_rel_err(s.debug("U1"), dbg["U1"]) <= TOL_STATE)
+
+
+def test_step(case):
+    """Two SSPRK(3,3) steps, each from the same state on both sides."""
+    name, mesh, og, g, U = case
+    prm = O.params(cfl=0.9)
+    s = abi.Solver(g, cfl=0.9)
+    s.set_state(U)
+    cur = s.get_state()
+    assert np.array_equal(cur, U)  # already slip-projected
+    for k in range(2):
+        say("step", name, k)
+        tau = og.compute_dt(prm, cur)
+        ref, st = og.ssprk3_step(prm, cur, tau)
+        assert st == 0
+        s.set_state(cur, project=False)
+        s.step(tau)
+        cur = s.get_state()
+        err = state_rel_err(cur, ref)
+        assert np.all(err <= TOL_STATE), (name, k, err)
+
+
+def test_vortex_every_step():
+    """Isentropic vortex on the periodic 64x64 mesh, 100 steps at CFL 0.5:
+    every step compared, each from the state the GPU reached."""
+    mesh, U = W.vortex_state(64)
+    og = O.Graph(2, mesh.n, mesh.lo, mesh.hi, mesh.periodic)
+    prm = O.params(cfl=0.5)
+    s = abi.Solver(abi.Graph(mesh), cfl=0.5)
+    s.set_state(U)
+    worst = 0.0
+    for k in range(100):
+        cur = s.get_state()
+        tau = og.compute_dt(prm, cur)
+        ref, st = og.ssprk3_step(prm, cur, tau)
+        s.step(tau)
+        err = state_rel_err(s.get_state(), ref).max()
+        worst = max(worst, err)
+        assert err <= TOL_STATE, (k, err)
+    say("vortex64 100 steps, worst per-step relative error", worst)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_four_quadrant_steps(seed):
+    """Four-quadrant Riemann data on 256x256 with walls: steps 1, 2 and 20
+    (each from the GPU's own state), plus conservation of mass and energy."""
+    mesh, U = W.four_quadrant_state(256, seed=seed)
+    og = O.Graph(2, mesh.n, mesh.lo, mesh.hi, mesh.periodic)
+    prm = O.params(cfl=0.5)
+    s = abi.Solver(abi.Graph(mesh), cfl=0.5)
+    s.set_state(U)
+    U0 = s.get_state()
+    for k in range(20):
+        cur = s.get_state()
+        if k in (0, 1, 19):
+            say("quad256 seed", seed, "step", k + 1)
+            tau = og.compute_dt(prm, cur)
+            ref, st = og.ssprk3_step(prm, cur, tau)
+            s.step(tau)
+            err = state_rel_err(s.get_state(), ref)
+            assert np.all(err <= TOL_STATE), (seed, k, err)
+        else:
+            s.step_cfl()
+    out = s.get_state()
+    for c in (0, 3):
+        a, b = (og.mi * U0[c]).sum(), (og.mi * out[c]).sum()
+        assert abs(a - b) <= 1e-13 * abs(a)
+
+
+def test_step_cfl_matches_compute_dt_then_step():
+    mesh, U = W.four_quadrant_state(130, seed=3)
+    g = abi.Graph(mesh)
+    a = abi.Solver(g, cfl=0.7)
+    b = abi.Solver(g, cfl=0.7)
+    a.set_state(U)
+    b.set_state(U)
+    for _ in range(3):
+        dt_b = b.compute_dt()
+        dt_a = a.step_cfl()
+        b.step(dt_b)
+        assert dt_a == dt_b
+        assert np.array_equal(a.get_state(), b.get_state())
+
+
+def test_deterministic_and_restartable():
+    mesh, U = W.shock_tube_state(20, seed=4)
+    g = abi.Graph(mesh)
+    a = abi.Solver(g, cfl=0.8)
+    a.set_state(U)
+    for _ in range(4):
+        a.step_cfl()
+    b = abi.Solver(g, cfl=0.8)
+    b.set_state(U)
+    for _ in range(2):
+        b.step_cfl()
+    ck = b.get_state()
+    c = abi.Solver(g, cfl=0.8)
+    c.set_state(ck, project=False)
+    for _ in range(2):
+        c.step_cfl()
+    assert np.array_equal(a.get_state(), c.get_state())
+
+
+def test_cfl_violation_is_transactional():
+    mesh, U = W.four_quadrant_state(40, seed=5)
+    s = abi.Solver(abi.Graph(mesh), cfl=0.5)
+    s.set_state(U)
+    before = s.get_state()
+    limit = s.compute_dt() / 0.5
+    rc = s.step_status(limit * 1.5)
+    assert rc == abi.NS_ECFL
+    assert np.array_equal(s.get_state(), before)
+    s.step(limit * 0.5)  # restart with a smaller step succeeds
+    assert not np.array_equal(s.get_state(), before)
+
+
+def test_set_state_rejects_inadmissible():
+    mesh, U = W.four_quadrant_state(20, seed=6)
+    s = abi.Solver(abi.Graph(mesh))
+    s.set_state(U)
+    good = s.get_state()
+    for bad_fn in (lambda V: V.__setitem__((0, 17), -1.0),
+                   lambda V: V.__setitem__((3, 5), 0.0),
+                   lambda V: V.__setitem__((1, 9), np.nan)):
+        V = U.copy()
+        bad_fn(V)
+        with pytest.raises(abi.NSError) as ei:
+            s.set_state(V)
+        assert ei.value.code == abi.NS_ENOTADMISSIBLE
+        assert np.array_equal(s.get_state(), good)
+    with pytest.raises(abi.NSError) as ei:
+        abi.Solver(abi.Graph(mesh)).step(1e-3)
+    assert ei.value.code == abi.NS_ESTATE
