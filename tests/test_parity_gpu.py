@@ -114,7 +114,8 @@ def test_step(case):
     s = abi.Solver(g, cfl=0.9)
     s.set_state(U)
     cur = s.get_state()
-    assert np.array_equal(cur, U)  # already slip-projected
+    # U is already slip-projected: projecting again only touches round-off
+    assert np.abs(cur - U).max() <= 1e-15 * np.abs(U).max()
     for k in range(2):
         say("step", name, k)
         tau = og.compute_dt(prm, cur)
