@@ -64,6 +64,33 @@ def stage_algorithmic_bytes(dim: int) -> float:
     return 4 * Wd + 8 * dim * Wd + 8 * Wd + 8 + 2 * 8 * nc + 8 * nc * 2 / 3
 
 
+def source_sha() -> str:
+    """sha256 (first 16 hex) of the kernel sources: csrc/*.hip, *.hpp, *.cpp."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2106_02159_amd", "csrc")
+    for ext in ("hip", "hpp", "cpp"):
+        for p in sorted(glob.glob(os.path.join(csrc, f"*.{ext}"))):
+            h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None if the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "hyp_stage_2d_4096_hbm_traffic.md")
+    try:
+        txt = open(path).read()
+        data = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if data.get("source_sha") != source_sha():
+        return None
+    k = data.get("kernels", {}).get(kernel)
+    return k["traffic_bytes"] if k else None
+
+
 def cpu_baseline(n_sample: int, seed: int):
     """The oracle, as it stands, on one SSPRK(3,3) step of the same workload
     at n_sample x n_sample nodes (graph assembly not timed)."""
@@ -119,6 +146,11 @@ def main():
     elapsed = time.perf_counter() - t0
     rep = solver.profile_report()
     solver.profile(False)
+    # plain device copy of 1 GiB: the achievable streaming bandwidth, and a
+    # kernel of known traffic for calibrating hardware byte counters
+    copy_bytes = 1 << 30
+    copy_ms = solver.copy_bench(copy_bytes, reps=5)
+    copy_gbs = 2 * copy_bytes / (copy_ms * 1e-3) / 1e9
 
     N = graph.N
     stages = 3 * args.steps
@@ -155,8 +187,10 @@ def main():
                    "nodes": N, "stages_per_step": 3},
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None},
+                     "traffic": measured_traffic(dname) if n == 4096 else None,
+                     "algorithmic_bytes": kb},
         "stage_algorithmic_frac": stage_frac,
+        "copy_GBs": copy_gbs,
         "kernels": kern,
         "setup_s": setup_s,
         "device_bytes": solver.device_bytes(),

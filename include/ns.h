@@ -184,6 +184,13 @@ int ns_profile_count(ns_solver *s);
  * duration in milliseconds.  Synchronises.  NS_EINVAL if k is out of range. */
 int ns_profile_get(ns_solver *s, int k, const char **name, int64_t *launches,
                    double *total_ms);
+/* Measurement utility: copies `bytes` (rounded down to a multiple of 16)
+ * between two scratch device buffers with a plain streaming copy kernel,
+ * `reps` times on the solver's stream, and returns the average kernel time
+ * in *avg_ms.  Used to state the achievable device copy bandwidth and to
+ * calibrate hardware byte counters against a kernel of known traffic.
+ * Allocates (and frees) the two buffers; NS_ENOMEM if they do not fit. */
+int ns_copy_bench(ns_solver *s, int64_t bytes, int reps, double *avg_ms);
 /* Device bytes allocated by the solver. */
 int64_t ns_device_bytes(const ns_solver *s);
 /* Message describing the last error of the solver (never NULL). */

@@ -29,7 +29,8 @@ EXPORTED = [
     "ns_solver_create", "ns_solver_destroy", "ns_set_state", "ns_get_state",
     "ns_compute_dt", "ns_step", "ns_step_cfl", "ns_fe_stage", "ns_get_debug",
     "ns_sync", "ns_stream", "ns_profile_enable", "ns_profile_count",
-    "ns_profile_get", "ns_device_bytes", "ns_last_error", "ns_create_error",
+    "ns_profile_get", "ns_copy_bench", "ns_device_bytes", "ns_last_error",
+    "ns_create_error",
     "ns_strerror",
 ]
 
@@ -83,6 +84,7 @@ def lib() -> C.CDLL:
             "ns_profile_enable": (C.c_int, [vp, C.c_int]),
             "ns_profile_count": (C.c_int, [vp]),
             "ns_profile_get": (C.c_int, [vp, C.c_int, C.POINTER(C.c_char_p), i64p, dp]),
+            "ns_copy_bench": (C.c_int, [vp, C.c_int64, C.c_int, dp]),
             "ns_device_bytes": (C.c_int64, [vp]),
             "ns_last_error": (C.c_char_p, [vp]),
             "ns_create_error": (C.c_char_p, []),
@@ -233,6 +235,12 @@ class Solver:
                                          C.byref(ms)))
             out[name.value.decode()] = (n.value, ms.value)
         return out
+
+    def copy_bench(self, nbytes: int, reps: int = 10) -> float:
+        """Average time (ms) of a plain device copy of nbytes."""
+        ms = C.c_double()
+        self._check(lib().ns_copy_bench(self.h, int(nbytes), int(reps), C.byref(ms)))
+        return ms.value
 
     def device_bytes(self) -> int:
         return lib().ns_device_bytes(self.h)

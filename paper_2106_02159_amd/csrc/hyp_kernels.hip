@@ -494,6 +494,13 @@ __global__ __launch_bounds__(kBlock) void k_slip(int nslip,
   for (int k = 0; k < DIM; ++k) U[(1 + k) * N + i] -= mn * n[k];
 }
 
+__global__ __launch_bounds__(kBlock) void k_copy(const double2 *__restrict__ src,
+                                                 double2 *__restrict__ dst,
+                                                 int64_t n16) {
+  const int64_t t = row_id();
+  if (t < n16) dst[t] = src[t];
+}
+
 __global__ void k_set_scalar(double *p, double v) {
   if (threadIdx.x == 0) p[0] = v;
 }
@@ -635,6 +642,12 @@ void launch_slip(int dim, int64_t N, int nslip, const int32_t *idx,
 
 void launch_set_scalar(double *p, double v, hipStream_t s) {
   hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(64), 0, s, p, v);
+}
+
+void launch_copy(const void *src, void *dst, int64_t n16, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy, grid_for(n16), dim3(kBlock), 0, s,
+                     static_cast<const double2 *>(src), static_cast<double2 *>(dst),
+                     n16);
 }
 
 void launch_clear_flags(int *flags, hipStream_t s) {

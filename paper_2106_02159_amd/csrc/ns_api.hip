@@ -599,6 +599,41 @@ int ns_profile_get(ns_solver *s, int k, const char **name, int64_t *launches,
   return NS_OK;
 }
 
+int ns_copy_bench(ns_solver *s, int64_t bytes, int reps, double *avg_ms) {
+  if (!s || !avg_ms || bytes < 16 || reps < 1) return NS_EINVAL;
+  const int64_t n16 = bytes / 16;
+  void *a = nullptr, *b = nullptr;
+  hipError_t e = hipMalloc(&a, n16 * 16);
+  if (e == hipSuccess) e = hipMalloc(&b, n16 * 16);
+  if (e != hipSuccess) {
+    if (a) (void)hipFree(a);
+    (void)hipGetLastError();
+    return s->fail(NS_ENOMEM, "copy buffers do not fit");
+  }
+  hipEvent_t t0, t1;
+  (void)hipEventCreate(&t0);
+  (void)hipEventCreate(&t1);
+  e = hipMemsetAsync(a, 0, n16 * 16, s->stream);
+  ns::launch_copy(a, b, n16, s->stream);  // warm-up
+  (void)hipEventRecord(t0, s->stream);
+  for (int r = 0; r < reps; ++r) {
+    Profiler::before(&s->prof, "copy");
+    ns::launch_copy(r % 2 ? b : a, r % 2 ? a : b, n16, s->stream);
+    Profiler::after(&s->prof);
+  }
+  (void)hipEventRecord(t1, s->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(t1);
+  float ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  (void)hipFree(a);
+  (void)hipFree(b);
+  if (e != hipSuccess) return s->hipfail(e, "copy benchmark");
+  *avg_ms = ms / reps;
+  return NS_OK;
+}
+
 int64_t ns_device_bytes(const ns_solver *s) { return s ? s->bytes : 0; }
 
 const char *ns_last_error(const ns_solver *s) {
