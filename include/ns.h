@@ -112,8 +112,10 @@ typedef struct ns_solver ns_solver;
 /* Creates a solver on the current HIP device.  `stream` is a hipStream_t to
  * order all work on, or NULL for a stream the solver creates and owns.  All
  * device memory (graph arrays, three state buffers, per-edge d_ij and
- * limiter arrays, per-node scratch) is allocated here.
- * Errors: NS_EINVAL for bad parameters; NS_ENOMEM if the device footprint
+ * limiter arrays, per-node scratch, the limiter's root work lists) is
+ * allocated here.
+ * Errors: NS_EINVAL for bad parameters or a mesh whose edge count (width x
+ * N rounded up to 64) exceeds 2^32 - 1; NS_ENOMEM if the device footprint
  * does not fit; NS_EHIP. */
 int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
                      ns_solver **out);
@@ -162,7 +164,7 @@ enum {
   NS_DBG_D = 1,         /* W*N    d^L_ij (off-diagonal entries)           */
   NS_DBG_ALPHA = 2,     /* N      alpha_i                                 */
   NS_DBG_UL = 3,        /* nc*N   low-order update U^L                    */
-  NS_DBG_FH = 4,        /* nc*N   high-order flux F^H_i                   */
+  NS_DBG_FH = 4,        /* nc*N   high-order flux F^H_i divided by m_i    */
   NS_DBG_BOUNDS = 5,    /* 3*N    relaxed rho_min, rho_max, Phi_min       */
   NS_DBG_LT1 = 6,       /* W*N    pass-1 limiter before symmetrisation    */
   NS_DBG_LT2 = 7,       /* W*N    pass-2 limiter before symmetrisation    */

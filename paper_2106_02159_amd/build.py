@@ -34,14 +34,16 @@ def _run(cmd):
     return out
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, extra=()) -> str:
+    """Compile every source and link libns.so; `extra` adds compiler flags
+    (e.g. -D settings of the kernels' chunk sizes)."""
     objs = []
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     for src in SOURCES:
         obj = os.path.join(bdir, src + ".o")
-        cmd = [HIPCC] + COMMON + DEVICE_FLAGS + ["-c", os.path.join(CSRC, src),
-                                                 "-o", obj]
+        cmd = [HIPCC] + COMMON + list(extra) + DEVICE_FLAGS + [
+            "-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
             cmd = [HIPCC] + COMMON + ["-x", "c++", "-c", os.path.join(CSRC, src),
                                       "-o", obj]

@@ -1,5 +1,5 @@
 // euler.hpp -- device-side pieces of the hyperbolic step: the maximum wave
-// speed bound and the limiter line search (Sec. 3.1 and 3.3).
+// speed bound and the pieces of the limiter line search (Sec. 3.1, 3.3).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -67,37 +67,56 @@ __device__ __forceinline__ double psi_eval(const Gas &g, const double *u,
   return eps - phi_min * rg;
 }
 
-// Largest l in [0,1] keeping rho in [rho_min, rho_max] and Phi >= phi_min.
-// Density is affine in l.  psi is concave in l, so from a feasible end a
-// (psi >= 0) and an infeasible end b (psi < 0) the chord's root stays
-// feasible and the tangent's root at b stays infeasible: both ends move
-// towards the root at once.  Every candidate is checked by evaluating psi,
-// so the returned end is feasible even under round-off.  Stops when the
-// bracket is below 1e-14 (l is dimensionless, in [0,1]).
+// Is u + l P inside the entropy bound Phi >= phi_min?  For gamma = 7/5 the
+// test eps >= phi_min rho^(7/5) is taken division- and pow-free as
+// (rho eps)^5 >= phi_min^5 rho^12 with rho eps = rho E - |m|^2/2 (both sides
+// are non-negative exactly when eps >= 0); pmin5 = phi_min^5.
 template <int DIM>
-__device__ double line_search(const Gas &g, const double *u, const double *P,
-                              double rho_min, double rho_max, double phi_min) {
-  double lr;
-  if (P[0] > 0.0) lr = (rho_max - u[0]) / P[0];
-  else if (P[0] < 0.0) lr = (rho_min - u[0]) / P[0];
-  else lr = 1.0;
-  lr = fmin(fmax(lr, 0.0), 1.0);
-  double db;
-  const double pb = psi_eval<DIM>(g, u, P, lr, phi_min, &db);
-  if (pb >= 0.0) return lr;
-  const double pa0 = psi_eval<DIM>(g, u, P, 0.0, phi_min, nullptr);
-  if (pa0 < 0.0) return 0.0;
-  double a = 0.0, b = lr, fa = pa0, fb = pb, dfb = db;
+__device__ __forceinline__ bool entropy_ok(const Gas &g, const double *u,
+                                           const double *P, double l,
+                                           double phi_min, double pmin5) {
+  const double r = u[0] + l * P[0];
+  double m2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    const double mk = u[1 + k] + l * P[1 + k];
+    m2 += mk * mk;
+  }
+  const double E = u[DIM + 1] + l * P[DIM + 1];
+  if (g.seven) {
+    const double A = r * E - 0.5 * m2;
+    if (!(A > 0.0)) return false;
+    const double A2 = A * A;
+    const double r2 = r * r, r4 = r2 * r2, r8 = r4 * r4;
+    return A2 * A2 * A >= pmin5 * (r8 * r4);
+  }
+  return E - 0.5 * m2 / r - phi_min * pow(r, g.gamma) >= 0.0;
+}
+
+// Root of psi in (a, b) with psi(a) >= 0 > psi(b).  psi is concave in l, so
+// from the feasible end a the chord's root stays feasible and from the
+// infeasible end b the tangent's root stays infeasible: both ends move towards
+// the root at once.  Every candidate is checked by evaluating psi, so the
+// returned end is feasible even under round-off.  Stops when the bracket is
+// below 1e-14 (l is dimensionless, in [0,1]).
+template <int DIM>
+__device__ __forceinline__ double entropy_root(const Gas &g, const double *u,
+                                            const double *P, double b,
+                                            double phi_min) {
+  double a = 0.0;
+  double fa = psi_eval<DIM>(g, u, P, 0.0, phi_min, nullptr);
+  double dfb;
+  double fb = psi_eval<DIM>(g, u, P, b, phi_min, &dfb);
+  if (fa < 0.0) return 0.0;
+  if (fb >= 0.0) return b;
   for (int it = 0; it < 24 && b - a > 1e-14; ++it) {
     const double w0 = b - a;
-    // chord root (feasible side)
-    double xs = a - fa * (b - a) / (fb - fa);
+    const double xs = a - fa * (b - a) / (fb - fa);
     if (xs > a && xs < b) {
       const double f = psi_eval<DIM>(g, u, P, xs, phi_min, nullptr);
       if (f >= 0.0) { a = xs; fa = f; }
       else { b = xs; fb = f; dfb = 0.0; }
     }
-    // tangent root at b (infeasible side)
     if (dfb < 0.0) {
       const double xn = b - fb / dfb;
       if (xn > a && xn < b) {
@@ -107,7 +126,6 @@ __device__ double line_search(const Gas &g, const double *u, const double *P,
         else { a = xn; fa = f; }
       }
     }
-    // safeguard: bisect when the bracket did not halve
     if (b - a > 0.5 * w0) {
       const double xm = 0.5 * (a + b);
       double d;
@@ -115,12 +133,99 @@ __device__ double line_search(const Gas &g, const double *u, const double *P,
       if (f >= 0.0) { a = xm; fa = f; }
       else { b = xm; fb = f; dfb = d; }
     }
-    if (dfb == 0.0 && b - a > 1e-14) {
-      // refresh the derivative at b for the next tangent step
-      psi_eval<DIM>(g, u, P, b, phi_min, &dfb);
-    }
+    if (dfb == 0.0 && b - a > 1e-14) psi_eval<DIM>(g, u, P, b, phi_min, &dfb);
   }
   return a;
+}
+
+// Root of the entropy bound for gamma = 7/5 on the polynomial form of the
+// test: g(l) = A(l)^5 - phi_min^5 rho(l)^12 with rho(l) = rho + l P_rho and
+// A(l) = rho(l) E(l) - |m(l)|^2/2 = a0 + a1 l + a2 l^2 (rho(l) eps(l)).  g has
+// the sign of psi wherever rho > 0, so its root in (0, b) is psi's.
+// Safeguarded Newton inside the bracket [a, b] (g(a) >= 0 > g(b)), falling
+// back to bisection when a Newton step leaves the bracket or shrinks it too
+// little; stops at a bracket of 1e-14 and returns the feasible end.  No
+// divisions by state values and no pow: a handful of FMAs per iteration.
+template <int DIM>
+__device__ __forceinline__ double entropy_root_seven(const double *u,
+                                                    const double *P, double b,
+                                                    double pmin5) {
+  const double r0 = u[0], pr = P[0];
+  double m0p = 0.0, pm2 = 0.0, m02 = 0.0;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    m0p += u[1 + k] * P[1 + k];
+    pm2 += P[1 + k] * P[1 + k];
+    m02 += u[1 + k] * u[1 + k];
+  }
+  const double E0 = u[DIM + 1], pE = P[DIM + 1];
+  const double a0 = r0 * E0 - 0.5 * m02;
+  const double a1 = r0 * pE + pr * E0 - m0p;
+  const double a2 = pr * pE - 0.5 * pm2;
+  auto g = [&](double l, double *dg) {
+    const double r = r0 + l * pr;
+    const double A = a0 + l * (a1 + l * a2);
+    const double dA = a1 + 2.0 * l * a2;
+    const double A2 = A * A, A4 = A2 * A2;
+    const double r2 = r * r, r4 = r2 * r2, r8 = r4 * r4, r11 = r8 * r2 * r;
+    *dg = 5.0 * A4 * dA - 12.0 * pmin5 * r11 * pr;
+    return A4 * A - pmin5 * (r11 * r);
+  };
+  double a = 0.0, dga, dgb;
+  double ga = g(0.0, &dga);
+  double gb = g(b, &dgb);
+  if (!(ga >= 0.0)) return 0.0;
+  if (gb >= 0.0) return b;
+  // start from the chord's root, then Newton; once a Newton step is below
+  // round-off the bracket is closed with two probes around it
+  double x = a - ga * (b - a) / (gb - ga);
+  if (!(x > a && x < b)) x = 0.5 * (a + b);
+  for (int it = 0; it < 60 && b - a > 1e-14; ++it) {
+    double dgx;
+    const double gx = g(x, &dgx);
+    if (gx >= 0.0) a = x;
+    else b = x;
+    if (b - a <= 1e-14) break;
+    double xn = x - gx / dgx;
+    if (!(xn > a && xn < b)) {
+      xn = 0.5 * (a + b);
+    } else if (fabs(xn - x) < 2e-15) {
+      double d;
+      const double lo = fmax(xn - 4e-15, a), hi = fmin(xn + 4e-15, b);
+      if (g(lo, &d) >= 0.0) a = lo; else b = lo;
+      if (hi > a && hi < b) {
+        if (g(hi, &d) >= 0.0) a = hi; else b = hi;
+      }
+      xn = 0.5 * (a + b);
+    }
+    x = xn;
+  }
+  return a;
+}
+
+// Root of the entropy bound to the accuracy of psi itself.  For gamma = 7/5
+// the polynomial root (whose own rounding can leave it ~1e-12 away) is
+// followed by one Newton step on psi: psi is concave, so the tangent root x1
+// is infeasible and, from such a close start, within round-off of the root;
+// the feasible point just below it is returned once psi confirms it.
+// Otherwise (or if that check fails) the bracketing search on psi runs.
+template <int DIM>
+__device__ __forceinline__ double entropy_root_fast(const Gas &g, const double *u,
+                                                   const double *P, double lr,
+                                                   double pmin, double pmin5) {
+  if (g.seven) {
+    const double x = entropy_root_seven<DIM>(u, P, lr, pmin5);
+    double d;
+    const double f = psi_eval<DIM>(g, u, P, x, pmin, &d);
+    if (d < 0.0) {
+      const double x1 = x - f / d;
+      if (x1 > 0.0 && x1 <= lr) {
+        const double a = fmax(x1 - 2e-15, 0.0);
+        if (psi_eval<DIM>(g, u, P, a, pmin, nullptr) >= 0.0) return a;
+      }
+    }
+  }
+  return entropy_root<DIM>(g, u, P, lr, pmin);
 }
 
 }  // namespace ns

@@ -2,6 +2,7 @@
 // See hyp_kernels.hpp for the sweep structure and data layout.
 #include "hyp_kernels.hpp"
 
+#include <algorithm>
 #include <climits>
 
 namespace ns {
@@ -14,6 +15,45 @@ template <int DIM> struct Aux {
   static constexpr int P = DIM, A = DIM + 1, B = DIM + 2, ETA = DIM + 3,
                        PHI = DIM + 4, COUNT = DIM + 5;
 };
+
+// Row width 3^DIM, processed in unrolled chunks of CH slots: the neighbour
+// gathers of a chunk are issued together, while the chunk size bounds the
+// registers a lane holds (and so the occupancy that hides gather latency).
+#ifndef NS_CH_VISC
+#define NS_CH_VISC 1
+#endif
+#ifndef NS_CH_LO
+#define NS_CH_LO 1
+#endif
+#ifndef NS_CH_LIM1
+#define NS_CH_LIM1 1
+#endif
+#ifndef NS_CH_LIM2
+#define NS_CH_LIM2 1
+#endif
+#ifndef NS_CH_FIN
+#define NS_CH_FIN 1
+#endif
+#ifndef NS_CACHE_P
+#define NS_CACHE_P 0
+#endif
+template <int DIM, int CHUNK = 9> struct Cfg {
+  static constexpr int NC = DIM + 2;
+  static constexpr int W = DIM == 2 ? 9 : 27;
+  static constexpr int CH = CHUNK;
+  static constexpr int NCH = W / CH;
+  static_assert(W % CH == 0, "chunk must divide the row width");
+};
+
+// Edge arrays are sliced ELL: rows are grouped in slices of 64 (one
+// wavefront) and within a slice stored slot-major, so the 64 lanes of a wave
+// reading slot k touch 64 consecutive entries, and all slots of the slice
+// share one contiguous block (one page) of every edge array.
+template <int DIM>
+__device__ __forceinline__ int64_t eidx(int k, int64_t i) {
+  constexpr int W = DIM == 2 ? 9 : 27;
+  return ((i >> 6) * W + k) * 64 + (i & 63);
+}
 
 __device__ __forceinline__ int64_t row_id() {
   return (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -93,6 +133,10 @@ __global__ __launch_bounds__(kBlock) void k_prim(int64_t N,
 
 // ---------------------------------------------------------------------------
 // Graph viscosity d^L_ij (j > i, stored at (i,j) and (j,i)) and alpha_i.
+// All column indices of the row are loaded first; each chunk of slots then
+// gathers its neighbour data unconditionally (absent entries read row i
+// itself) so that the loads of a chunk are in flight together, and the
+// arithmetic is predicated on the entry being present.
 template <int DIM, int IND>
 __global__ __launch_bounds__(kBlock) void k_visc(DevGraph G,
                                                  const double *__restrict__ U,
@@ -101,11 +145,16 @@ __global__ __launch_bounds__(kBlock) void k_visc(DevGraph G,
                                                  double *__restrict__ alpha,
                                                  Gas g) {
   using X = Aux<DIM>;
-  constexpr int NC = DIM + 2;
+  using C = Cfg<DIM, NS_CH_VISC>;
+  constexpr int NC = C::NC;
   const int64_t N = G.N;
   const int64_t i = row_id();
   if (i >= N) return;
-  const int W = G.W;
+  const int32_t *__restrict__ colp = G.col;
+  const uint8_t *__restrict__ trkp = G.trk;
+  int32_t jv[C::W];
+#pragma unroll
+  for (int k = 0; k < C::W; ++k) jv[k] = colp[eidx<DIM>(k, i)];
   double vi[DIM];
 #pragma unroll
   for (int k = 0; k < DIM; ++k) vi[k] = aux[k * N + i];
@@ -131,69 +180,79 @@ __global__ __launch_bounds__(kBlock) void k_visc(DevGraph G,
     etap[NC - 1] = -ri * ie;
   }
   double num = 0.0, den = 0.0, scl = 0.0;
-  for (int k = 0; k < W; ++k) {
-    const int64_t e = (int64_t)k * N + i;
-    const int32_t j = G.col[e];
-    if (j < 0) continue;
-    double c[DIM];
-    load_c<DIM>(G, e, c);
-    double vj[DIM];
 #pragma unroll
-    for (int q = 0; q < DIM; ++q) vj[q] = aux[q * N + j];
-    const double pj = aux[X::P * N + j], aj = aux[X::A * N + j];
-    if constexpr (IND == 0) {
-      double uj[NC], fc[NC];
-      load_state<NC>(U, N, j, uj);
-      const double etaj = aux[X::ETA * N + j];
-      double vc = 0.0, c2 = 0.0;
+  for (int ch = 0; ch < C::NCH; ++ch) {
+    double c[C::CH][DIM], vj[C::CH][DIM], pj[C::CH], aj[C::CH], bj[C::CH];
+    double uj[C::CH][IND == 0 ? NC : 1], etaj[C::CH];
 #pragma unroll
-      for (int q = 0; q < DIM; ++q) {
-        vc += vj[q] * c[q];
-        c2 += c[q] * c[q];
+    for (int kk = 0; kk < C::CH; ++kk) {
+      const int k = ch * C::CH + kk;
+      const int64_t e = eidx<DIM>(k, i);
+      const int64_t js = jv[k] >= 0 ? jv[k] : i;
+      load_c<DIM>(G, e, c[kk]);
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) vj[kk][q] = aux[q * N + js];
+      pj[kk] = aux[X::P * N + js];
+      aj[kk] = aux[X::A * N + js];
+      bj[kk] = aux[X::B * N + js];
+      if constexpr (IND == 0) {
+        load_state<NC>(U, N, js, uj[kk]);
+        etaj[kk] = aux[X::ETA * N + js];
       }
-      flux_dot<DIM>(uj, vj, pj, c, fc);
-      double t = etaj * vc;
-#pragma unroll
-      for (int q = 0; q < NC; ++q) t -= etap[q] * fc[q];
-      num += t;
-      den += fabs(t);
-      scl += sqrt(c2) * aj * (uj[0] + fabs(etaj));
     }
-    if (j > i) {
-      const double bj = aux[X::B * N + j];
+#pragma unroll
+    for (int kk = 0; kk < C::CH; ++kk) {
+      const int k = ch * C::CH + kk;
+      const int32_t j = jv[k];
+      if (j < 0) continue;
       double c2 = 0.0;
 #pragma unroll
-      for (int q = 0; q < DIM; ++q) c2 += c[q] * c[q];
+      for (int q = 0; q < DIM; ++q) c2 += c[kk][q] * c[kk][q];
       const double cn = sqrt(c2);
-      const double icn = 1.0 / cn;
-      double uL = 0.0, uR = 0.0;
+      if constexpr (IND == 0) {
+        double fc[NC], vc = 0.0;
 #pragma unroll
-      for (int q = 0; q < DIM; ++q) {
-        uL += vi[q] * c[q] * icn;
-        uR += vj[q] * c[q] * icn;
+        for (int q = 0; q < DIM; ++q) vc += vj[kk][q] * c[kk][q];
+        flux_dot<DIM>(uj[kk], vj[kk], pj[kk], c[kk], fc);
+        double t = etaj[kk] * vc;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) t -= etap[q] * fc[q];
+        num += t;
+        den += fabs(t);
+        scl += cn * aj[kk] * (uj[kk][0] + fabs(etaj[kk]));
       }
-      double dij = lambda_max(g, uL, pi, ai, bi, uR, pj, aj, bj) * cn;
-      const int kt = G.trk[e];
-      const int64_t et = (int64_t)kt * N + j;
-      if (wall_i) {
-        // both ends may be on the wall: c_ji != -c_ij, take both directions
-        double ct[DIM];
-        load_c<DIM>(G, et, ct);
-        double ct2 = 0.0;
-#pragma unroll
-        for (int q = 0; q < DIM; ++q) ct2 += ct[q] * ct[q];
-        const double ctn = sqrt(ct2);
-        const double ictn = 1.0 / ctn;
-        double uLt = 0.0, uRt = 0.0;
+      if (j > i) {
+        const int64_t e = eidx<DIM>(k, i);
+        const double icn = 1.0 / cn;
+        double uL = 0.0, uR = 0.0;
 #pragma unroll
         for (int q = 0; q < DIM; ++q) {
-          uLt += vj[q] * ct[q] * ictn;
-          uRt += vi[q] * ct[q] * ictn;
+          uL += vi[q] * c[kk][q] * icn;
+          uR += vj[kk][q] * c[kk][q] * icn;
         }
-        dij = fmax(dij, lambda_max(g, uLt, pj, aj, bj, uRt, pi, ai, bi) * ctn);
+        double dij = lambda_max(g, uL, pi, ai, bi, uR, pj[kk], aj[kk], bj[kk]) * cn;
+        const int kt = trkp[e];
+        const int64_t et = eidx<DIM>(kt, j);
+        if (wall_i) {
+          // both ends may be on the wall: c_ji != -c_ij, take both directions
+          double ct[DIM];
+          load_c<DIM>(G, et, ct);
+          double ct2 = 0.0;
+#pragma unroll
+          for (int q = 0; q < DIM; ++q) ct2 += ct[q] * ct[q];
+          const double ctn = sqrt(ct2);
+          const double ictn = 1.0 / ctn;
+          double uLt = 0.0, uRt = 0.0;
+#pragma unroll
+          for (int q = 0; q < DIM; ++q) {
+            uLt += vj[kk][q] * ct[q] * ictn;
+            uRt += vi[q] * ct[q] * ictn;
+          }
+          dij = fmax(dij, lambda_max(g, uLt, pj[kk], aj[kk], bj[kk], uRt, pi, ai, bi) * ctn);
+        }
+        d[e] = dij;
+        d[et] = dij;
       }
-      d[e] = dij;
-      d[et] = dij;
     }
   }
   if constexpr (IND == 0) alpha[i] = fabs(num) / (den + 1e-2 * scl);
@@ -203,18 +262,22 @@ __global__ __launch_bounds__(kBlock) void k_visc(DevGraph G,
 
 // ---------------------------------------------------------------------------
 // Time step: per-block min of m_i / (2 sum_{j != i} d_ij) = -m_i / (2 d_ii).
+template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_dt_partial(DevGraph G,
                                                        const double *__restrict__ d,
                                                        double *__restrict__ partial) {
+  using C = Cfg<DIM>;
   const int64_t N = G.N;
   const int64_t i = row_id();
   double r = INFINITY;
   if (i < N) {
     double dsum = 0.0;
-    for (int k = 0; k < G.W; ++k) {
-      const int64_t e = (int64_t)k * N + i;
+#pragma unroll
+    for (int k = 0; k < C::W; ++k) {
+      const int64_t e = eidx<DIM>(k, i);
       const int32_t j = G.col[e];
-      if (j >= 0 && j != i) dsum += d[e];
+      const double v = d[e];  // absent entries hold 0
+      if (j >= 0 && j != i) dsum += v;
     }
     r = G.mi[i] / (2.0 * dsum);
   }
@@ -239,65 +302,92 @@ __global__ __launch_bounds__(1024) void k_dt_final(const double *__restrict__ pa
 }
 
 // ---------------------------------------------------------------------------
-// Low-order update, bounds and high-order flux.
+// Low-order update, bounds and high-order flux (stored divided by m_i).
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_lo(DevGraph G, StageArgs A, Gas g) {
   using X = Aux<DIM>;
-  constexpr int NC = DIM + 2;
+  using C = Cfg<DIM, NS_CH_LO>;
+  constexpr int NC = C::NC;
   const int64_t N = G.N;
   const int64_t i = row_id();
   if (i >= N) return;
+  if (i == 0) {  // the limiter work lists of this stage start empty
+    A.qcnt[0] = 0;
+    A.qcnt[1] = 0;
+  }
   const double *__restrict__ U = A.U;
   const double *__restrict__ aux = A.aux;
+  const double *__restrict__ alpha = A.alpha;
+  const double *__restrict__ dd = A.d;
+  const int32_t *__restrict__ colp = G.col;
+  int32_t jv[C::W];
+#pragma unroll
+  for (int k = 0; k < C::W; ++k) jv[k] = colp[eidx<DIM>(k, i)];
   double ui[NC], vi[DIM];
   load_state<NC>(U, N, i, ui);
 #pragma unroll
   for (int k = 0; k < DIM; ++k) vi[k] = aux[k * N + i];
   const double pi = aux[X::P * N + i];
-  const double ali = A.alpha[i];
+  const double ali = alpha[i];
   const double tau = *A.tau;
   double acc[NC], fh[NC];
 #pragma unroll
   for (int q = 0; q < NC; ++q) { acc[q] = 0.0; fh[q] = 0.0; }
   double rmin = ui[0], rmax = ui[0], phimin = aux[X::PHI * N + i], dsum = 0.0;
-  for (int k = 0; k < G.W; ++k) {
-    const int64_t e = (int64_t)k * N + i;
-    const int32_t j = G.col[e];
-    if (j < 0) continue;
-    double c[DIM], fci[NC];
-    load_c<DIM>(G, e, c);
-    flux_dot<DIM>(ui, vi, pi, c, fci);
-    if (j == i) {
 #pragma unroll
-      for (int q = 0; q < NC; ++q) fh[q] -= fci[q];
-      continue;
+  for (int ch = 0; ch < C::NCH; ++ch) {
+    double c[C::CH][DIM], uj[C::CH][NC], vj[C::CH][DIM], pj[C::CH], phij[C::CH],
+        alj[C::CH], dij[C::CH];
+#pragma unroll
+    for (int kk = 0; kk < C::CH; ++kk) {
+      const int k = ch * C::CH + kk;
+      const int64_t e = eidx<DIM>(k, i);
+      const int64_t js = jv[k] >= 0 ? jv[k] : i;
+      load_c<DIM>(G, e, c[kk]);
+      load_state<NC>(U, N, js, uj[kk]);
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) vj[kk][q] = aux[q * N + js];
+      pj[kk] = aux[X::P * N + js];
+      phij[kk] = aux[X::PHI * N + js];
+      alj[kk] = alpha[js];
+      dij[kk] = dd[e];
     }
-    double uj[NC], vj[DIM], fcj[NC];
-    load_state<NC>(U, N, j, uj);
 #pragma unroll
-    for (int q = 0; q < DIM; ++q) vj[q] = aux[q * N + j];
-    const double pj = aux[X::P * N + j];
-    flux_dot<DIM>(uj, vj, pj, c, fcj);
-    const double dij = A.d[e];
-    // density of the bar state (eq. bar_state) for the local bounds
-    const double rbar = 0.5 * (ui[0] + uj[0]) - (fcj[0] - fci[0]) / (2.0 * dij);
-    rmin = fmin(rmin, rbar);
-    rmax = fmax(rmax, rbar);
-    phimin = fmin(phimin, aux[X::PHI * N + j]);
-    const double dH = 0.5 * (ali + A.alpha[j]) * dij;
+    for (int kk = 0; kk < C::CH; ++kk) {
+      const int k = ch * C::CH + kk;
+      const int32_t j = jv[k];
+      if (j < 0) continue;
+      double fci[NC];
+      flux_dot<DIM>(ui, vi, pi, c[kk], fci);
+      if (j == i) {
 #pragma unroll
-    for (int q = 0; q < NC; ++q) {
-      const double du = uj[q] - ui[q];
-      acc[q] += dij * du - (fcj[q] - fci[q]);
-      fh[q] += -fcj[q] + dH * du;
+        for (int q = 0; q < NC; ++q) fh[q] -= fci[q];
+        continue;
+      }
+      double fcj[NC];
+      flux_dot<DIM>(uj[kk], vj[kk], pj[kk], c[kk], fcj);
+      const double dk = dij[kk];
+      // density of the bar state (eq. bar_state) for the local bounds
+      const double rbar = 0.5 * (ui[0] + uj[kk][0]) - (fcj[0] - fci[0]) / (2.0 * dk);
+      rmin = fmin(rmin, rbar);
+      rmax = fmax(rmax, rbar);
+      phimin = fmin(phimin, phij[kk]);
+      const double dH = 0.5 * (ali + alj[kk]) * dk;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const double du = uj[kk][q] - ui[q];
+        acc[q] += dk * du - (fcj[q] - fci[q]);
+        fh[q] += -fcj[q] + dH * du;
+      }
+      dsum += dk;
     }
-    dsum += dij;
   }
-  const double tm = tau * G.rmi[i];
+  const double rmi = G.rmi[i];
+  const double tm = tau * rmi;
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
     A.UL[q * N + i] = ui[q] + tm * acc[q];
-    A.FH[q * N + i] = fh[q];
+    A.FH[q * N + i] = fh[q] * rmi;
   }
   if (A.check_cfl && tau > G.mi[i] / (2.0 * dsum)) A.flags[0] = 1;
   const double r = G.rrel[i];
@@ -307,12 +397,13 @@ __global__ __launch_bounds__(kBlock) void k_lo(DevGraph G, StageArgs A, Gas g) {
 }
 
 // P_ij = tau/(m_i lambda_i) (b_ij F_j - b_ji F_i + (dH - d)(U_j - U_i)) with
-// b_ij = -m_ij/m_j, b_ji = -m_ij/m_i (Sec. 3.3).
+// b_ij = -m_ij/m_j, b_ji = -m_ij/m_i (Sec. 3.3); with Fs = F^H/m stored:
+// P_ij = tau (|I(i)|-1)/m_i (m_ij (Fs_i - Fs_j) + (dH - d)(U_j - U_i)).
 template <int DIM>
 struct RowCtx {
   static constexpr int NC = DIM + 2;
   double ui[NC], fi[NC];
-  double ali, rmi_i, coef;
+  double ali, coef;
 };
 
 template <int DIM>
@@ -323,27 +414,46 @@ __device__ __forceinline__ void load_row(const DevGraph &G, const StageArgs &A,
   load_state<NC>(A.U, N, i, R.ui);
   load_state<NC>(A.FH, N, i, R.fi);
   R.ali = A.alpha[i];
-  R.rmi_i = G.rmi[i];
-  R.coef = tau * G.lfac[i] * R.rmi_i;
+  R.coef = tau * G.lfac[i] * G.rmi[i];
+}
+
+// Neighbour data entering P_ij, gathered unconditionally (absent entries
+// read row i itself) so that a chunk's loads are in flight together.
+template <int DIM>
+struct PIn {
+  static constexpr int NC = DIM + 2;
+  double u[NC], f[NC], al, d, m;
+};
+
+template <int DIM>
+__device__ __forceinline__ void gather_P(const DevGraph &G, const StageArgs &A,
+                                         int64_t e, int64_t js, PIn<DIM> &x) {
+  constexpr int NC = DIM + 2;
+  const int64_t N = G.N;
+  load_state<NC>(A.U, N, js, x.u);
+  load_state<NC>(A.FH, N, js, x.f);
+  x.al = A.alpha[js];
+  x.d = A.d[e];
+  x.m = G.mij[e];
+}
+
+template <int DIM>
+__device__ __forceinline__ void make_P(const RowCtx<DIM> &R, const PIn<DIM> &x,
+                                       double *P) {
+  constexpr int NC = DIM + 2;
+  const double dH = 0.5 * (R.ali + x.al) * x.d;
+#pragma unroll
+  for (int q = 0; q < NC; ++q)
+    P[q] = R.coef * (x.m * (R.fi[q] - x.f[q]) + (dH - x.d) * (x.u[q] - R.ui[q]));
 }
 
 template <int DIM>
 __device__ __forceinline__ void compute_P(const DevGraph &G, const StageArgs &A,
                                           const RowCtx<DIM> &R, int64_t e,
                                           int32_t j, double *P) {
-  constexpr int NC = DIM + 2;
-  const int64_t N = G.N;
-  double uj[NC], fj[NC];
-  load_state<NC>(A.U, N, j, uj);
-  load_state<NC>(A.FH, N, j, fj);
-  const double dij = A.d[e];
-  const double dH = 0.5 * (R.ali + A.alpha[j]) * dij;
-  const double mij = G.mij[e];
-  const double rmj = G.rmi[j];
-#pragma unroll
-  for (int q = 0; q < NC; ++q)
-    P[q] = R.coef * (mij * (R.fi[q] * R.rmi_i - fj[q] * rmj) +
-                     (dH - dij) * (uj[q] - R.ui[q]));
+  PIn<DIM> x;
+  gather_P<DIM>(G, A, e, j, x);
+  make_P<DIM>(R, x, P);
 }
 
 template <int DIM>
@@ -370,98 +480,302 @@ __device__ __forceinline__ void finish(const DevGraph &G, const StageArgs &A,
   for (int q = 0; q < NC; ++q) A.out[q * N + i] = w[q];
 }
 
+struct Bounds {
+  double rmin, rmax, pmin, pmin5;
+};
+
+__device__ __forceinline__ Bounds load_bounds(const StageArgs &A, int64_t N,
+                                              int64_t i) {
+  Bounds b;
+  b.rmin = A.bnds[i];
+  b.rmax = A.bnds[N + i];
+  b.pmin = A.bnds[2 * N + i];
+  const double p2 = b.pmin * b.pmin;
+  b.pmin5 = p2 * p2 * b.pmin;
+  return b;
+}
+
+// Limiter line search for every off-diagonal entry of the row.  The cheap
+// part (density limit, entropy test at that limit and at 0) runs in the
+// row sweep, which stores l = l_rho; entries whose entropy bound cuts inside
+// (0, l_rho) are appended to the work list and their root is found by
+// k_root.  In a sweep such entries are rare but scattered: solved in place,
+// a few lanes would hold their whole wavefront for the length of a root
+// search, and the root finder's registers would lower the sweep's occupancy.
+template <int DIM>
+__device__ __forceinline__ int limit_fast(const Gas &g, const double *u,
+                                          const double *P, const Bounds &b,
+                                          double *l) {
+  double lr;
+  if (P[0] > 0.0) lr = (b.rmax - u[0]) / P[0];
+  else if (P[0] < 0.0) lr = (b.rmin - u[0]) / P[0];
+  else lr = 1.0;
+  lr = fmin(fmax(lr, 0.0), 1.0);
+  *l = lr;
+  if (entropy_ok<DIM>(g, u, P, lr, b.pmin, b.pmin5)) return 0;
+  if (!entropy_ok<DIM>(g, u, P, 0.0, b.pmin, b.pmin5)) { *l = 0.0; return 0; }
+  return 1;  // root of psi in (0, lr) still to be found
+}
+
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_lim1(DevGraph G, StageArgs A, Gas g) {
-  constexpr int NC = DIM + 2;
+  using C = Cfg<DIM, NS_CH_LIM1>;
+  constexpr int NC = C::NC;
   const int64_t N = G.N;
   const int64_t i = row_id();
   if (i >= N) return;
+  const int32_t *__restrict__ colp = G.col;
+  int32_t jv[C::W];
+#pragma unroll
+  for (int k = 0; k < C::W; ++k) jv[k] = colp[eidx<DIM>(k, i)];
   RowCtx<DIM> R;
   load_row<DIM>(G, A, i, *A.tau, R);
   double ul[NC];
   load_state<NC>(A.UL, N, i, ul);
-  const double rmin = A.bnds[i], rmax = A.bnds[N + i], pmin = A.bnds[2 * N + i];
-  for (int k = 0; k < G.W; ++k) {
-    const int64_t e = (int64_t)k * N + i;
-    const int32_t j = G.col[e];
-    if (j < 0 || j == i) continue;
-    double P[NC];
-    compute_P<DIM>(G, A, R, e, j, P);
-    A.lt1[e] = line_search<DIM>(g, ul, P, rmin, rmax, pmin);
+  const Bounds b = load_bounds(A, N, i);
+  double *__restrict__ lt1 = A.lt1;
+  uint32_t slow = 0;
+#pragma unroll
+  for (int ch = 0; ch < C::NCH; ++ch) {
+    PIn<DIM> x[C::CH];
+#pragma unroll
+    for (int kk = 0; kk < C::CH; ++kk) {
+      const int k = ch * C::CH + kk;
+      gather_P<DIM>(G, A, eidx<DIM>(k, i), jv[k] >= 0 ? jv[k] : i, x[kk]);
+    }
+#pragma unroll
+    for (int kk = 0; kk < C::CH; ++kk) {
+      const int k = ch * C::CH + kk;
+      if (jv[k] < 0 || jv[k] == i) continue;
+      double P[NC], l;
+      make_P<DIM>(R, x[kk], P);
+      if (limit_fast<DIM>(g, ul, P, b, &l)) slow |= 1u << k;
+      lt1[eidx<DIM>(k, i)] = l;
+    }
+  }
+  if (slow) {
+    uint32_t t = atomicAdd(&A.qcnt[0], (uint32_t)__builtin_popcount(slow));
+    while (slow) {
+      const int k = __builtin_ctz(slow);
+      slow &= slow - 1;
+      A.q[t++] = (uint32_t)eidx<DIM>(k, i);
+    }
   }
 }
 
-// MODE 0: convex, pass 1 update + pass-2 line search; 1: convex with one
+// MODE 0: convex, pass-1 update + pass-2 line search; 1: convex with one
 // pass, final; 2: l = 1 (unlimited high order), final.
 template <int DIM, int MODE>
 __global__ __launch_bounds__(kBlock) void k_lim2(DevGraph G, StageArgs A, Gas g) {
-  constexpr int NC = DIM + 2;
+  using C = Cfg<DIM, NS_CH_LIM2>;
+  constexpr int NC = C::NC;
   const int64_t N = G.N;
   const int64_t i = row_id();
   if (i >= N) return;
+  const int32_t *__restrict__ colp = G.col;
+  const uint8_t *__restrict__ trkp = G.trk;
+  const double *__restrict__ lt1 = A.lt1;
+  int32_t jv[C::W];
+  int tv[C::W];
+#pragma unroll
+  for (int k = 0; k < C::W; ++k) {
+    jv[k] = colp[eidx<DIM>(k, i)];
+    tv[k] = MODE != 2 ? trkp[eidx<DIM>(k, i)] : 0;
+  }
   RowCtx<DIM> R;
   load_row<DIM>(G, A, i, *A.tau, R);
   const double lam = 1.0 / G.lfac[i];
   double u1[NC];
   load_state<NC>(A.UL, N, i, u1);
-  for (int k = 0; k < G.W; ++k) {
-    const int64_t e = (int64_t)k * N + i;
-    const int32_t j = G.col[e];
-    if (j < 0 || j == i) continue;
-    double l = 1.0;
-    if constexpr (MODE != 2) {
-      const int64_t et = (int64_t)G.trk[e] * N + j;
-      l = fmin(A.lt1[e], A.lt1[et]);
-    }
-    double P[NC];
-    compute_P<DIM>(G, A, R, e, j, P);
+  // 2D: the row's P_ij and l_ij stay in registers for the pass-2 search
+  constexpr bool CACHE = DIM == 2 && MODE == 0;
+  double Pc[CACHE ? C::W : 1][NC];
+  double lc[CACHE ? C::W : 1];
 #pragma unroll
-    for (int q = 0; q < NC; ++q) u1[q] += lam * l * P[q];
+  for (int ch = 0; ch < C::NCH; ++ch) {
+    PIn<DIM> x[C::CH];
+    double la[C::CH], lb[C::CH];
+#pragma unroll
+    for (int kk = 0; kk < C::CH; ++kk) {
+      const int k = ch * C::CH + kk;
+      const int64_t e = eidx<DIM>(k, i);
+      const int64_t js = jv[k] >= 0 ? jv[k] : i;
+      gather_P<DIM>(G, A, e, js, x[kk]);
+      if constexpr (MODE != 2) {
+        la[kk] = lt1[e];
+        lb[kk] = lt1[eidx<DIM>(tv[k], js)];
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < C::CH; ++kk) {
+      const int k = ch * C::CH + kk;
+      if (jv[k] < 0 || jv[k] == i) continue;
+      const double l = MODE != 2 ? fmin(la[kk], lb[kk]) : 1.0;
+      double P[NC];
+      make_P<DIM>(R, x[kk], P);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) u1[q] += lam * l * P[q];
+      if constexpr (CACHE) {
+#pragma unroll
+        for (int q = 0; q < NC; ++q) Pc[k][q] = P[q];
+        lc[k] = l;
+      }
+    }
   }
   if constexpr (MODE != 0) {
     finish<DIM>(G, A, i, u1);
   } else {
 #pragma unroll
     for (int q = 0; q < NC; ++q) A.U1[q * N + i] = u1[q];
-    const double rmin = A.bnds[i], rmax = A.bnds[N + i],
-                 pmin = A.bnds[2 * N + i];
-    for (int k = 0; k < G.W; ++k) {
-      const int64_t e = (int64_t)k * N + i;
-      const int32_t j = G.col[e];
-      if (j < 0 || j == i) continue;
-      const int64_t et = (int64_t)G.trk[e] * N + j;
-      const double l = fmin(A.lt1[e], A.lt1[et]);
-      double P[NC];
-      compute_P<DIM>(G, A, R, e, j, P);
-#pragma unroll
-      for (int q = 0; q < NC; ++q) P[q] *= (1.0 - l);
-      A.lt2[e] = line_search<DIM>(g, u1, P, rmin, rmax, pmin);
+    const Bounds b = load_bounds(A, N, i);
+    double *__restrict__ lt2 = A.lt2;
+    uint32_t slow = 0;
+    if constexpr (!CACHE) {
+      // reload the neighbour data rather than keep a whole row of it live
+      asm volatile("" ::: "memory");
     }
+#pragma unroll
+    for (int ch = 0; ch < C::NCH; ++ch) {
+      double P[C::CH][NC], l[C::CH];
+      if constexpr (CACHE) {
+#pragma unroll
+        for (int kk = 0; kk < C::CH; ++kk) {
+          const int k = ch * C::CH + kk;
+#pragma unroll
+          for (int q = 0; q < NC; ++q) P[kk][q] = Pc[k][q];
+          l[kk] = lc[k];
+        }
+      } else {
+        // one chunk of gathers in flight at a time (bounds the registers)
+        asm volatile("" ::: "memory");
+        PIn<DIM> x[C::CH];
+        double la[C::CH], lb[C::CH];
+#pragma unroll
+        for (int kk = 0; kk < C::CH; ++kk) {
+          const int k = ch * C::CH + kk;
+          const int64_t e = eidx<DIM>(k, i);
+          const int64_t js = jv[k] >= 0 ? jv[k] : i;
+          gather_P<DIM>(G, A, e, js, x[kk]);
+          la[kk] = lt1[e];
+          lb[kk] = lt1[eidx<DIM>(tv[k], js)];
+        }
+#pragma unroll
+        for (int kk = 0; kk < C::CH; ++kk) {
+          make_P<DIM>(R, x[kk], P[kk]);
+          l[kk] = fmin(la[kk], lb[kk]);
+        }
+      }
+#pragma unroll
+      for (int kk = 0; kk < C::CH; ++kk) {
+        const int k = ch * C::CH + kk;
+        if (jv[k] < 0 || jv[k] == i) continue;
+        double l2;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) P[kk][q] *= (1.0 - l[kk]);
+        if (limit_fast<DIM>(g, u1, P[kk], b, &l2)) slow |= 1u << k;
+        lt2[eidx<DIM>(k, i)] = l2;
+      }
+    }
+    if (slow) {
+      uint32_t t = atomicAdd(&A.qcnt[1], (uint32_t)__builtin_popcount(slow));
+      while (slow) {
+        const int k = __builtin_ctz(slow);
+        slow &= slow - 1;
+        A.q[t++] = (uint32_t)eidx<DIM>(k, i);
+      }
+    }
+  }
+}
+
+// Row of a sliced-ELL edge index (inverse of eidx in the row).
+template <int DIM>
+__device__ __forceinline__ int64_t edge_row(int64_t e) {
+  constexpr int W = DIM == 2 ? 9 : 27;
+  return ((e >> 6) / W) * 64 + (e & 63);
+}
+
+// Roots of the entropy bound for the work list of limiter pass PASS (1 or 2):
+// one lane per listed entry, grid-stride over the list, so the rare root
+// finder runs at full occupancy instead of stalling a row sweep's wavefront.
+// The line search's density limit l_rho was stored in lt by the sweep.
+template <int DIM, int PASS>
+__global__ __launch_bounds__(kBlock) void k_root(DevGraph G, StageArgs A, Gas g) {
+  constexpr int NC = DIM + 2;
+  const int64_t N = G.N;
+  const uint32_t n = A.qcnt[PASS - 1];
+  const uint32_t *__restrict__ q = A.q;
+  double *__restrict__ lt = PASS == 1 ? A.lt1 : A.lt2;
+  const double tau = *A.tau;
+  for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < n;
+       t += gridDim.x * kBlock) {
+    const int64_t e = q[t];
+    const int64_t i = edge_row<DIM>(e);
+    const int32_t j = G.col[e];
+    RowCtx<DIM> R;
+    load_row<DIM>(G, A, i, tau, R);
+    double u[NC], P[NC];
+    load_state<NC>(PASS == 1 ? A.UL : A.U1, N, i, u);
+    const Bounds b = load_bounds(A, N, i);
+    compute_P<DIM>(G, A, R, e, j, P);
+    if constexpr (PASS == 2) {
+      const double l = fmin(A.lt1[e], A.lt1[eidx<DIM>(G.trk[e], j)]);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) P[c] *= (1.0 - l);
+    }
+    lt[e] = entropy_root_fast<DIM>(g, u, P, lt[e], b.pmin, b.pmin5);
   }
 }
 
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_fin(DevGraph G, StageArgs A, Gas g) {
-  constexpr int NC = DIM + 2;
+  using C = Cfg<DIM, NS_CH_FIN>;
+  constexpr int NC = C::NC;
   const int64_t N = G.N;
   const int64_t i = row_id();
   if (i >= N) return;
+  const int32_t *__restrict__ colp = G.col;
+  const uint8_t *__restrict__ trkp = G.trk;
+  const double *__restrict__ lt1 = A.lt1;
+  const double *__restrict__ lt2 = A.lt2;
+  int32_t jv[C::W];
+  int tv[C::W];
+#pragma unroll
+  for (int k = 0; k < C::W; ++k) {
+    jv[k] = colp[eidx<DIM>(k, i)];
+    tv[k] = trkp[eidx<DIM>(k, i)];
+  }
   RowCtx<DIM> R;
   load_row<DIM>(G, A, i, *A.tau, R);
   const double lam = 1.0 / G.lfac[i];
   double u2[NC];
   load_state<NC>(A.U1, N, i, u2);
-  for (int k = 0; k < G.W; ++k) {
-    const int64_t e = (int64_t)k * N + i;
-    const int32_t j = G.col[e];
-    if (j < 0 || j == i) continue;
-    const int64_t et = (int64_t)G.trk[e] * N + j;
-    const double l1 = fmin(A.lt1[e], A.lt1[et]);
-    const double l2 = fmin(A.lt2[e], A.lt2[et]);
-    double P[NC];
-    compute_P<DIM>(G, A, R, e, j, P);
 #pragma unroll
-    for (int q = 0; q < NC; ++q) u2[q] += lam * l2 * ((1.0 - l1) * P[q]);
+  for (int ch = 0; ch < C::NCH; ++ch) {
+    PIn<DIM> x[C::CH];
+    double l1a[C::CH], l1b[C::CH], l2a[C::CH], l2b[C::CH];
+#pragma unroll
+    for (int kk = 0; kk < C::CH; ++kk) {
+      const int k = ch * C::CH + kk;
+      const int64_t e = eidx<DIM>(k, i);
+      const int64_t js = jv[k] >= 0 ? jv[k] : i;
+      const int64_t et = eidx<DIM>(tv[k], js);
+      gather_P<DIM>(G, A, e, js, x[kk]);
+      l1a[kk] = lt1[e];
+      l1b[kk] = lt1[et];
+      l2a[kk] = lt2[e];
+      l2b[kk] = lt2[et];
+    }
+#pragma unroll
+    for (int kk = 0; kk < C::CH; ++kk) {
+      const int k = ch * C::CH + kk;
+      if (jv[k] < 0 || jv[k] == i) continue;
+      const double l1 = fmin(l1a[kk], l1b[kk]);
+      const double l2 = fmin(l2a[kk], l2b[kk]);
+      double P[NC];
+      make_P<DIM>(R, x[kk], P);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) u2[q] += lam * l2 * ((1.0 - l1) * P[q]);
+    }
   }
   finish<DIM>(G, A, i, u2);
 }
@@ -559,8 +873,8 @@ void stage_impl(const Gas &gas, const DevGraph &G, const StageArgs &A,
     NS_LAUNCH("visc", hipLaunchKernelGGL((k_visc<DIM, 2>), grid, block, 0, s, G,
                                          A.U, A.aux, A.d, A.alpha, gas));
   if (auto_dt) {
-    NS_LAUNCH("dt_partial", hipLaunchKernelGGL(k_dt_partial, grid, block, 0, s, G,
-                                               A.d, A.partial));
+    NS_LAUNCH("dt_partial", hipLaunchKernelGGL(k_dt_partial<DIM>, grid, block, 0, s,
+                                               G, A.d, A.partial));
     NS_LAUNCH("dt_final", hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1024), 0, s,
                                              A.partial, (int64_t)grid.x, cfl,
                                              A.tau));
@@ -573,13 +887,20 @@ void stage_impl(const Gas &gas, const DevGraph &G, const StageArgs &A,
     NS_LAUNCH("lim2", hipLaunchKernelGGL((k_lim2<DIM, 2>), grid, block, 0, s, G, A,
                                          gas));
   } else {
+    // the work lists hold a small fraction of the edges: a grid of a few
+    // wavefronts per SIMD covers them in one or two passes
+    const dim3 rgrid(std::min<unsigned>(grid.x, 1024u));
     NS_LAUNCH("lim1", hipLaunchKernelGGL(k_lim1<DIM>, grid, block, 0, s, G, A, gas));
+    NS_LAUNCH("root1", hipLaunchKernelGGL((k_root<DIM, 1>), rgrid, block, 0, s, G,
+                                          A, gas));
     if (passes == 1) {
       NS_LAUNCH("lim2", hipLaunchKernelGGL((k_lim2<DIM, 1>), grid, block, 0, s, G,
                                            A, gas));
     } else {
       NS_LAUNCH("lim2", hipLaunchKernelGGL((k_lim2<DIM, 0>), grid, block, 0, s, G,
                                            A, gas));
+      NS_LAUNCH("root2", hipLaunchKernelGGL((k_root<DIM, 2>), rgrid, block, 0, s, G,
+                                            A, gas));
       NS_LAUNCH("fin", hipLaunchKernelGGL(k_fin<DIM>, grid, block, 0, s, G, A, gas));
     }
   }
@@ -599,7 +920,7 @@ void dt_impl(const Gas &gas, const DevGraph &G, const StageArgs &A, double cfl,
                      A.alpha, gas);
   after(prof);
   before(prof, "dt_partial");
-  hipLaunchKernelGGL(k_dt_partial, grid, block, 0, s, G, A.d, A.partial);
+  hipLaunchKernelGGL(k_dt_partial<DIM>, grid, block, 0, s, G, A.d, A.partial);
   after(prof);
   before(prof, "dt_final");
   hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1024), 0, s, A.partial,

@@ -2,10 +2,10 @@
 // hyperbolic step (Algorithm 1 of arXiv:2106.02159), gfx950.
 //
 // Layout: node arrays are structure-of-arrays (component c of node i at
-// c*N + i); edge arrays are slot-major ELL (slot k of row i at k*N + i), so
-// lane i of a wavefront reading slot k of its row produces one coalesced
-// access per slot.  One lane owns one row; neighbour data are gathered
-// through the L1/L2 caches.  Sweeps, in dependency order (each needs the
+// c*N + i); edge arrays are sliced ELL (rows in slices of 64, slot-major
+// within a slice: slot k of row i at ((i/64) W + k) 64 + i%64), so lane i of
+// a wavefront reading slot k of its row produces one coalesced access.  One
+// lane owns one row; neighbour data are gathered through the L1/L2 caches.  Sweeps, in dependency order (each needs the
 // previous one complete over the whole mesh):
 //   k_prim   per node: v, p, sound speed a, a p^(-(g-1)/(2g)), eta, Phi
 //   k_visc   d^L_ij for j > i (Sec. 3.1), written to (i,j) and (j,i);
@@ -13,7 +13,10 @@
 //   k_dt     (auto time step only) per-block min of m_i / (2 sum_j d_ij)
 //   k_lo     d_ii, stage CFL check, U^L (eq. loworder), local bounds from
 //            the bar states (eq. bar_state), F^H_i (Sec. 3.2)
-//   k_lim1   P_ij (Sec. 3.3) and the pass-1 line search l~_ij
+//   k_lim1   P_ij (Sec. 3.3) and the pass-1 line search l~_ij; entries
+//            whose entropy bound cuts inside (0, l_rho) go to a work list
+//   k_root   roots of the entropy bound for the listed entries, one lane
+//            per entry (the rare slow path, kept out of the row sweeps)
 //   k_lim2   l_ij = min(l~_ij, l~_ji), U^(1) = U^L + lambda_i sum l P;
 //            pass-2 line search on (1 - l) P (or the final state for one pass)
 //   k_fin    l' symmetrised, U = U^(1) + lambda_i sum l' (1-l) P, SSP
@@ -31,13 +34,14 @@ namespace ns {
 
 constexpr int kBlock = 256;
 
+// Np: N rounded up to a multiple of 64 (whole slices).
 struct DevGraph {
   int64_t N;
   int W;
-  const int32_t *col;   // W*N
-  const uint8_t *trk;   // W*N: slot of the transposed entry in row col
-  const double *mij;    // W*N
-  const double *c0, *c1, *c2;  // W*N each (c2 unused in 2D)
+  const int32_t *col;   // W*Np
+  const uint8_t *trk;   // W*Np: slot of the transposed entry in row col
+  const double *mij;    // W*Np
+  const double *c0, *c1, *c2;  // W*Np each (c2 unused in 2D)
   const double *mi;     // N
   const double *rmi;    // N: 1 / m_i
   const double *lfac;   // N: |I(i)| - 1 = 1 / lambda_i
@@ -51,18 +55,24 @@ struct StageArgs {
   double *out;       // stage output, nc*N
   double *aux;       // (dim+5)*N
   double *alpha;     // N
-  double *d;         // W*N
+  double *d;         // W*Np
   double *UL;        // nc*N
   double *FH;        // nc*N
   double *bnds;      // 3*N
-  double *lt1;       // W*N
-  double *lt2;       // W*N
+  double *lt1;       // W*Np
+  double *lt2;       // W*Np
   double *U1;        // nc*N
   double *partial;   // per-block minima for the time step
   double *tau;       // device scalar
   int *flags;        // [0] CFL violated, [1] inadmissible state
   double sa, sb;     // SSP combination out = sa*Un + sb*E(U)
   int check_cfl;
+  // Work list of the edges (sliced ELL index) whose line search needs the
+  // root of the entropy bound; W*Np entries, so that it holds every edge.
+  // Pass 1 fills it and k_root<1> drains it before pass 2 fills it again;
+  // qcnt[p] counts the entries of pass p+1 (reset by k_lo).
+  uint32_t *q;
+  uint32_t *qcnt;
 };
 
 void launch_stage(int dim, const Gas &gas, const DevGraph &g,

@@ -102,6 +102,7 @@ struct ns_solver {
   ns::Gas gas{};
   int dim = 0, nc = 0;
   int64_t N = 0;
+  int64_t Np = 0;  // N rounded up to the 64-row slices of the edge arrays
   int W = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -124,6 +125,7 @@ struct ns_solver {
          *FH = nullptr, *bnds = nullptr, *lt1 = nullptr, *lt2 = nullptr,
          *U1 = nullptr, *partial = nullptr, *tau = nullptr;
   int *flags = nullptr;
+  uint32_t *q = nullptr, *qcnt = nullptr;
   int *hflags = nullptr;   // pinned
   double *htau = nullptr;  // pinned
   int last_out = 1;        // buffer holding the last stage output
@@ -143,6 +145,7 @@ struct ns_solver {
     a.aux = aux; a.alpha = alpha; a.d = d; a.UL = UL; a.FH = FH; a.bnds = bnds;
     a.lt1 = lt1; a.lt2 = lt2; a.U1 = U1; a.partial = partial; a.tau = tau;
     a.flags = flags; a.sa = sa; a.sb = sb; a.check_cfl = check;
+    a.q = q; a.qcnt = qcnt;
     return a;
   }
   int fail(int code, const std::string &msg) { err = msg; return code; }
@@ -313,6 +316,10 @@ int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
                      "indicator/limiter in range, passes 1 or 2, relax >= 0)";
     return NS_EINVAL;
   }
+  if ((int64_t)g->mg.W * ((g->mg.N + 63) / 64 * 64) > (int64_t)UINT32_MAX) {
+    g_create_error = "mesh too large: edge indices must fit in 32 bits";
+    return NS_EINVAL;
+  }
   ns_solver *s = new (std::nothrow) ns_solver;
   if (!s) { g_create_error = "host allocation"; return NS_ENOMEM; }
   s->mg = g->mg;
@@ -320,6 +327,7 @@ int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
   s->dim = g->mg.dim;
   s->nc = s->dim + 2;
   s->N = g->mg.N;
+  s->Np = (g->mg.N + 63) / 64 * 64;
   s->W = g->mg.W;
   const double gm = p->gamma;
   s->gas.gamma = gm;
@@ -344,7 +352,7 @@ int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
     s->own_stream = true;
   }
   s->prof.stream = s->stream;
-  const int64_t N = s->N, W = s->W, nc = s->nc, dim = s->dim;
+  const int64_t N = s->N, W = s->W, nc = s->nc, dim = s->dim, Np = s->Np;
   const int64_t nblocks = (N + ns::kBlock - 1) / ns::kBlock;
 #define NS_ALLOC(ptr, count)                                                \
   do {                                                                      \
@@ -355,10 +363,10 @@ int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
                                  " failed: " + hipGetErrorString(e));       \
     }                                                                       \
   } while (0)
-  NS_ALLOC(s->col, W * N);
-  NS_ALLOC(s->trk, W * N);
-  NS_ALLOC(s->mij, W * N);
-  for (int k = 0; k < dim; ++k) NS_ALLOC(s->c[k], W * N);
+  NS_ALLOC(s->col, W * Np);
+  NS_ALLOC(s->trk, W * Np);
+  NS_ALLOC(s->mij, W * Np);
+  for (int k = 0; k < dim; ++k) NS_ALLOC(s->c[k], W * Np);
   NS_ALLOC(s->mi, N);
   NS_ALLOC(s->rmi, N);
   NS_ALLOC(s->lfac, N);
@@ -367,38 +375,53 @@ int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
   for (int b = 0; b < 3; ++b) NS_ALLOC(s->S[b], nc * N);
   NS_ALLOC(s->aux, (dim + 5) * N);
   NS_ALLOC(s->alpha, N);
-  NS_ALLOC(s->d, W * N);
+  NS_ALLOC(s->d, W * Np);
   NS_ALLOC(s->UL, nc * N);
   NS_ALLOC(s->FH, nc * N);
   NS_ALLOC(s->bnds, 3 * N);
-  NS_ALLOC(s->lt1, W * N);
-  NS_ALLOC(s->lt2, W * N);
+  NS_ALLOC(s->lt1, W * Np);
+  NS_ALLOC(s->lt2, W * Np);
   NS_ALLOC(s->U1, nc * N);
   NS_ALLOC(s->partial, nblocks);
   NS_ALLOC(s->tau, 1);
   NS_ALLOC(s->flags, 4);
+  // limiter root work list, large enough for every edge
+  NS_ALLOC(s->q, W * Np);
+  NS_ALLOC(s->qcnt, 2);
 
-  // --- upload the graph slot by slot (host staging of one slot at a time)
+  // --- upload the graph: generate slot by slot, place into the sliced ELL
+  // layout (entry (k, i) at ((i/64)*W + k)*64 + i%64) on the host, upload
   {
-    std::vector<int32_t> col(N);
-    std::vector<uint8_t> trk(N);
-    std::vector<double> mij(N), cc((size_t)dim * N);
+    std::vector<int32_t> col(N), scol(W * Np, -1);
+    std::vector<uint8_t> trk(N), strk(W * Np, 0);
+    std::vector<double> tmp(N), cc((size_t)dim * N);
     std::vector<int> cnt(N, 0);
-    for (int k = 0; k < W; ++k) {
-      double *cp[3] = {cc.data(), cc.data() + N, dim == 3 ? cc.data() + 2 * N : nullptr};
-      s->mg.fill_slot(k, col.data(), trk.data(), mij.data(), cp);
-      for (int64_t i = 0; i < N; ++i) cnt[i] += col[i] >= 0;
-      const size_t off = (size_t)k * N;
-      e = hipMemcpy(s->col + off, col.data(), N * sizeof(int32_t), hipMemcpyHostToDevice);
-      if (e == hipSuccess)
-        e = hipMemcpy(s->trk + off, trk.data(), N, hipMemcpyHostToDevice);
-      if (e == hipSuccess)
-        e = hipMemcpy(s->mij + off, mij.data(), N * sizeof(double), hipMemcpyHostToDevice);
-      for (int q = 0; q < dim && e == hipSuccess; ++q)
-        e = hipMemcpy(s->c[q] + off, cc.data() + (size_t)q * N, N * sizeof(double),
-                      hipMemcpyHostToDevice);
+    auto sl = [W](int k, int64_t i) { return ((i >> 6) * W + k) * 64 + (i & 63); };
+    // m_ij and the components of c_ij, one array at a time
+    for (int a = -1; a < dim; ++a) {
+      std::vector<double> sv(W * Np, 0.0);
+      for (int k = 0; k < W; ++k) {
+        double *cp[3] = {cc.data(), cc.data() + N, dim == 3 ? cc.data() + 2 * N : nullptr};
+        s->mg.fill_slot(k, col.data(), trk.data(), a < 0 ? tmp.data() : nullptr,
+                        a < 0 ? nullptr : cp);
+        const double *src = a < 0 ? tmp.data() : cc.data() + (size_t)a * N;
+        for (int64_t i = 0; i < N; ++i) sv[sl(k, i)] = src[i];
+        if (a < 0) {
+          for (int64_t i = 0; i < N; ++i) {
+            scol[sl(k, i)] = col[i];
+            strk[sl(k, i)] = trk[i];
+            cnt[i] += col[i] >= 0;
+          }
+        }
+      }
+      e = hipMemcpy(a < 0 ? s->mij : s->c[a], sv.data(), W * Np * sizeof(double),
+                    hipMemcpyHostToDevice);
       if (e != hipSuccess) return bail(NS_EHIP, "graph upload failed");
     }
+    e = hipMemcpy(s->col, scol.data(), W * Np * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(s->trk, strk.data(), W * Np, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(NS_EHIP, "graph upload failed");
     std::vector<double> mi(N), bnd((size_t)dim * N), rmi(N), lfac(N), rrel(N);
     std::vector<uint8_t> wall(N);
     s->mg.fill_nodes(mi.data(), bnd.data(), wall.data());
@@ -439,7 +462,7 @@ int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
   }
   // zero the scratch edge arrays once: entries never written stay zero
   for (double *z : {s->d, s->lt1, s->lt2}) {
-    e = hipMemset(z, 0, (size_t)W * N * sizeof(double));
+    e = hipMemset(z, 0, (size_t)W * Np * sizeof(double));
     if (e != hipSuccess) return bail(NS_EHIP, "memset failed");
   }
   e = hipHostMalloc(reinterpret_cast<void **>(&s->hflags), 4 * sizeof(int));
@@ -545,25 +568,32 @@ int ns_fe_stage(ns_solver *s, double dt) {
 
 int ns_get_debug(ns_solver *s, int what, double *out) {
   if (!s || !out) return NS_EINVAL;
-  const int64_t N = s->N, W = s->W, nc = s->nc;
+  const int64_t N = s->N, W = s->W, nc = s->nc, Np = s->Np;
   const double *src = nullptr;
   int64_t count = 0;
+  bool edge = false;
   switch (what) {
     case NS_DBG_STAGE_OUT: src = s->S[s->last_out]; count = nc * N; break;
-    case NS_DBG_D: src = s->d; count = W * N; break;
+    case NS_DBG_D: src = s->d; count = W * Np; edge = true; break;
     case NS_DBG_ALPHA: src = s->alpha; count = N; break;
     case NS_DBG_UL: src = s->UL; count = nc * N; break;
     case NS_DBG_FH: src = s->FH; count = nc * N; break;
     case NS_DBG_BOUNDS: src = s->bnds; count = 3 * N; break;
-    case NS_DBG_LT1: src = s->lt1; count = W * N; break;
-    case NS_DBG_LT2: src = s->lt2; count = W * N; break;
+    case NS_DBG_LT1: src = s->lt1; count = W * Np; edge = true; break;
+    case NS_DBG_LT2: src = s->lt2; count = W * Np; edge = true; break;
     case NS_DBG_U1: src = s->U1; count = nc * N; break;
     default: return s->fail(NS_EINVAL, "unknown debug array");
   }
-  hipError_t e = hipMemcpyAsync(out, src, count * sizeof(double),
+  std::vector<double> tmp(edge ? count : 0);
+  hipError_t e = hipMemcpyAsync(edge ? tmp.data() : out, src, count * sizeof(double),
                                 hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return s->hipfail(e, "debug download");
+  if (edge) {
+    for (int k = 0; k < W; ++k)
+      for (int64_t i = 0; i < N; ++i)
+        out[k * N + i] = tmp[((i >> 6) * W + k) * 64 + (i & 63)];
+  }
   return NS_OK;
 }
 

@@ -94,7 +94,7 @@ def test_stage(case, mode):
     assert rel_err(d[off], dbg["d"][idx][off]) <= 1e-13
     assert np.abs(s.debug("alpha") - dbg["alpha"]).max() <= 1e-10
     assert np.all(state_rel_err(s.debug("UL"), dbg["UL"]) <= 1e-13)
-    assert np.all(state_rel_err(s.debug("FH"), dbg["FH"]) <= 1e-12)
+    assert np.all(state_rel_err(s.debug("FH") * og.mi, dbg["FH"]) <= 1e-12)
     r = kw.get("relax", 1.0) * (og.mi / og.mi.sum()) ** (1.5 / og.dim)
     bref = dbg["bounds"] * np.array([1 - r, 1 + r, 1 - r])
     assert np.all(rel_err(s.debug("bounds"), bref, axis=1) <= 1e-13)
