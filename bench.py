@@ -149,8 +149,10 @@ def main():
     # plain device copy of 1 GiB: the achievable streaming bandwidth, and a
     # kernel of known traffic for calibrating hardware byte counters
     copy_bytes = 1 << 30
-    copy_ms = solver.copy_bench(copy_bytes, reps=5)
+    copy_ms = solver.copy_bench(copy_bytes, reps=5, word=16)
     copy_gbs = 2 * copy_bytes / (copy_ms * 1e-3) / 1e9
+    copy8_ms = solver.copy_bench(copy_bytes, reps=5, word=8)
+    copy8_gbs = 2 * copy_bytes / (copy8_ms * 1e-3) / 1e9
 
     N = graph.N
     stages = 3 * args.steps
@@ -191,6 +193,7 @@ def main():
                      "algorithmic_bytes": kb},
         "stage_algorithmic_frac": stage_frac,
         "copy_GBs": copy_gbs,
+        "copy8_GBs": copy8_gbs,
         "kernels": kern,
         "setup_s": setup_s,
         "device_bytes": solver.device_bytes(),

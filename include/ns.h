@@ -187,12 +187,15 @@ int ns_profile_count(ns_solver *s);
 int ns_profile_get(ns_solver *s, int k, const char **name, int64_t *launches,
                    double *total_ms);
 /* Measurement utility: copies `bytes` (rounded down to a multiple of 16)
- * between two scratch device buffers with a plain streaming copy kernel,
- * `reps` times on the solver's stream, and returns the average kernel time
- * in *avg_ms.  Used to state the achievable device copy bandwidth and to
- * calibrate hardware byte counters against a kernel of known traffic.
- * Allocates (and frees) the two buffers; NS_ENOMEM if they do not fit. */
-int ns_copy_bench(ns_solver *s, int64_t bytes, int reps, double *avg_ms);
+ * between two scratch device buffers with a plain streaming copy kernel
+ * that moves `word` bytes per lane (8 or 16; the kernels are profiled as
+ * "copy8" and "copy"), `reps` times on the solver's stream, and returns the
+ * average kernel time in *avg_ms.  Used to state the achievable device copy
+ * bandwidth and to calibrate hardware byte counters against a kernel of
+ * known traffic.  Allocates (and frees) the two buffers; NS_EINVAL for a
+ * word size other than 8 or 16, NS_ENOMEM if the buffers do not fit. */
+int ns_copy_bench(ns_solver *s, int64_t bytes, int reps, int word,
+                  double *avg_ms);
 /* Device bytes allocated by the solver. */
 int64_t ns_device_bytes(const ns_solver *s);
 /* Message describing the last error of the solver (never NULL). */

@@ -84,7 +84,7 @@ def lib() -> C.CDLL:
             "ns_profile_enable": (C.c_int, [vp, C.c_int]),
             "ns_profile_count": (C.c_int, [vp]),
             "ns_profile_get": (C.c_int, [vp, C.c_int, C.POINTER(C.c_char_p), i64p, dp]),
-            "ns_copy_bench": (C.c_int, [vp, C.c_int64, C.c_int, dp]),
+            "ns_copy_bench": (C.c_int, [vp, C.c_int64, C.c_int, C.c_int, dp]),
             "ns_device_bytes": (C.c_int64, [vp]),
             "ns_last_error": (C.c_char_p, [vp]),
             "ns_create_error": (C.c_char_p, []),
@@ -236,10 +236,12 @@ class Solver:
             out[name.value.decode()] = (n.value, ms.value)
         return out
 
-    def copy_bench(self, nbytes: int, reps: int = 10) -> float:
-        """Average time (ms) of a plain device copy of nbytes."""
+    def copy_bench(self, nbytes: int, reps: int = 10, word: int = 16) -> float:
+        """Average time (ms) of a plain device copy of nbytes moving `word`
+        (8 or 16) bytes per lane."""
         ms = C.c_double()
-        self._check(lib().ns_copy_bench(self.h, int(nbytes), int(reps), C.byref(ms)))
+        self._check(lib().ns_copy_bench(self.h, int(nbytes), int(reps), int(word),
+                                        C.byref(ms)))
         return ms.value
 
     def device_bytes(self) -> int:

@@ -815,6 +815,13 @@ __global__ __launch_bounds__(kBlock) void k_copy(const double2 *__restrict__ src
   if (t < n16) dst[t] = src[t];
 }
 
+__global__ __launch_bounds__(kBlock) void k_copy8(const double *__restrict__ src,
+                                                  double *__restrict__ dst,
+                                                  int64_t n8) {
+  const int64_t t = row_id();
+  if (t < n8) dst[t] = src[t];
+}
+
 __global__ void k_set_scalar(double *p, double v) {
   if (threadIdx.x == 0) p[0] = v;
 }
@@ -965,10 +972,16 @@ void launch_set_scalar(double *p, double v, hipStream_t s) {
   hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(64), 0, s, p, v);
 }
 
-void launch_copy(const void *src, void *dst, int64_t n16, hipStream_t s) {
-  hipLaunchKernelGGL(k_copy, grid_for(n16), dim3(kBlock), 0, s,
-                     static_cast<const double2 *>(src), static_cast<double2 *>(dst),
-                     n16);
+void launch_copy(const void *src, void *dst, int64_t n16, int word,
+                 hipStream_t s) {
+  if (word == 8)
+    hipLaunchKernelGGL(k_copy8, grid_for(2 * n16), dim3(kBlock), 0, s,
+                       static_cast<const double *>(src), static_cast<double *>(dst),
+                       2 * n16);
+  else
+    hipLaunchKernelGGL(k_copy, grid_for(n16), dim3(kBlock), 0, s,
+                       static_cast<const double2 *>(src),
+                       static_cast<double2 *>(dst), n16);
 }
 
 void launch_clear_flags(int *flags, hipStream_t s) {

@@ -90,8 +90,10 @@ void launch_dt_only(int dim, const Gas &gas, const DevGraph &g,
 void launch_slip(int dim, int64_t N, int nslip, const int32_t *idx,
                  const double *nrm, double *U, hipStream_t s);
 void launch_set_scalar(double *p, double v, hipStream_t s);
-// plain streaming copy of n16 16-byte words (calibration)
-void launch_copy(const void *src, void *dst, int64_t n16, hipStream_t s);
+// plain streaming copy of 16*n16 bytes, `word` (8 or 16) bytes per lane
+// (bandwidth and counter calibration)
+void launch_copy(const void *src, void *dst, int64_t n16, int word,
+                 hipStream_t s);
 void launch_clear_flags(int *flags, hipStream_t s);
 void launch_check_state(int dim, int64_t N, const double *U, int *flags,
                         hipStream_t s);

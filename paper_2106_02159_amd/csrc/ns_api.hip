@@ -629,8 +629,11 @@ int ns_profile_get(ns_solver *s, int k, const char **name, int64_t *launches,
   return NS_OK;
 }
 
-int ns_copy_bench(ns_solver *s, int64_t bytes, int reps, double *avg_ms) {
-  if (!s || !avg_ms || bytes < 16 || reps < 1) return NS_EINVAL;
+int ns_copy_bench(ns_solver *s, int64_t bytes, int reps, int word,
+                  double *avg_ms) {
+  if (!s || !avg_ms || bytes < 16 || reps < 1 || (word != 8 && word != 16))
+    return NS_EINVAL;
+  const char *label = word == 8 ? "copy8" : "copy";
   const int64_t n16 = bytes / 16;
   void *a = nullptr, *b = nullptr;
   hipError_t e = hipMalloc(&a, n16 * 16);
@@ -644,11 +647,11 @@ int ns_copy_bench(ns_solver *s, int64_t bytes, int reps, double *avg_ms) {
   (void)hipEventCreate(&t0);
   (void)hipEventCreate(&t1);
   e = hipMemsetAsync(a, 0, n16 * 16, s->stream);
-  ns::launch_copy(a, b, n16, s->stream);  // warm-up
+  ns::launch_copy(a, b, n16, word, s->stream);  // warm-up
   (void)hipEventRecord(t0, s->stream);
   for (int r = 0; r < reps; ++r) {
-    Profiler::before(&s->prof, "copy");
-    ns::launch_copy(r % 2 ? b : a, r % 2 ? a : b, n16, s->stream);
+    Profiler::before(&s->prof, label);
+    ns::launch_copy(r % 2 ? b : a, r % 2 ? a : b, n16, word, s->stream);
     Profiler::after(&s->prof);
   }
   (void)hipEventRecord(t1, s->stream);
