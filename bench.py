@@ -6,7 +6,9 @@ step computed on the device from the first stage's graph viscosity, three
 forward-Euler stages (graph viscosity, indicator, low-order update, bounds,
 high-order flux, two limiter passes) and the slip post-processing after
 each stage.  Workload: 2D Euler, gamma = 1.4, Q1 on a 4096x4096-node uniform
-mesh of [0,1]^2 with reflecting walls, seeded four-quadrant Riemann data, FP64.
+mesh of [0,1]^2 with reflecting walls, seeded four-quadrant Riemann data, FP64
+(--dim 3: the 3D Mach-3 shock tube on 256^3 nodes, the hyperbolic step of the
+Navier-Stokes configuration).
 Metric: DoF-updates per second per SSP-RK stage = nodes x 3 x steps / time.
 
 Prints one JSON line.  --gpus above 1 is not supported (one GPU per run).
@@ -28,7 +30,7 @@ from paper_2106_02159_amd import abi, workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes per node per launch of each kernel (FP64, slot-major ELL
+# Algorithmic bytes per node per launch of each kernel (FP64, sliced ELL
 # with int32 columns and uint8 transpose slots; every array a kernel touches
 # counted once; W = 3^d slots, nc = d + 2 components).
 def kernel_bytes(name: str, dim: int) -> float:
@@ -76,10 +78,11 @@ def source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, tag: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None if the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "hyp_stage_2d_4096_hbm_traffic.md")
+    summary of workload `tag`, or None if the kernel sources changed since it
+    was taken."""
+    path = os.path.join(ROOT, "profiles", f"hyp_stage_{tag}_hbm_traffic.md")
     try:
         txt = open(path).read()
         data = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
@@ -91,13 +94,19 @@ def measured_traffic(kernel: str):
     return k["traffic_bytes"] if k else None
 
 
-def cpu_baseline(n_sample: int, seed: int):
+def workload(dim: int, n: int, seed: int):
+    if dim == 2:
+        return W.four_quadrant_state(n, seed=seed)
+    return W.shock_tube_state(n, seed=seed)
+
+
+def cpu_baseline(dim: int, n_sample: int, seed: int):
     """The oracle, as it stands, on one SSPRK(3,3) step of the same workload
-    at n_sample x n_sample nodes (graph assembly not timed)."""
+    at n_sample nodes per direction (graph assembly not timed)."""
     from oracle import oracle as O
     O.build(force=False)
-    mesh, U = W.four_quadrant_state(n_sample, seed=seed)
-    og = O.Graph(2, mesh.n, mesh.lo, mesh.hi, mesh.periodic)
+    mesh, U = workload(dim, n_sample, seed)
+    og = O.Graph(dim, mesh.n, mesh.lo, mesh.hi, mesh.periodic, export=False)
     prm = O.params(cfl=0.5)
     U = og.slip_bc(U)
     t0 = time.perf_counter()
@@ -106,8 +115,9 @@ def cpu_baseline(n_sample: int, seed: int):
     dt = time.perf_counter() - t0
     return {"value": og.N * 3 / dt, "unit": "DoF-updates/s per SSP-RK stage",
             "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"one SSPRK3 step (time step + 3 stages) of the four-quadrant "
-                      f"workload at {n_sample}x{n_sample} nodes, seed {seed}, "
+            "sample": f"one SSPRK3 step (time step + 3 stages) of the "
+                      f"{'four-quadrant' if dim == 2 else 'Mach-3 shock-tube'} "
+                      f"workload at {n_sample}^{dim} nodes, seed {seed}, "
                       f"{dt:.2f} s"}
 
 
@@ -116,9 +126,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=4096, help="nodes per direction")
+    ap.add_argument("--dim", type=int, default=2, choices=(2, 3),
+                    help="2: four-quadrant data on 4096^2 nodes; 3: Mach-3 "
+                         "shock tube on 256^3 nodes (hyperbolic step)")
+    ap.add_argument("--n", type=int, default=0,
+                    help="nodes per direction (default 4096 in 2D, 256 in 3D)")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-sample", type=int, default=1024)
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="oracle sample, nodes per direction (default 1024 in "
+                         "2D, 96 in 3D)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -126,9 +142,10 @@ def main():
               "on a single MI355X (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
-    n = args.n
+    dim = args.dim
+    n = args.n or (4096 if dim == 2 else 256)
     t0 = time.perf_counter()
-    mesh, U = W.four_quadrant_state(n, seed=args.seed)
+    mesh, U = workload(dim, n, args.seed)
     graph = abi.Graph(mesh)
     solver = abi.Solver(graph, gamma=1.4, cfl=0.5)
     solver.set_state(U)
@@ -157,7 +174,7 @@ def main():
     N = graph.N
     stages = 3 * args.steps
     value = N * stages / elapsed
-    dim = 2
+    tag = f"{dim}d_{n}"
     # dominant kernel by summed time
     dom = max(rep.items(), key=lambda kv: kv[1][1])
     dname, (dlaunch, dms) = dom
@@ -182,14 +199,19 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"2D Euler gamma=1.4, Q1 {n}x{n} nodes on [0,1]^2, "
-                               f"reflecting walls, seeded four-quadrant Riemann data "
-                               f"(seed {args.seed}), SSPRK3 + 2-pass convex limiting, "
-                               f"CFL 0.5",
+        "config": {"workload": (
+                       f"2D Euler gamma=1.4, Q1 {n}x{n} nodes on [0,1]^2, "
+                       f"reflecting walls, seeded four-quadrant Riemann data "
+                       f"(seed {args.seed}), SSPRK3 + 2-pass convex limiting, CFL 0.5"
+                       if dim == 2 else
+                       f"3D Euler gamma=1.4 (hyperbolic step of the Navier-Stokes "
+                       f"configuration), Q1 {n}^3 nodes on [0,1]^3, reflecting walls, "
+                       f"Mach-3 shock tube with seeded 1% density noise (seed "
+                       f"{args.seed}), SSPRK3 + 2-pass convex limiting, CFL 0.5"),
                    "nodes": N, "stages_per_step": 3},
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dname) if n == 4096 else None,
+                     "traffic": measured_traffic(dname, tag),
                      "algorithmic_bytes": kb},
         "stage_algorithmic_frac": stage_frac,
         "copy_GBs": copy_gbs,
@@ -199,7 +221,8 @@ def main():
         "device_bytes": solver.device_bytes(),
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_sample, args.seed)
+        out["cpu_baseline"] = cpu_baseline(
+            dim, args.cpu_sample or (1024 if dim == 2 else 96), args.seed)
     print(json.dumps(out), flush=True)
 
 

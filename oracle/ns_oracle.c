@@ -568,6 +568,7 @@ int orc_fe_stage(const orc_graph *g, const orc_params *p, const double *U,
   {
     double vol = 0.0;
     for (long i = 0; i < N; ++i) vol += g->mi[i];
+    if (p->volume > 0.0) vol = p->volume;
     for (long i = 0; i < N; ++i) {
       const double r = p->relax * pow(g->mi[i] / vol, 1.5 / dim);
       rb[i] = (1.0 - r) * bounds[i];

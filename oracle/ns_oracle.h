@@ -48,6 +48,9 @@ typedef struct orc_params {
   int limiter;        /* ORC_LIM_* */
   int passes;         /* limiter passes for ORC_LIM_CONVEX (1 or 2) */
   double relax;       /* bound relaxation factor r0 (0 = strict bounds) */
+  double volume;      /* |Omega| in the relaxation; 0 = sum of the graph's m_i
+                         (a sub-mesh cut from a larger domain passes the
+                         larger domain's volume) */
 } orc_params;
 
 /* Optional per-stage intermediate results (any pointer may be NULL). */

@@ -36,7 +36,8 @@ def build(force: bool = True) -> str:
 class _Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("cfl", C.c_double),
                 ("indicator", C.c_int), ("limiter", C.c_int),
-                ("passes", C.c_int), ("relax", C.c_double)]
+                ("passes", C.c_int), ("relax", C.c_double),
+                ("volume", C.c_double)]
 
 
 class _Debug(C.Structure):
@@ -94,8 +95,11 @@ def num_threads() -> int:
 
 
 def params(gamma=1.4, cfl=0.5, indicator=IND_ENTROPY, limiter=LIM_CONVEX,
-           passes=2, relax=1.0) -> _Params:
-    return _Params(gamma, cfl, indicator, limiter, passes, relax)
+           passes=2, relax=1.0, volume=0.0) -> _Params:
+    """volume: |Omega| entering the bound relaxation; 0 = the mesh's own
+    (sum of m_i).  A sub-mesh window cut from a larger domain passes that
+    domain's volume so that its rows see the same relaxed bounds."""
+    return _Params(gamma, cfl, indicator, limiter, passes, relax, volume)
 
 
 def lambda_max(gamma, ui, uj, n) -> float:
@@ -120,7 +124,7 @@ def pressure(gamma, u) -> float:
 class Graph:
     """Oracle graph of a uniform Q1 mesh on a box (Gauss-quadrature assembly)."""
 
-    def __init__(self, dim, n, lo, hi, periodic):
+    def __init__(self, dim, n, lo, hi, periodic, export=True):
         L = lib()
         self.dim = dim
         nn = (C.c_long * 3)(*(list(n) + [1] * (3 - len(n))))
@@ -136,7 +140,8 @@ class Graph:
         self.N = L.orc_graph_N(h)
         self.nnz = L.orc_graph_nnz(h)
         self.nc = dim + 2
-        self._export()
+        if export:  # numpy copies of the graph (tests of the graph itself)
+            self._export()
 
     def _export(self):
         N, nnz, dim = self.N, self.nnz, self.dim

@@ -31,14 +31,22 @@ def rel_err(a, b, axis=None):
     return num / np.where(den > 0, den, 1.0)
 
 
-def state_rel_err(a, b):
-    """Per-component relative max-norm error of two (nc, N) states; momentum
-    components share one scale (the largest momentum component)."""
-    a = np.asarray(a)
+def state_scale(b):
+    """Per-component max norm of an (nc, N) state; the momentum components
+    share one scale (the largest of them)."""
     b = np.asarray(b)
-    nc = b.shape[0]
-    dim = nc - 2
+    dim = b.shape[0] - 2
     scale = np.abs(b).max(axis=1)
     scale[1:1 + dim] = scale[1:1 + dim].max()
-    scale = np.where(scale > 0, scale, 1.0)
+    return np.where(scale > 0, scale, 1.0)
+
+
+def state_rel_err(a, b, scale=None):
+    """Per-component relative max-norm error of two (nc, N) states, divided
+    by state_scale(b), or by `scale` (e.g. the norm of the whole field when
+    a and b are a sample of it)."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    if scale is None:
+        scale = state_scale(b)
     return np.abs(a - b).max(axis=1) / scale
