@@ -104,6 +104,48 @@ int orc_ssprk3_step(const orc_graph *g, const orc_params *p, const double *U,
 int orc_high_order_direct(const orc_graph *g, const orc_params *p,
                           const double *U, double tau, double *UH);
 
+/* ---- parabolic sub-step and Strang composition (ns_oracle_parabolic.c) --
+ * Viscous and thermal data: sigma(v) = 2 mu eps(v) + (lambda - 2/3 mu)
+ * div(v) I; the heat operator has the coefficient kappa / cv.  Walls of
+ * non-periodic directions are no-slip for the velocity (all components of
+ * a wall node prescribed to 0) and homogeneous Neumann for the internal
+ * energy. */
+typedef struct orc_visc {
+  double mu, lambda, kappa, cv;
+  double cg_rtol;     /* stop when ||r||_2 <= cg_rtol ||b||_2 */
+  int cg_maxit;
+  int fct;            /* 0: limit only if min e^H <= 0; 1: always limit */
+} orc_visc;
+
+typedef struct orc_par_info {
+  int it_v, it_e, it_l;  /* CG iterations (velocity, energy, low order);
+                            -1 = not converged */
+  int fct;               /* 1 if the limited update was used */
+  double min_eH;         /* min of the high-order internal energy */
+  double min_e;          /* min of the final internal energy */
+} orc_par_info;
+
+/* Y = A V with a(v, phi_i e_k) (no boundary conditions); V, Y: dim*N */
+void orc_stress_apply(const orc_graph *g, const orc_visc *vp, const double *V,
+                      double *Y);
+/* Y = B e with b(e, phi_i) = kappa/cv int grad e . grad phi_i */
+void orc_heat_apply(const orc_graph *g, const orc_visc *vp, const double *e,
+                    double *Y);
+/* B_ij = b(phi_j, phi_i) on the CSR pattern (nnz) */
+void orc_heat_matrix(const orc_graph *g, const orc_visc *vp, double *B);
+/* K_i = (1/m_i) int sigma(v) : eps(v) phi_i */
+void orc_dissipation(const orc_graph *g, const orc_visc *vp, const double *V,
+                     double *K);
+/* One parabolic step over dt (the Strang composition passes 2 tau).
+ * Returns 0, or -1 if a CG solve did not converge. */
+int orc_parabolic_step(const orc_graph *g, const orc_visc *vp, const double *U,
+                       double dt, double *Uout, orc_par_info *info);
+/* H(tau) P(2 tau) H(tau); returns a bit mask: 1 stage CFL violated, 2 CG
+ * did not converge. */
+int orc_strang_step(const orc_graph *g, const orc_params *p, const orc_visc *vp,
+                    const double *U, double tau, double *Uout,
+                    orc_par_info *info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,7 +17,7 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "ns_oracle.c")
+SRCS = [os.path.join(HERE, "ns_oracle.c"), os.path.join(HERE, "ns_oracle_parabolic.c")]
 LIB = os.path.join(HERE, "libns_oracle.so")
 
 IND_ENTROPY, IND_ONE, IND_ZERO = 0, 1, 2
@@ -28,7 +28,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle shared library (plain C, gcc)."""
     if force or not os.path.exists(LIB):
         cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
-               "-fno-fast-math", "-Wall", "-o", LIB, SRC, "-lm"]
+               "-fno-fast-math", "-Wall", "-o", LIB] + SRCS + ["-lm"]
         subprocess.check_call(cmd)
     return LIB
 
@@ -38,6 +38,17 @@ class _Params(C.Structure):
                 ("indicator", C.c_int), ("limiter", C.c_int),
                 ("passes", C.c_int), ("relax", C.c_double),
                 ("volume", C.c_double)]
+
+
+class _Visc(C.Structure):
+    _fields_ = [("mu", C.c_double), ("lam", C.c_double), ("kappa", C.c_double),
+                ("cv", C.c_double), ("cg_rtol", C.c_double), ("cg_maxit", C.c_int),
+                ("fct", C.c_int)]
+
+
+class ParInfo(C.Structure):
+    _fields_ = [("it_v", C.c_int), ("it_e", C.c_int), ("it_l", C.c_int),
+                ("fct", C.c_int), ("min_eH", C.c_double), ("min_e", C.c_double)]
 
 
 class _Debug(C.Structure):
@@ -81,6 +92,14 @@ def lib():
                                       C.c_double, dp]
         L.orc_high_order_direct.argtypes = [C.c_void_p, C.POINTER(_Params), dp,
                                             C.c_double, dp]
+        vpp = C.POINTER(_Visc)
+        for name in ("orc_stress_apply", "orc_heat_apply", "orc_dissipation"):
+            getattr(L, name).argtypes = [C.c_void_p, vpp, dp, dp]
+        L.orc_heat_matrix.argtypes = [C.c_void_p, vpp, dp]
+        L.orc_parabolic_step.argtypes = [C.c_void_p, vpp, dp, C.c_double, dp,
+                                         C.POINTER(ParInfo)]
+        L.orc_strang_step.argtypes = [C.c_void_p, C.POINTER(_Params), vpp, dp,
+                                      C.c_double, dp, C.POINTER(ParInfo)]
         _lib = L
     return _lib
 
@@ -100,6 +119,14 @@ def params(gamma=1.4, cfl=0.5, indicator=IND_ENTROPY, limiter=LIM_CONVEX,
     (sum of m_i).  A sub-mesh window cut from a larger domain passes that
     domain's volume so that its rows see the same relaxed bounds."""
     return _Params(gamma, cfl, indicator, limiter, passes, relax, volume)
+
+
+def visc(mu=1e-4, lam=0.0, kappa=1.4e-4, cv=2.5, cg_rtol=1e-10, cg_maxit=500,
+         fct=0) -> _Visc:
+    """Viscous data of the parabolic step (stress coefficients mu, lambda,
+    heat coefficient kappa / cv), the CG tolerance and the limiting mode
+    (0: only when the high-order internal energy is not positive, 1: always)."""
+    return _Visc(mu, lam, kappa, cv, cg_rtol, cg_maxit, fct)
 
 
 def lambda_max(gamma, ui, uj, n) -> float:
@@ -208,6 +235,46 @@ class Graph:
         out = np.empty_like(U)
         lib().orc_high_order_direct(self.h, C.byref(prm), _dp(U), tau, _dp(out))
         return out
+
+    # -- parabolic sub-step ------------------------------------------------
+    def stress_apply(self, vp, V):
+        V = np.ascontiguousarray(V, np.float64)
+        Y = np.empty_like(V)
+        lib().orc_stress_apply(self.h, C.byref(vp), _dp(V), _dp(Y))
+        return Y
+
+    def heat_apply(self, vp, e):
+        e = np.ascontiguousarray(e, np.float64)
+        Y = np.empty_like(e)
+        lib().orc_heat_apply(self.h, C.byref(vp), _dp(e), _dp(Y))
+        return Y
+
+    def heat_matrix(self, vp):
+        B = np.empty(self.nnz)
+        lib().orc_heat_matrix(self.h, C.byref(vp), _dp(B))
+        return B
+
+    def dissipation(self, vp, V):
+        V = np.ascontiguousarray(V, np.float64)
+        K = np.empty(self.N)
+        lib().orc_dissipation(self.h, C.byref(vp), _dp(V), _dp(K))
+        return K
+
+    def parabolic_step(self, vp, U, dt):
+        U = np.ascontiguousarray(U, np.float64)
+        out = np.empty_like(U)
+        info = ParInfo()
+        st = lib().orc_parabolic_step(self.h, C.byref(vp), _dp(U), dt, _dp(out),
+                                      C.byref(info))
+        return out, st, info
+
+    def strang_step(self, prm, vp, U, tau):
+        U = np.ascontiguousarray(U, np.float64)
+        out = np.empty_like(U)
+        info = ParInfo()
+        st = lib().orc_strang_step(self.h, C.byref(prm), C.byref(vp), _dp(U), tau,
+                                   _dp(out), C.byref(info))
+        return out, st, info
 
     # -- helpers for tests -------------------------------------------------
     def rows(self):
