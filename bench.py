@@ -100,9 +100,10 @@ def workload(dim: int, n: int, seed: int):
     return W.shock_tube_state(n, seed=seed)
 
 
-def cpu_baseline(dim: int, n_sample: int, seed: int):
-    """The oracle, as it stands, on one SSPRK(3,3) step of the same workload
-    at n_sample nodes per direction (graph assembly not timed)."""
+def cpu_baseline(dim: int, n_sample: int, seed: int, ns: bool = False):
+    """The oracle, as it stands, on one SSPRK(3,3) step (one Strang step with
+    `ns`) of the same workload at n_sample nodes per direction (graph
+    assembly not timed)."""
     from oracle import oracle as O
     O.build(force=False)
     mesh, U = workload(dim, n_sample, seed)
@@ -111,11 +112,19 @@ def cpu_baseline(dim: int, n_sample: int, seed: int):
     U = og.slip_bc(U)
     t0 = time.perf_counter()
     tau = og.compute_dt(prm, U)
-    og.ssprk3_step(prm, U, tau)
+    if ns:
+        og.strang_step(prm, O.visc(mu=1e-4, lam=0.0, kappa=1.4e-4, cv=2.5,
+                                   cg_rtol=1e-10), U, tau)
+    else:
+        og.ssprk3_step(prm, U, tau)
     dt = time.perf_counter() - t0
-    return {"value": og.N * 3 / dt, "unit": "DoF-updates/s per SSP-RK stage",
+    stages = 6 if ns else 3
+    what = ("one Strang step (time step + 6 stages + parabolic step; the "
+            "oracle's parabolic part is serial)" if ns else
+            "one SSPRK3 step (time step + 3 stages)")
+    return {"value": og.N * stages / dt, "unit": "DoF-updates/s per SSP-RK stage",
             "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"one SSPRK3 step (time step + 3 stages) of the "
+            "sample": f"{what} of the "
                       f"{'four-quadrant' if dim == 2 else 'Mach-3 shock-tube'} "
                       f"workload at {n_sample}^{dim} nodes, seed {seed}, "
                       f"{dt:.2f} s"}
@@ -131,6 +140,10 @@ def main():
                          "shock tube on 256^3 nodes (hyperbolic step)")
     ap.add_argument("--n", type=int, default=0,
                     help="nodes per direction (default 4096 in 2D, 256 in 3D)")
+    ap.add_argument("--ns", action="store_true",
+                    help="Navier-Stokes: Strang steps (hyperbolic tau, parabolic "
+                         "2 tau, hyperbolic tau) with mu = 1e-4, lambda = 0, "
+                         "kappa = 1.4e-4, cv = 1/(gamma-1), CG rtol 1e-10")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="oracle sample, nodes per direction (default 1024 in "
@@ -142,7 +155,7 @@ def main():
               "on a single MI355X (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
-    dim = args.dim
+    dim = 3 if args.ns else args.dim
     n = args.n or (4096 if dim == 2 else 256)
     t0 = time.perf_counter()
     mesh, U = workload(dim, n, args.seed)
@@ -150,15 +163,24 @@ def main():
     solver = abi.Solver(graph, gamma=1.4, cfl=0.5)
     solver.set_state(U)
     del U
+    if args.ns:
+        solver.set_viscous(mu=1e-4, lam=0.0, kappa=1.4e-4, cv=1.0 / 0.4, cg_rtol=1e-10)
+        advance = solver.step_strang_cfl
+    else:
+        advance = solver.step_cfl
     setup_s = time.perf_counter() - t0
     for _ in range(args.warmup):
-        solver.step_cfl()
+        advance()
     solver.sync()
     solver.profile(True)
     solver.sync()
+    cg_iters = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        solver.step_cfl()
+        advance()
+        if args.ns:
+            info = solver.parabolic_info()
+            cg_iters.append((info.it_v, info.it_e, info.it_l, info.fct))
     solver.sync()
     elapsed = time.perf_counter() - t0
     rep = solver.profile_report()
@@ -172,7 +194,8 @@ def main():
     copy8_gbs = 2 * copy_bytes / (copy8_ms * 1e-3) / 1e9
 
     N = graph.N
-    stages = 3 * args.steps
+    stages_per_step = 6 if args.ns else 3
+    stages = stages_per_step * args.steps
     value = N * stages / elapsed
     tag = f"{dim}d_{n}"
     # dominant kernel by summed time
@@ -200,6 +223,12 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": (
+                       f"3D Navier-Stokes gamma=1.4, Q1 {n}^3 nodes on [0,1]^3, "
+                       f"mu=1e-4, lambda=0, kappa=1.4e-4, cv=2.5, Mach-3 shock tube "
+                       f"with seeded 1% density noise (seed {args.seed}); Strang step "
+                       f"= SSPRK3(tau) + parabolic CN/CG(2 tau, Jacobi, rtol 1e-10; "
+                       f"no-slip, insulated walls) + SSPRK3(tau), CFL 0.5"
+                       if args.ns else
                        f"2D Euler gamma=1.4, Q1 {n}x{n} nodes on [0,1]^2, "
                        f"reflecting walls, seeded four-quadrant Riemann data "
                        f"(seed {args.seed}), SSPRK3 + 2-pass convex limiting, CFL 0.5"
@@ -208,7 +237,7 @@ def main():
                        f"configuration), Q1 {n}^3 nodes on [0,1]^3, reflecting walls, "
                        f"Mach-3 shock tube with seeded 1% density noise (seed "
                        f"{args.seed}), SSPRK3 + 2-pass convex limiting, CFL 0.5"),
-                   "nodes": N, "stages_per_step": 3},
+                   "nodes": N, "stages_per_step": stages_per_step},
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dname, tag),
@@ -220,9 +249,15 @@ def main():
         "setup_s": setup_s,
         "device_bytes": solver.device_bytes(),
     }
+    if args.ns:
+        out["cg_iterations"] = {"velocity": [c[0] for c in cg_iters],
+                                "energy": [c[1] for c in cg_iters],
+                                "low_order": [c[2] for c in cg_iters],
+                                "limited_steps": sum(c[3] for c in cg_iters)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(
-            dim, args.cpu_sample or (1024 if dim == 2 else 96), args.seed)
+            dim, args.cpu_sample or (1024 if dim == 2 else (64 if args.ns else 96)),
+            args.seed, ns=args.ns)
     print(json.dumps(out), flush=True)
 
 

@@ -8,7 +8,9 @@
  * 3D hexahedra), ideal-gas Euler flux, graph viscosity from a guaranteed
  * maximum wave speed, low-order update, local bounds, high-order flux with
  * the approximate inverse mass matrix, convex limiting (Sec. 3, Algorithm 1),
- * SSPRK(3,3) with slip post-processing after every stage (Sec. 4.1-4.2).
+ * SSPRK(3,3) with slip post-processing after every stage (Sec. 4.1-4.2);
+ * the parabolic (viscous) sub-step with matrix-free conjugate gradients and
+ * the Strang composition of the Navier-Stokes step (Sec. 2, Sec. 5).
  *
  * Conventions shared by every call:
  *   - Status codes: NS_OK (0) or a negative NS_E* value.  No call throws.
@@ -41,6 +43,8 @@ extern "C" {
 #define NS_ECFL (-5)            /* dt above the stage CFL limit (c_cfl = 1)  */
 #define NS_EBOUNDS (-6)         /* a stage produced an inadmissible state    */
 #define NS_ESTATE (-7)          /* no state has been set                     */
+#define NS_ECG (-8)             /* a CG solve of the parabolic step did not
+                                   converge within its iteration limit      */
 
 /* ---- options ------------------------------------------------------------ */
 /* Entropy-production indicator alpha_i of Sec. 3.2 (d^H_ij = (alpha_i +
@@ -149,6 +153,69 @@ int ns_step(ns_solver *s, double dt);
  * first stage from that stage's own d_ij and reused by stages 2 and 3
  * (Sec. 3.1).  The dt used is returned in *dt (may be NULL). */
 int ns_step_cfl(ns_solver *s, double *dt);
+
+/* ---- parabolic sub-step and Strang composition (Sec. 5) ----------------
+ * Viscous and thermal data of the Navier-Stokes system: the viscous stress
+ * sigma(v) = 2 mu eps(v) + (lambda - 2/3 mu) div(v) I, eps(v) the symmetric
+ * velocity gradient, and the heat flux -(kappa/cv) grad e.  In the parabolic
+ * step every wall node (non-periodic face) is no-slip for the velocity (its
+ * velocity is prescribed to 0 at both time levels) and the internal energy
+ * satisfies homogeneous Neumann conditions (thermally insulated walls).
+ * The two linear systems are solved by conjugate gradients preconditioned
+ * with the diagonal of the operator, started from the values at t^n and
+ * stopped when ||r||_2 <= cg_rtol ||b||_2 (unpreconditioned residual). */
+enum { NS_FCT_AUTO = 0, NS_FCT_ALWAYS = 1 };
+typedef struct ns_viscous {
+  double mu;       /* shear viscosity, >= 0                                 */
+  double lambda;   /* bulk viscosity, >= 0                                  */
+  double kappa;    /* thermal conductivity, >= 0                            */
+  double cv;       /* heat capacity at constant volume, > 0                 */
+  double cg_rtol;  /* relative residual of both CG solves, in (0, 1)        */
+  int cg_maxit;    /* iteration limit of each CG solve, >= 1                */
+  int fct;         /* NS_FCT_AUTO: limit the internal energy only when the
+                      Crank-Nicolson value is not positive somewhere;
+                      NS_FCT_ALWAYS: always (tests)                         */
+} ns_viscous;
+
+/* Enables the parabolic step: validates the data, builds the Q1 element
+ * matrices of the stress and heat operators and allocates the CG vectors
+ * (about 7 dim N + 8 N doubles) and a fourth state buffer that keeps
+ * Strang steps transactional.  May be called again to change the data.
+ * NS_EINVAL for a NULL pointer or data out of range; NS_ENOMEM. */
+int ns_set_viscous(ns_solver *s, const ns_viscous *v);
+
+/* One parabolic step of size dt from the current state (the
+ * parabolic-step algorithm of the appendix): density unchanged; velocity
+ * by Crank-Nicolson, eq. mt_parabolic_discrete (f = 0) and
+ * vel_parabolic_discrete; K_i of eq. def_Ki_nplusone from V^{n+1/2};
+ * internal energy by Crank-Nicolson, eq. high_int_energy_CN; if the
+ * resulting internal energy is not positive somewhere (or with
+ * NS_FCT_ALWAYS), the low-order backward-Euler energy with source
+ * dt m_i K_i and flux-corrected limiting of A_ij (eq. Aij_for_internal_energy)
+ * towards the local bounds [min_j e^L_j, max_j e^L_j]; total energy by eq.
+ * energy_parabolic_discrete.  Transactional.  NS_ESTATE without
+ * ns_set_viscous or a state; NS_ECG if a CG solve did not converge;
+ * NS_EBOUNDS if the result is not admissible. */
+int ns_step_parabolic(ns_solver *s, double dt);
+
+/* One Strang step (eq. continuous_Strang): SSPRK(3,3) step with tau,
+ * parabolic step with 2 tau, SSPRK(3,3) step with tau; time advances by
+ * 2 tau.  The second hyperbolic step reuses tau and checks the stage CFL
+ * limit in all its stages.  Transactional: on any error the state at the
+ * start is restored. */
+int ns_step_strang(ns_solver *s, double tau);
+/* Same, tau computed on the device in the first stage of the first
+ * hyperbolic step (returned in *tau, may be NULL). */
+int ns_step_strang_cfl(ns_solver *s, double *tau);
+
+typedef struct ns_par_info {
+  int it_v, it_e, it_l;  /* CG iterations: velocity, energy, low-order energy
+                            (0 when the limiting was not needed)            */
+  int fct;               /* 1 if the limited internal energy was used       */
+  double min_eH;         /* minimum of the Crank-Nicolson internal energy   */
+} ns_par_info;
+/* Diagnostics of the last parabolic step. */
+int ns_parabolic_info(ns_solver *s, ns_par_info *out);
 
 /* Test access: one forward-Euler stage of size dt from the current state,
  * without SSP combination or post-processing; the result and every

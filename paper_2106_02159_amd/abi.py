@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(HERE, "libns.so")
 
 # status codes (ns.h)
 NS_OK, NS_EINVAL, NS_ENOMEM, NS_EHIP = 0, -1, -2, -3
-NS_ENOTADMISSIBLE, NS_ECFL, NS_EBOUNDS, NS_ESTATE = -4, -5, -6, -7
+NS_ENOTADMISSIBLE, NS_ECFL, NS_EBOUNDS, NS_ESTATE, NS_ECG = -4, -5, -6, -7, -8
+FCT_AUTO, FCT_ALWAYS = 0, 1
 IND_ENTROPY, IND_ONE, IND_ZERO = 0, 1, 2
 LIM_CONVEX, LIM_LOW, LIM_HIGH = 0, 1, 2
 ON_DEVICE, NO_PROJECT = 1, 2
@@ -31,7 +32,8 @@ EXPORTED = [
     "ns_sync", "ns_stream", "ns_profile_enable", "ns_profile_count",
     "ns_profile_get", "ns_copy_bench", "ns_device_bytes", "ns_last_error",
     "ns_create_error",
-    "ns_strerror",
+    "ns_strerror", "ns_set_viscous", "ns_step_parabolic", "ns_step_strang",
+    "ns_step_strang_cfl", "ns_parabolic_info",
 ]
 
 
@@ -89,6 +91,11 @@ def lib() -> C.CDLL:
             "ns_last_error": (C.c_char_p, [vp]),
             "ns_create_error": (C.c_char_p, []),
             "ns_strerror": (C.c_char_p, [C.c_int]),
+            "ns_set_viscous": (C.c_int, [vp, C.POINTER(Viscous)]),
+            "ns_step_parabolic": (C.c_int, [vp, C.c_double]),
+            "ns_step_strang": (C.c_int, [vp, C.c_double]),
+            "ns_step_strang_cfl": (C.c_int, [vp, dp]),
+            "ns_parabolic_info": (C.c_int, [vp, C.POINTER(ParInfo)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -154,6 +161,17 @@ class Graph:
             pass
 
 
+class Viscous(C.Structure):
+    _fields_ = [("mu", C.c_double), ("lam", C.c_double), ("kappa", C.c_double),
+                ("cv", C.c_double), ("cg_rtol", C.c_double), ("cg_maxit", C.c_int),
+                ("fct", C.c_int)]
+
+
+class ParInfo(C.Structure):
+    _fields_ = [("it_v", C.c_int), ("it_e", C.c_int), ("it_l", C.c_int),
+                ("fct", C.c_int), ("min_eH", C.c_double)]
+
+
 class Solver:
     """ns_solver_create and the per-solver calls."""
 
@@ -202,6 +220,31 @@ class Solver:
     def step_status(self, dt: float) -> int:
         """ns_step returning the raw status instead of raising."""
         return lib().ns_step(self.h, float(dt))
+
+    # -- parabolic sub-step and Strang composition --------------------------
+    def set_viscous(self, mu=1e-4, lam=0.0, kappa=1.4e-4, cv=2.5, cg_rtol=1e-10,
+                    cg_maxit=500, fct=FCT_AUTO):
+        self.vprm = Viscous(mu, lam, kappa, cv, cg_rtol, cg_maxit, fct)
+        self._check(lib().ns_set_viscous(self.h, C.byref(self.vprm)))
+
+    def step_parabolic(self, dt: float):
+        return self._check(lib().ns_step_parabolic(self.h, float(dt)))
+
+    def step_parabolic_status(self, dt: float) -> int:
+        return lib().ns_step_parabolic(self.h, float(dt))
+
+    def step_strang(self, tau: float):
+        return self._check(lib().ns_step_strang(self.h, float(tau)))
+
+    def step_strang_cfl(self) -> float:
+        tau = C.c_double()
+        self._check(lib().ns_step_strang_cfl(self.h, C.byref(tau)))
+        return tau.value
+
+    def parabolic_info(self) -> ParInfo:
+        info = ParInfo()
+        self._check(lib().ns_parabolic_info(self.h, C.byref(info)))
+        return info
 
     def fe_stage(self, dt: float) -> int:
         return lib().ns_fe_stage(self.h, float(dt))

@@ -5,6 +5,7 @@
 // SPPRK33) with a device-resident time step, and per-kernel event timing.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -14,8 +15,10 @@
 #include <vector>
 
 #include "../../include/ns.h"
+#include "element.hpp"
 #include "graph.hpp"
 #include "hyp_kernels.hpp"
+#include "par_kernels.hpp"
 
 struct ns_graph {
   ns::MeshGraph mg;
@@ -129,6 +132,15 @@ struct ns_solver {
   int *hflags = nullptr;   // pinned
   double *htau = nullptr;  // pinned
   int last_out = 1;        // buffer holding the last stage output
+  // parabolic step (allocated by ns_set_viscous)
+  bool viscous = false;
+  ns_viscous vprm{};
+  ns::ParBufs pb{};
+  double *ptab = nullptr;
+  double *backup = nullptr;       // nc*N: state at the start of a Strang step
+  ns::CGState *hcg = nullptr;     // pinned
+  double *hscal = nullptr;        // pinned
+  ns_par_info pinfo{};
   std::string err = "no error";
   Profiler prof;
 
@@ -174,6 +186,8 @@ void release(ns_solver *s) {
   s->allocs.clear();
   if (s->hflags) (void)hipHostFree(s->hflags);
   if (s->htau) (void)hipHostFree(s->htau);
+  if (s->hcg) (void)hipHostFree(s->hcg);
+  if (s->hscal) (void)hipHostFree(s->hscal);
   if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
 }
 
@@ -242,6 +256,130 @@ int ssprk3(ns_solver *s, double dt, bool auto_dt, double *dt_out) {
   return NS_OK;
 }
 
+ns::ParGrid par_grid(const ns_solver *s) {
+  ns::ParGrid g;
+  g.N = s->N;
+  for (int d = 0; d < 3; ++d) {
+    g.n[d] = s->mg.n[d];
+    g.per[d] = d < s->dim ? s->mg.periodic[d] : 0;
+  }
+  return g;
+}
+
+// Conjugate gradients on the device: start, then batches of iterations
+// with one status readback per batch.
+int run_cg(ns_solver *s, int ncomp, double cdt, const char *label, int *iters) {
+  const ns::ParGrid g = par_grid(s);
+  Profiler::before(&s->prof, label);
+  ns::par_cg_start(s->dim, ncomp, g, s->pb, cdt, s->vprm.cg_rtol, s->vprm.cg_maxit,
+                   s->stream);
+  Profiler::after(&s->prof);
+  int launched = 0, batch = 2;
+  for (;;) {
+    Profiler::before(&s->prof, label);
+    ns::par_cg_iterate(s->dim, ncomp, g, s->pb, cdt, batch, s->stream);
+    Profiler::after(&s->prof);
+    launched += batch;
+    hipError_t e = hipMemcpyAsync(s->hcg, s->pb.cg, sizeof(ns::CGState),
+                                  hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return s->hipfail(e, "parabolic CG");
+    if (s->hcg->done || launched > s->vprm.cg_maxit) break;
+    batch = std::min(2 * batch, 16);
+  }
+  *iters = s->hcg->it;
+  const bool ok = s->hcg->bb == 0.0 || s->hcg->rr <= s->hcg->rtol2 * s->hcg->bb;
+  if (!ok) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s: CG did not converge in %d iterations (|r|/|b| = %.3g)",
+             label, s->hcg->it, std::sqrt(s->hcg->rr / s->hcg->bb));
+    return s->fail(NS_ECG, buf);
+  }
+  return NS_OK;
+}
+
+// Parabolic step of size dt from S[in] into S[out] (the parabolic-step
+// algorithm of the appendix); S[in] is not modified.
+int par_step(ns_solver *s, double dt, int in, int out) {
+  const ns::ParGrid g = par_grid(s);
+  const ns::ParBufs &B = s->pb;
+  const double *U = s->S[in];
+  double *O = s->S[out];
+  const int dim = s->dim;
+  s->pinfo = ns_par_info{};
+  ns::launch_clear_flags(s->flags, s->stream);
+  Profiler::before(&s->prof, "par_prep");
+  ns::par_prep(dim, g, B, U, dt, s->stream);
+  Profiler::after(&s->prof);
+  // Step 1: velocity (Crank-Nicolson, no-slip rows eliminated)
+  int rc = run_cg(s, dim, 0.5 * dt, "cg_velocity", &s->pinfo.it_v);
+  if (rc != NS_OK) return rc;
+  Profiler::before(&s->prof, "par_velocity");
+  ns::par_velocity_done(dim, g, B, U, O, s->vprm.mu, s->vprm.lambda, s->stream);
+  Profiler::after(&s->prof);
+  // Step 2: internal energy (Crank-Nicolson, source dt/2 m K)
+  Profiler::before(&s->prof, "par_energy_setup");
+  ns::par_energy_setup(dim, g, B, 0.5 * dt, 0.5 * dt, s->stream);
+  Profiler::after(&s->prof);
+  rc = run_cg(s, 1, 0.5 * dt, "cg_energy", &s->pinfo.it_e);
+  if (rc != NS_OK) return rc;
+  Profiler::before(&s->prof, "par_energy_high");
+  ns::par_energy_high(dim, g, B, s->stream);
+  Profiler::after(&s->prof);
+  hipError_t e = hipMemcpyAsync(s->hscal, B.scal, sizeof(double), hipMemcpyDeviceToHost,
+                                s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return s->hipfail(e, "parabolic step");
+  s->pinfo.min_eH = s->hscal[0];
+  // Step 3: limiting when the internal energy is not positive (or forced)
+  if (s->vprm.fct == NS_FCT_ALWAYS || !(s->hscal[0] > 0.0)) {
+    s->pinfo.fct = 1;
+    Profiler::before(&s->prof, "par_energy_setup");
+    ns::par_energy_setup(dim, g, B, dt, dt, s->stream);
+    Profiler::after(&s->prof);
+    rc = run_cg(s, 1, dt, "cg_low", &s->pinfo.it_l);
+    if (rc != NS_OK) return rc;
+    Profiler::before(&s->prof, "par_fct");
+    ns::par_fct(dim, g, B, dt, s->stream);
+    Profiler::after(&s->prof);
+  }
+  Profiler::before(&s->prof, "par_finish");
+  ns::par_finish(dim, g, B, U, B.eH, O, s->stream);
+  Profiler::after(&s->prof);
+  rc = read_flags(s);
+  if (rc != NS_OK) return rc;
+  if (s->hflags[1])
+    return s->fail(NS_EBOUNDS, "the parabolic step produced a non-positive internal energy");
+  return NS_OK;
+}
+
+int strang(ns_solver *s, double tau, bool auto_dt, double *tau_out) {
+  if (!s->has_state) return s->fail(NS_ESTATE, "no state set");
+  if (!s->viscous) return s->fail(NS_ESTATE, "ns_set_viscous has not been called");
+  const size_t bytes = (size_t)s->nc * s->N * sizeof(double);
+  hipError_t e = hipMemcpyAsync(s->backup, s->S[s->cur], bytes, hipMemcpyDeviceToDevice,
+                                s->stream);
+  if (e != hipSuccess) return s->hipfail(e, "state backup");
+  double t = tau;
+  int rc = ssprk3(s, tau, auto_dt, &t);
+  if (rc != NS_OK) return rc;  // the hyperbolic step left the state unchanged
+  if (tau_out) *tau_out = t;
+  const int o = others(s->cur, 0);
+  rc = par_step(s, 2.0 * t, s->cur, o);
+  if (rc == NS_OK) {
+    s->cur = o;
+    rc = ssprk3(s, t, false, nullptr);
+  }
+  if (rc != NS_OK) {
+    e = hipMemcpyAsync(s->S[s->cur], s->backup, bytes, hipMemcpyDeviceToDevice,
+                       s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return s->hipfail(e, "state restore");
+  }
+  return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -256,6 +394,7 @@ const char *ns_strerror(int code) {
     case NS_ECFL: return "time step above the CFL limit";
     case NS_EBOUNDS: return "inadmissible state produced";
     case NS_ESTATE: return "no state set";
+    case NS_ECG: return "CG did not converge";
     default: return "unknown status";
   }
 }
@@ -548,6 +687,83 @@ int ns_step(ns_solver *s, double dt) {
 int ns_step_cfl(ns_solver *s, double *dt) {
   if (!s) return NS_EINVAL;
   return ssprk3(s, 0.0, true, dt);
+}
+
+int ns_set_viscous(ns_solver *s, const ns_viscous *v) {
+  if (!s || !v) return NS_EINVAL;
+  const double vals[] = {v->mu, v->lambda, v->kappa, v->cv, v->cg_rtol};
+  for (double x : vals)
+    if (!std::isfinite(x)) return s->fail(NS_EINVAL, "viscous data must be finite");
+  if (!(v->mu >= 0.0) || !(v->lambda >= 0.0) || !(v->kappa >= 0.0) || !(v->cv > 0.0) ||
+      !(v->cg_rtol > 0.0 && v->cg_rtol < 1.0) || v->cg_maxit < 1 ||
+      (v->fct != NS_FCT_AUTO && v->fct != NS_FCT_ALWAYS))
+    return s->fail(NS_EINVAL, "viscous data out of range (need mu, lambda, kappa >= 0, "
+                              "cv > 0, 0 < cg_rtol < 1, cg_maxit >= 1, fct 0 or 1)");
+  ns::Q1Tables t;
+  ns::build_q1_tables(s->dim, s->mg.h, v->mu, v->lambda, v->kappa / v->cv, &t);
+  const std::vector<double> tab = t.packed();
+  hipError_t e = hipSuccess;
+  if (!s->ptab) {
+    const int64_t N = s->N, dN = (int64_t)s->dim * N;
+    const int64_t nblocks = (N + ns::kParBlock - 1) / ns::kParBlock;
+    ns::ParBufs &B = s->pb;
+    double **dvecs[] = {&B.Vn, &B.x, &B.r, &B.p, &B.q, &B.b, &B.diag};
+    double **nvecs[] = {&B.rm, &B.en, &B.K, &B.eH, &B.eL, &B.w, &B.Rp, &B.Rm};
+    for (double **d : dvecs)
+      if (e == hipSuccess) e = s->alloc(d, dN);
+    for (double **d : nvecs)
+      if (e == hipSuccess) e = s->alloc(d, N);
+    if (e == hipSuccess) e = s->alloc(&B.partial, 3 * nblocks);
+    if (e == hipSuccess) e = s->alloc(&B.cg, 1);
+    if (e == hipSuccess) e = s->alloc(&B.scal, 4);
+    if (e == hipSuccess) e = s->alloc(&s->ptab, tab.size());
+    if (e == hipSuccess) e = s->alloc(&s->backup, (size_t)s->nc * N);
+    if (e == hipSuccess)
+      e = hipHostMalloc(reinterpret_cast<void **>(&s->hcg), sizeof(ns::CGState));
+    if (e == hipSuccess)
+      e = hipHostMalloc(reinterpret_cast<void **>(&s->hscal), 4 * sizeof(double));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return s->fail(NS_ENOMEM, std::string("parabolic buffers: ") + hipGetErrorString(e));
+    }
+    B.tab = s->ptab;
+    B.mi = s->mi;
+    B.fixed = s->wall;
+    B.flags = s->flags;
+  }
+  e = hipMemcpy(s->ptab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return s->hipfail(e, "element table upload");
+  s->vprm = *v;
+  s->viscous = true;
+  return NS_OK;
+}
+
+int ns_step_parabolic(ns_solver *s, double dt) {
+  if (!s) return NS_EINVAL;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return s->fail(NS_EINVAL, "dt must be positive");
+  if (!s->has_state) return s->fail(NS_ESTATE, "no state set");
+  if (!s->viscous) return s->fail(NS_ESTATE, "ns_set_viscous has not been called");
+  const int o = others(s->cur, 0);
+  const int rc = par_step(s, dt, s->cur, o);
+  if (rc == NS_OK) s->cur = o;
+  return rc;
+}
+
+int ns_step_strang(ns_solver *s, double tau) {
+  if (!s) return NS_EINVAL;
+  if (!(tau > 0.0) || !std::isfinite(tau)) return s->fail(NS_EINVAL, "tau must be positive");
+  return strang(s, tau, false, nullptr);
+}
+
+int ns_step_strang_cfl(ns_solver *s, double *tau) {
+  if (!s) return NS_EINVAL;
+  return strang(s, 0.0, true, tau);
+}
+
+int ns_parabolic_info(ns_solver *s, ns_par_info *out) {
+  if (!s || !out) return NS_EINVAL;
+  *out = s->pinfo;
+  return NS_OK;
 }
 
 int ns_fe_stage(ns_solver *s, double dt) {

@@ -122,3 +122,50 @@ def test_full_size(key):
         err = state_rel_err(U2[:, idx], ref, scale=scale)
         say("  err", err.max())
         assert err.max() <= TOL, (key, b, err)
+
+
+@pytest.mark.timeout(900)
+def test_full_size_navier_stokes_3d():
+    """The Navier-Stokes configuration at 256^3: hyperbolic step tau,
+    parabolic step 2 tau (mu = 1e-4, kappa = 1.4e-4, cv = 2.5, CG rtol
+    1e-10), hyperbolic step tau -- the Strang step as separate calls, so
+    that the parabolic step's properties can be checked on its own input:
+    density unchanged bit for bit, wall velocity zero, total energy changed
+    by exactly the kinetic energy removed at the no-slip nodes (to the CG
+    tolerance), admissibility; mass conserved over the whole step."""
+    gold = GOLD["3d"]
+    mesh, U0 = W.shock_tube_state(256, seed=0)
+    say("full size NS 3d build")
+    g = abi.Graph(mesh)
+    s = abi.Solver(g, gamma=gold["gamma"], cfl=gold["cfl"])
+    s.set_state(U0)
+    s.set_viscous(mu=1e-4, lam=0.0, kappa=1.4e-4, cv=2.5, cg_rtol=1e-10)
+    tau = gold["tau"]
+    Uin = s.get_state()
+    s.step(tau)
+    U1 = s.get_state()
+    say("parabolic")
+    s.step_parabolic(2.0 * tau)
+    info = s.parabolic_info()
+    say("  CG iterations", info.it_v, info.it_e, info.it_l, "fct", info.fct)
+    assert 0 < info.it_v < 500 and 0 < info.it_e < 500
+    U2 = s.get_state()
+    s.step(tau)
+    U3 = s.get_state()
+    del s
+    m = lumped_mass(mesh)
+    assert np.array_equal(U2[0], U1[0])
+    idx = np.indices(mesh.n[::-1]).reshape(3, -1)[::-1]
+    wall = np.zeros(mesh.N, bool)
+    for d in range(3):
+        wall |= (idx[d] == 0) | (idx[d] == mesh.n[d] - 1)
+    assert np.all(U2[1:4, wall] == 0.0)
+    ke_wall = 0.5 * np.sum((m * np.sum(U1[1:4] ** 2, axis=0) / U1[0])[wall])
+    dE = np.dot(m, U2[4]) - np.dot(m, U1[4])
+    say("  energy change", dE, "wall kinetic energy", ke_wall)
+    assert dE == pytest.approx(-ke_wall, abs=1e-9 * np.dot(m, U1[4]))
+    for U in (U2, U3):
+        eps = U[4] - 0.5 * (U[1:4] ** 2).sum(axis=0) / U[0]
+        assert np.all(U[0] > 0) and np.all(eps > 0)
+    a, b = np.dot(m, Uin[0]), np.dot(m, U3[0])
+    assert abs(b - a) <= 1e-12 * a

@@ -1,0 +1,219 @@
+"""GPU parity of the parabolic sub-step and the Strang step: the HIP path
+through the C ABI against the CPU oracle on the same seeded inputs.
+
+Both sides run diagonal-preconditioned CG from the same start values with
+the same stopping rule; the parity cases use cg_rtol = 1e-13 so that both
+are within round-off of the exact discrete solution, and the bar is the
+step bar, 1e-12 relative to the field's max norm.  Iteration counts must
+agree to within one (the stopping test is taken on residuals that differ
+by round-off).  Meshes span several 256-node blocks and a ragged tail."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2106_02159_amd import abi, workloads as W
+from tests.helpers import state_rel_err, state_scale
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+VISC = dict(mu=0.01, lam=0.005, kappa=0.02, cv=2.5)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rough(mesh, seed):
+    return mesh, W.random_rough_state(mesh, seed=seed)
+
+
+CASES = {
+    "rough2d_67x45": lambda: rough(W.Mesh(2, (67, 45), (0, 0), (1.0, 0.7), (False, False)), 11),
+    "rough2d_per_x": lambda: rough(W.Mesh(2, (40, 23), (0, 0), (1.0, 0.6), (True, False)), 12),
+    "quad2d_64": lambda: W.four_quadrant_state(64, seed=2),
+    "tube3d_17": lambda: W.shock_tube_state(17, seed=1),
+    "rough3d_13x11x9": lambda: rough(W.Mesh(3, (13, 11, 9), (0,) * 3, (1.0, 0.8, 0.7),
+                                           (False, True, False)), 13),
+    "tiny2d_2x2": lambda: rough(W.Mesh(2, (2, 2), (0, 0), (1, 1), (False, False)), 14),
+    "tiny3d_3x3x3per": lambda: rough(W.Mesh(3, (3, 3, 3), (0,) * 3, (1,) * 3, (True,) * 3), 15),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    mesh, U = CASES[request.param]()
+    og = O.Graph(mesh.dim, mesh.n, mesh.lo, mesh.hi, mesh.periodic)
+    U = og.slip_bc(U)
+    return request.param, mesh, og, abi.Graph(mesh), U
+
+
+def gpu_solver(g, U, fct=abi.FCT_AUTO, rtol=1e-13, maxit=2000, **kw):
+    s = abi.Solver(g)
+    s.set_state(U, project=False)
+    v = dict(VISC, **kw)
+    s.set_viscous(cg_rtol=rtol, cg_maxit=maxit, fct=fct, **v)
+    return s
+
+
+def oracle_visc(fct=0, rtol=1e-13, maxit=2000, **kw):
+    v = dict(VISC, **kw)
+    return O.visc(cg_rtol=rtol, cg_maxit=maxit, fct=fct, **v)
+
+
+def check_info(gi, oi):
+    assert gi.fct == oi.fct
+    assert abs(gi.it_v - oi.it_v) <= 1, (gi.it_v, oi.it_v)
+    assert abs(gi.it_e - oi.it_e) <= 1, (gi.it_e, oi.it_e)
+    if oi.fct:
+        assert abs(gi.it_l - oi.it_l) <= 1, (gi.it_l, oi.it_l)
+
+
+@pytest.mark.parametrize("fct", [0, 1])
+def test_parabolic_step(case, fct):
+    name, mesh, og, g, U = case
+    say("parabolic", name, "fct", fct)
+    dt = 0.5 * og.compute_dt(O.params(), U) * 2.0
+    ref, st, oi = og.parabolic_step(oracle_visc(fct=fct), U, dt)
+    assert st == 0
+    s = gpu_solver(g, U, fct=fct)
+    s.step_parabolic(dt)
+    out = s.get_state()
+    gi = s.parabolic_info()
+    check_info(gi, oi)
+    assert np.array_equal(out[0], U[0])
+    err = state_rel_err(out, ref, scale=state_scale(ref))
+    say("  err", err.max(), "iters", gi.it_v, gi.it_e, gi.it_l)
+    assert err.max() <= TOL, err
+
+
+def test_parabolic_large_dt(case):
+    """A step 20 times the hyperbolic one: more CG iterations, and on the
+    rough states CN undershoots, so the limiting runs by itself."""
+    name, mesh, og, g, U = case
+    say("parabolic large dt", name)
+    dt = 20.0 * og.compute_dt(O.params(), U)
+    ref, st, oi = og.parabolic_step(oracle_visc(), U, dt)
+    assert st == 0
+    s = gpu_solver(g, U)
+    s.step_parabolic(dt)
+    out = s.get_state()
+    check_info(s.parabolic_info(), oi)
+    err = state_rel_err(out, ref, scale=state_scale(ref))
+    say("  err", err.max(), "fct", oi.fct)
+    assert err.max() <= TOL, err
+
+
+def test_strang_step(case):
+    name, mesh, og, g, U = case
+    say("strang", name)
+    prm = O.params()
+    tau = og.compute_dt(prm, U)
+    ref, st, oi = og.strang_step(prm, oracle_visc(), U, tau)
+    assert st == 0
+    s = gpu_solver(g, U)
+    s.step_strang(tau)
+    out = s.get_state()
+    check_info(s.parabolic_info(), oi)
+    err = state_rel_err(out, ref, scale=state_scale(ref))
+    say("  err", err.max())
+    assert err.max() <= TOL, err
+    # the CFL variant computes the same tau on the device
+    s2 = gpu_solver(g, U)
+    t2 = s2.step_strang_cfl()
+    assert t2 == pytest.approx(tau, rel=1e-14, abs=0)
+    assert np.array_equal(s2.get_state(), gpu_strang_given(g, U, t2))
+
+
+def gpu_strang_given(g, U, tau):
+    s = gpu_solver(g, U)
+    s.step_strang(tau)
+    return s.get_state()
+
+
+def test_spike_triggers_limiting():
+    mesh = W.Mesh(2, (48, 37), (0.0, 0.0), (1.0, 0.75), (False, False))
+    x, y = mesh.coords()
+    rho = 1.0 + 0.2 * np.sin(3 * x)
+    e = np.where((np.abs(x - 0.5) < 0.011) & (np.abs(y - 0.4) < 0.011), 1.0, 1e-4)
+    v = np.zeros((2, mesh.N))
+    U = np.vstack([rho[None], rho * v, (rho * e)[None]])
+    og = O.Graph(2, mesh.n, mesh.lo, mesh.hi, mesh.periodic)
+    kw = dict(mu=0.0, lam=0.0, kappa=2.5, cv=2.5)
+    ref, st, oi = og.parabolic_step(oracle_visc(**kw), U, 0.05)
+    assert st == 0 and oi.fct == 1 and oi.min_eH < 0
+    s = gpu_solver(abi.Graph(mesh), U, **kw)
+    s.step_parabolic(0.05)
+    gi = s.parabolic_info()
+    check_info(gi, oi)
+    assert gi.min_eH == pytest.approx(oi.min_eH, rel=1e-12)
+    out = s.get_state()
+    err = state_rel_err(out, ref, scale=state_scale(ref))
+    assert err.max() <= TOL, err
+    eps = out[3] / out[0]
+    assert eps.min() >= e.min() * (1 - 1e-12)
+
+
+def test_default_tolerance_properties():
+    """At the production tolerance (1e-10): density bit for bit, energy
+    change equal to the kinetic energy removed at the no-slip nodes, and
+    agreement with the tight-tolerance oracle to the solver tolerance."""
+    mesh, U = W.shock_tube_state(24, seed=3)
+    og = O.Graph(3, mesh.n, mesh.lo, mesh.hi, mesh.periodic)
+    U = og.slip_bc(U)
+    dt = 2.0 * og.compute_dt(O.params(), U)
+    s = gpu_solver(abi.Graph(mesh), U, rtol=1e-10, mu=1e-3, lam=0.0, kappa=1.4e-3)
+    s.step_parabolic(dt)
+    out = s.get_state()
+    assert np.array_equal(out[0], U[0])
+    m = og.mi
+    wall = og.on_wall.astype(bool)
+    ke_wall = 0.5 * np.sum((m * np.sum(U[1:4] ** 2, axis=0) / U[0])[wall])
+    dE = np.dot(m, out[4]) - np.dot(m, U[4])
+    assert dE == pytest.approx(-ke_wall, abs=1e-9 * np.dot(m, U[4]))
+    ref, _, _ = og.parabolic_step(oracle_visc(mu=1e-3, lam=0.0, kappa=1.4e-3), U, dt)
+    assert state_rel_err(out, ref, scale=state_scale(ref)).max() <= 1e-9
+
+
+def test_cg_failure_is_transactional():
+    mesh, U = W.four_quadrant_state(40, seed=4)
+    g = abi.Graph(mesh)
+    s = gpu_solver(g, U, rtol=1e-13, maxit=1)
+    before = s.get_state()
+    rc = s.step_parabolic_status(0.01)
+    assert rc == abi.NS_ECG
+    assert np.array_equal(s.get_state(), before)
+    # a Strang step failing in its parabolic part restores the start state
+    with pytest.raises(abi.NSError):
+        s.step_strang(1e-5)
+    assert np.array_equal(s.get_state(), before)
+
+
+def test_invalid_viscous_data():
+    mesh, U = W.four_quadrant_state(16, seed=5)
+    s = abi.Solver(abi.Graph(mesh))
+    s.set_state(U)
+    with pytest.raises(abi.NSError):
+        s.step_parabolic(0.01)  # no viscous data yet
+    for bad in (dict(mu=-1.0), dict(cv=0.0), dict(cg_rtol=0.0), dict(cg_rtol=1.0),
+                dict(cg_maxit=0), dict(fct=2), dict(kappa=float("nan"))):
+        with pytest.raises(abi.NSError):
+            s.set_viscous(**bad)
+    s.set_viscous()
+    with pytest.raises(abi.NSError):
+        s.step_parabolic(-1.0)
+
+
+def test_strang_equals_its_parts():
+    """ns_step_strang is the composition of ns_step(tau),
+    ns_step_parabolic(2 tau) and ns_step(tau), bit for bit."""
+    mesh, U = W.shock_tube_state(20, seed=6)
+    g = abi.Graph(mesh)
+    a = gpu_solver(g, U, rtol=1e-10)
+    tau = a.compute_dt()
+    a.step_strang(tau)
+    b = gpu_solver(g, U, rtol=1e-10)
+    b.step(tau)
+    b.step_parabolic(2.0 * tau)
+    b.step(tau)
+    assert np.array_equal(a.get_state(), b.get_state())
