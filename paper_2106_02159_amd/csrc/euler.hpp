@@ -17,8 +17,13 @@ struct Gas {
   int seven;       // 1 when gamma == 7/5
 };
 
+// SEV: 1 when gamma == 7/5 is fixed at compile time (integer powers and the
+// polynomial entropy test), 0 for a general gamma (pow).  The kernels are
+// instantiated for both and the host picks by Gas::seven, so the gamma = 7/5
+// kernels carry no pow code at all.
+template <int SEV>
 __device__ __forceinline__ double pow_inv_ex(const Gas &g, double x) {
-  if (g.seven) {
+  if constexpr (SEV) {
     const double x2 = x * x;
     const double x4 = x2 * x2;
     return x4 * x2 * x;
@@ -31,12 +36,13 @@ __device__ __forceinline__ double pow_inv_ex(const Gas &g, double x) {
 // direction n (u = v.n).  bL = aL pL^(-ex), bR likewise (precomputed per
 // node).  Two-rarefaction bound on the star pressure, valid for
 // 1 < gamma <= 5/3, inserted in the extreme shock/rarefaction speeds.
+template <int SEV>
 __device__ __forceinline__ double lambda_max(const Gas &g, double uL, double pL,
                                              double aL, double bL, double uR,
                                              double pR, double aR, double bR) {
   const double num = aL + aR - 0.5 * g.gm1 * (uR - uL);
   double ptr = 0.0;
-  if (num > 0.0) ptr = pow_inv_ex(g, num / (bL + bR));
+  if (num > 0.0) ptr = pow_inv_ex<SEV>(g, num / (bL + bR));
   const double l1 = uL - aL * sqrt(1.0 + g.cg * fmax(ptr / pL - 1.0, 0.0));
   const double l3 = uR + aR * sqrt(1.0 + g.cg * fmax(ptr / pR - 1.0, 0.0));
   return fmax(fmax(-l1, 0.0), fmax(l3, 0.0));
@@ -71,7 +77,7 @@ __device__ __forceinline__ double psi_eval(const Gas &g, const double *u,
 // test eps >= phi_min rho^(7/5) is taken division- and pow-free as
 // (rho eps)^5 >= phi_min^5 rho^12 with rho eps = rho E - |m|^2/2 (both sides
 // are non-negative exactly when eps >= 0); pmin5 = phi_min^5.
-template <int DIM>
+template <int DIM, int SEV>
 __device__ __forceinline__ bool entropy_ok(const Gas &g, const double *u,
                                            const double *P, double l,
                                            double phi_min, double pmin5) {
@@ -83,14 +89,16 @@ __device__ __forceinline__ bool entropy_ok(const Gas &g, const double *u,
     m2 += mk * mk;
   }
   const double E = u[DIM + 1] + l * P[DIM + 1];
-  if (g.seven) {
+  if constexpr (SEV) {
     const double A = r * E - 0.5 * m2;
     if (!(A > 0.0)) return false;
     const double A2 = A * A;
     const double r2 = r * r, r4 = r2 * r2, r8 = r4 * r4;
     return A2 * A2 * A >= pmin5 * (r8 * r4);
   }
-  return E - 0.5 * m2 / r - phi_min * pow(r, g.gamma) >= 0.0;
+  else {
+    return E - 0.5 * m2 / r - phi_min * pow(r, g.gamma) >= 0.0;
+  }
 }
 
 // Root of psi in (a, b) with psi(a) >= 0 > psi(b).  psi is concave in l, so
@@ -209,11 +217,11 @@ __device__ __forceinline__ double entropy_root_seven(const double *u,
 // is infeasible and, from such a close start, within round-off of the root;
 // the feasible point just below it is returned once psi confirms it.
 // Otherwise (or if that check fails) the bracketing search on psi runs.
-template <int DIM>
+template <int DIM, int SEV>
 __device__ __forceinline__ double entropy_root_fast(const Gas &g, const double *u,
                                                    const double *P, double lr,
                                                    double pmin, double pmin5) {
-  if (g.seven) {
+  if constexpr (SEV) {
     const double x = entropy_root_seven<DIM>(u, P, lr, pmin5);
     double d;
     const double f = psi_eval<DIM>(g, u, P, x, pmin, &d);

@@ -34,9 +34,6 @@ template <int DIM> struct Aux {
 #ifndef NS_CH_FIN
 #define NS_CH_FIN 1
 #endif
-#ifndef NS_CACHE_P
-#define NS_CACHE_P 0
-#endif
 template <int DIM, int CHUNK = 9> struct Cfg {
   static constexpr int NC = DIM + 2;
   static constexpr int W = DIM == 2 ? 9 : 27;
@@ -55,7 +52,34 @@ __device__ __forceinline__ int64_t eidx(int k, int64_t i) {
   return ((i >> 6) * W + k) * 64 + (i & 63);
 }
 
+// Column (or transpose-slot) indices of a row: in 2D all W are loaded at
+// the start so that a chunk's gathers can be issued at once; in 3D each is
+// loaded where its chunk starts (27 of them would hold 27 registers through
+// the whole kernel and lower the occupancy).
+template <int DIM, typename T>
+struct RowIdx {
+  static constexpr bool PRE = DIM == 2;
+  static constexpr int W = DIM == 2 ? 9 : 27;
+  const T *p;
+  int64_t i;
+  T v[PRE ? W : 1];
+  __device__ __forceinline__ RowIdx(const T *ptr, int64_t row) : p(ptr), i(row) {
+    if constexpr (PRE) {
+#pragma unroll
+      for (int k = 0; k < W; ++k) v[k] = p[eidx<DIM>(k, i)];
+    }
+  }
+  __device__ __forceinline__ int operator[](int k) const {
+    if constexpr (PRE) return v[k];
+    else return p[eidx<DIM>(k, i)];
+  }
+};
+
 __device__ __forceinline__ int64_t row_id() {
+  return (int64_t)blockIdx.x * kBlock + threadIdx.x;
+}
+
+__device__ __forceinline__ int64_t plain_id() {
   return (int64_t)blockIdx.x * kBlock + threadIdx.x;
 }
 
@@ -137,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_prim(int64_t N,
 // gathers its neighbour data unconditionally (absent entries read row i
 // itself) so that the loads of a chunk are in flight together, and the
 // arithmetic is predicated on the entry being present.
-template <int DIM, int IND>
+template <int DIM, int IND, int SEV>
 __global__ __launch_bounds__(kBlock) void k_visc(DevGraph G,
                                                  const double *__restrict__ U,
                                                  const double *__restrict__ aux,
@@ -152,9 +176,7 @@ __global__ __launch_bounds__(kBlock) void k_visc(DevGraph G,
   if (i >= N) return;
   const int32_t *__restrict__ colp = G.col;
   const uint8_t *__restrict__ trkp = G.trk;
-  int32_t jv[C::W];
-#pragma unroll
-  for (int k = 0; k < C::W; ++k) jv[k] = colp[eidx<DIM>(k, i)];
+  const RowIdx<DIM, int32_t> jv(colp, i);
   double vi[DIM];
 #pragma unroll
   for (int k = 0; k < DIM; ++k) vi[k] = aux[k * N + i];
@@ -184,11 +206,13 @@ __global__ __launch_bounds__(kBlock) void k_visc(DevGraph G,
   for (int ch = 0; ch < C::NCH; ++ch) {
     double c[C::CH][DIM], vj[C::CH][DIM], pj[C::CH], aj[C::CH], bj[C::CH];
     double uj[C::CH][IND == 0 ? NC : 1], etaj[C::CH];
+    int32_t jc[C::CH];
 #pragma unroll
     for (int kk = 0; kk < C::CH; ++kk) {
       const int k = ch * C::CH + kk;
       const int64_t e = eidx<DIM>(k, i);
-      const int64_t js = jv[k] >= 0 ? jv[k] : i;
+      jc[kk] = jv[k];
+      const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
       load_c<DIM>(G, e, c[kk]);
 #pragma unroll
       for (int q = 0; q < DIM; ++q) vj[kk][q] = aux[q * N + js];
@@ -203,7 +227,7 @@ __global__ __launch_bounds__(kBlock) void k_visc(DevGraph G,
 #pragma unroll
     for (int kk = 0; kk < C::CH; ++kk) {
       const int k = ch * C::CH + kk;
-      const int32_t j = jv[k];
+      const int32_t j = jc[kk];
       if (j < 0) continue;
       double c2 = 0.0;
 #pragma unroll
@@ -230,7 +254,7 @@ __global__ __launch_bounds__(kBlock) void k_visc(DevGraph G,
           uL += vi[q] * c[kk][q] * icn;
           uR += vj[kk][q] * c[kk][q] * icn;
         }
-        double dij = lambda_max(g, uL, pi, ai, bi, uR, pj[kk], aj[kk], bj[kk]) * cn;
+        double dij = lambda_max<SEV>(g, uL, pi, ai, bi, uR, pj[kk], aj[kk], bj[kk]) * cn;
         const int kt = trkp[e];
         const int64_t et = eidx<DIM>(kt, j);
         if (wall_i) {
@@ -248,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_visc(DevGraph G,
             uLt += vj[kk][q] * ct[q] * ictn;
             uRt += vi[q] * ct[q] * ictn;
           }
-          dij = fmax(dij, lambda_max(g, uLt, pj[kk], aj[kk], bj[kk], uRt, pi, ai, bi) * ctn);
+          dij = fmax(dij, lambda_max<SEV>(g, uLt, pj[kk], aj[kk], bj[kk], uRt, pi, ai, bi) * ctn);
         }
         d[e] = dij;
         d[et] = dij;
@@ -320,9 +344,7 @@ __global__ __launch_bounds__(kBlock) void k_lo(DevGraph G, StageArgs A, Gas g) {
   const double *__restrict__ alpha = A.alpha;
   const double *__restrict__ dd = A.d;
   const int32_t *__restrict__ colp = G.col;
-  int32_t jv[C::W];
-#pragma unroll
-  for (int k = 0; k < C::W; ++k) jv[k] = colp[eidx<DIM>(k, i)];
+  const RowIdx<DIM, int32_t> jv(colp, i);
   double ui[NC], vi[DIM];
   load_state<NC>(U, N, i, ui);
 #pragma unroll
@@ -338,11 +360,13 @@ __global__ __launch_bounds__(kBlock) void k_lo(DevGraph G, StageArgs A, Gas g) {
   for (int ch = 0; ch < C::NCH; ++ch) {
     double c[C::CH][DIM], uj[C::CH][NC], vj[C::CH][DIM], pj[C::CH], phij[C::CH],
         alj[C::CH], dij[C::CH];
+    int32_t jc[C::CH];
 #pragma unroll
     for (int kk = 0; kk < C::CH; ++kk) {
       const int k = ch * C::CH + kk;
       const int64_t e = eidx<DIM>(k, i);
-      const int64_t js = jv[k] >= 0 ? jv[k] : i;
+      jc[kk] = jv[k];
+      const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
       load_c<DIM>(G, e, c[kk]);
       load_state<NC>(U, N, js, uj[kk]);
 #pragma unroll
@@ -355,7 +379,7 @@ __global__ __launch_bounds__(kBlock) void k_lo(DevGraph G, StageArgs A, Gas g) {
 #pragma unroll
     for (int kk = 0; kk < C::CH; ++kk) {
       const int k = ch * C::CH + kk;
-      const int32_t j = jv[k];
+      const int32_t j = jc[kk];
       if (j < 0) continue;
       double fci[NC];
       flux_dot<DIM>(ui, vi, pi, c[kk], fci);
@@ -502,7 +526,7 @@ __device__ __forceinline__ Bounds load_bounds(const StageArgs &A, int64_t N,
 // k_root.  In a sweep such entries are rare but scattered: solved in place,
 // a few lanes would hold their whole wavefront for the length of a root
 // search, and the root finder's registers would lower the sweep's occupancy.
-template <int DIM>
+template <int DIM, int SEV>
 __device__ __forceinline__ int limit_fast(const Gas &g, const double *u,
                                           const double *P, const Bounds &b,
                                           double *l) {
@@ -512,12 +536,12 @@ __device__ __forceinline__ int limit_fast(const Gas &g, const double *u,
   else lr = 1.0;
   lr = fmin(fmax(lr, 0.0), 1.0);
   *l = lr;
-  if (entropy_ok<DIM>(g, u, P, lr, b.pmin, b.pmin5)) return 0;
-  if (!entropy_ok<DIM>(g, u, P, 0.0, b.pmin, b.pmin5)) { *l = 0.0; return 0; }
+  if (entropy_ok<DIM, SEV>(g, u, P, lr, b.pmin, b.pmin5)) return 0;
+  if (!entropy_ok<DIM, SEV>(g, u, P, 0.0, b.pmin, b.pmin5)) { *l = 0.0; return 0; }
   return 1;  // root of psi in (0, lr) still to be found
 }
 
-template <int DIM>
+template <int DIM, int SEV>
 __global__ __launch_bounds__(kBlock) void k_lim1(DevGraph G, StageArgs A, Gas g) {
   using C = Cfg<DIM, NS_CH_LIM1>;
   constexpr int NC = C::NC;
@@ -525,9 +549,7 @@ __global__ __launch_bounds__(kBlock) void k_lim1(DevGraph G, StageArgs A, Gas g)
   const int64_t i = row_id();
   if (i >= N) return;
   const int32_t *__restrict__ colp = G.col;
-  int32_t jv[C::W];
-#pragma unroll
-  for (int k = 0; k < C::W; ++k) jv[k] = colp[eidx<DIM>(k, i)];
+  const RowIdx<DIM, int32_t> jv(colp, i);
   RowCtx<DIM> R;
   load_row<DIM>(G, A, i, *A.tau, R);
   double ul[NC];
@@ -538,18 +560,20 @@ __global__ __launch_bounds__(kBlock) void k_lim1(DevGraph G, StageArgs A, Gas g)
 #pragma unroll
   for (int ch = 0; ch < C::NCH; ++ch) {
     PIn<DIM> x[C::CH];
+    int32_t jc[C::CH];
 #pragma unroll
     for (int kk = 0; kk < C::CH; ++kk) {
       const int k = ch * C::CH + kk;
-      gather_P<DIM>(G, A, eidx<DIM>(k, i), jv[k] >= 0 ? jv[k] : i, x[kk]);
+      jc[kk] = jv[k];
+      gather_P<DIM>(G, A, eidx<DIM>(k, i), jc[kk] >= 0 ? jc[kk] : i, x[kk]);
     }
 #pragma unroll
     for (int kk = 0; kk < C::CH; ++kk) {
       const int k = ch * C::CH + kk;
-      if (jv[k] < 0 || jv[k] == i) continue;
+      if (jc[kk] < 0 || jc[kk] == i) continue;
       double P[NC], l;
       make_P<DIM>(R, x[kk], P);
-      if (limit_fast<DIM>(g, ul, P, b, &l)) slow |= 1u << k;
+      if (limit_fast<DIM, SEV>(g, ul, P, b, &l)) slow |= 1u << k;
       lt1[eidx<DIM>(k, i)] = l;
     }
   }
@@ -564,8 +588,10 @@ __global__ __launch_bounds__(kBlock) void k_lim1(DevGraph G, StageArgs A, Gas g)
 }
 
 // MODE 0: convex, pass-1 update + pass-2 line search; 1: convex with one
-// pass, final; 2: l = 1 (unlimited high order), final.
-template <int DIM, int MODE>
+// pass, final; 2: l = 1 (unlimited high order), final; 3: convex, pass-1
+// update only (3D: the pass-2 search is k_lim2b, since both in one kernel
+// need more registers than a SIMD lane has).
+template <int DIM, int MODE, int SEV>
 __global__ __launch_bounds__(kBlock) void k_lim2(DevGraph G, StageArgs A, Gas g) {
   using C = Cfg<DIM, NS_CH_LIM2>;
   constexpr int NC = C::NC;
@@ -575,13 +601,8 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraph G, StageArgs A, Gas g)
   const int32_t *__restrict__ colp = G.col;
   const uint8_t *__restrict__ trkp = G.trk;
   const double *__restrict__ lt1 = A.lt1;
-  int32_t jv[C::W];
-  int tv[C::W];
-#pragma unroll
-  for (int k = 0; k < C::W; ++k) {
-    jv[k] = colp[eidx<DIM>(k, i)];
-    tv[k] = MODE != 2 ? trkp[eidx<DIM>(k, i)] : 0;
-  }
+  const RowIdx<DIM, int32_t> colk(colp, i);
+  const RowIdx<DIM, uint8_t> trkk(trkp, i);
   RowCtx<DIM> R;
   load_row<DIM>(G, A, i, *A.tau, R);
   const double lam = 1.0 / G.lfac[i];
@@ -595,21 +616,23 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraph G, StageArgs A, Gas g)
   for (int ch = 0; ch < C::NCH; ++ch) {
     PIn<DIM> x[C::CH];
     double la[C::CH], lb[C::CH];
+    int32_t jc[C::CH];
 #pragma unroll
     for (int kk = 0; kk < C::CH; ++kk) {
       const int k = ch * C::CH + kk;
       const int64_t e = eidx<DIM>(k, i);
-      const int64_t js = jv[k] >= 0 ? jv[k] : i;
+      jc[kk] = colk[k];
+      const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
       gather_P<DIM>(G, A, e, js, x[kk]);
       if constexpr (MODE != 2) {
         la[kk] = lt1[e];
-        lb[kk] = lt1[eidx<DIM>(tv[k], js)];
+        lb[kk] = lt1[eidx<DIM>(trkk[k], js)];
       }
     }
 #pragma unroll
     for (int kk = 0; kk < C::CH; ++kk) {
       const int k = ch * C::CH + kk;
-      if (jv[k] < 0 || jv[k] == i) continue;
+      if (jc[kk] < 0 || jc[kk] == i) continue;
       const double l = MODE != 2 ? fmin(la[kk], lb[kk]) : 1.0;
       double P[NC];
       make_P<DIM>(R, x[kk], P);
@@ -622,7 +645,10 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraph G, StageArgs A, Gas g)
       }
     }
   }
-  if constexpr (MODE != 0) {
+  if constexpr (MODE == 3) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q) A.U1[q * N + i] = u1[q];
+  } else if constexpr (MODE != 0) {
     finish<DIM>(G, A, i, u1);
   } else {
 #pragma unroll
@@ -637,6 +663,7 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraph G, StageArgs A, Gas g)
 #pragma unroll
     for (int ch = 0; ch < C::NCH; ++ch) {
       double P[C::CH][NC], l[C::CH];
+      int32_t jc[C::CH];
       if constexpr (CACHE) {
 #pragma unroll
         for (int kk = 0; kk < C::CH; ++kk) {
@@ -644,6 +671,7 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraph G, StageArgs A, Gas g)
 #pragma unroll
           for (int q = 0; q < NC; ++q) P[kk][q] = Pc[k][q];
           l[kk] = lc[k];
+          jc[kk] = colk[k];
         }
       } else {
         // one chunk of gathers in flight at a time (bounds the registers)
@@ -654,10 +682,11 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraph G, StageArgs A, Gas g)
         for (int kk = 0; kk < C::CH; ++kk) {
           const int k = ch * C::CH + kk;
           const int64_t e = eidx<DIM>(k, i);
-          const int64_t js = jv[k] >= 0 ? jv[k] : i;
+          jc[kk] = colk[k];
+          const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
           gather_P<DIM>(G, A, e, js, x[kk]);
           la[kk] = lt1[e];
-          lb[kk] = lt1[eidx<DIM>(tv[k], js)];
+          lb[kk] = lt1[eidx<DIM>(trkk[k], js)];
         }
 #pragma unroll
         for (int kk = 0; kk < C::CH; ++kk) {
@@ -668,11 +697,11 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraph G, StageArgs A, Gas g)
 #pragma unroll
       for (int kk = 0; kk < C::CH; ++kk) {
         const int k = ch * C::CH + kk;
-        if (jv[k] < 0 || jv[k] == i) continue;
+        if (jc[kk] < 0 || jc[kk] == i) continue;
         double l2;
 #pragma unroll
         for (int q = 0; q < NC; ++q) P[kk][q] *= (1.0 - l[kk]);
-        if (limit_fast<DIM>(g, u1, P[kk], b, &l2)) slow |= 1u << k;
+        if (limit_fast<DIM, SEV>(g, u1, P[kk], b, &l2)) slow |= 1u << k;
         lt2[eidx<DIM>(k, i)] = l2;
       }
     }
@@ -683,6 +712,62 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraph G, StageArgs A, Gas g)
         slow &= slow - 1;
         A.q[t++] = (uint32_t)eidx<DIM>(k, i);
       }
+    }
+  }
+}
+
+// Pass-2 line search on (1 - l_ij) P_ij from U^(1) (stored by k_lim2<3>).
+template <int DIM, int SEV>
+__global__ __launch_bounds__(kBlock) void k_lim2b(DevGraph G, StageArgs A, Gas g) {
+  using C = Cfg<DIM, NS_CH_LIM2>;
+  constexpr int NC = C::NC;
+  const int64_t N = G.N;
+  const int64_t i = row_id();
+  if (i >= N) return;
+  const int32_t *__restrict__ colp = G.col;
+  const uint8_t *__restrict__ trkp = G.trk;
+  const double *__restrict__ lt1 = A.lt1;
+  double *__restrict__ lt2 = A.lt2;
+  RowCtx<DIM> R;
+  load_row<DIM>(G, A, i, *A.tau, R);
+  double u1[NC];
+  load_state<NC>(A.U1, N, i, u1);
+  const Bounds b = load_bounds(A, N, i);
+  uint32_t slow = 0;
+#pragma unroll
+  for (int ch = 0; ch < C::NCH; ++ch) {
+    PIn<DIM> x[C::CH];
+    double la[C::CH], lb[C::CH];
+    int32_t jc[C::CH];
+#pragma unroll
+    for (int kk = 0; kk < C::CH; ++kk) {
+      const int k = ch * C::CH + kk;
+      const int64_t e = eidx<DIM>(k, i);
+      jc[kk] = colp[e];
+      const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
+      gather_P<DIM>(G, A, e, js, x[kk]);
+      la[kk] = lt1[e];
+      lb[kk] = lt1[eidx<DIM>(trkp[e], js)];
+    }
+#pragma unroll
+    for (int kk = 0; kk < C::CH; ++kk) {
+      const int k = ch * C::CH + kk;
+      if (jc[kk] < 0 || jc[kk] == i) continue;
+      double P[NC], l2;
+      make_P<DIM>(R, x[kk], P);
+      const double l = fmin(la[kk], lb[kk]);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) P[q] *= (1.0 - l);
+      if (limit_fast<DIM, SEV>(g, u1, P, b, &l2)) slow |= 1u << k;
+      lt2[eidx<DIM>(k, i)] = l2;
+    }
+  }
+  if (slow) {
+    uint32_t t = atomicAdd(&A.qcnt[1], (uint32_t)__builtin_popcount(slow));
+    while (slow) {
+      const int k = __builtin_ctz(slow);
+      slow &= slow - 1;
+      A.q[t++] = (uint32_t)eidx<DIM>(k, i);
     }
   }
 }
@@ -698,7 +783,7 @@ __device__ __forceinline__ int64_t edge_row(int64_t e) {
 // one lane per listed entry, grid-stride over the list, so the rare root
 // finder runs at full occupancy instead of stalling a row sweep's wavefront.
 // The line search's density limit l_rho was stored in lt by the sweep.
-template <int DIM, int PASS>
+template <int DIM, int PASS, int SEV>
 __global__ __launch_bounds__(kBlock) void k_root(DevGraph G, StageArgs A, Gas g) {
   constexpr int NC = DIM + 2;
   const int64_t N = G.N;
@@ -722,7 +807,7 @@ __global__ __launch_bounds__(kBlock) void k_root(DevGraph G, StageArgs A, Gas g)
 #pragma unroll
       for (int c = 0; c < NC; ++c) P[c] *= (1.0 - l);
     }
-    lt[e] = entropy_root_fast<DIM>(g, u, P, lt[e], b.pmin, b.pmin5);
+    lt[e] = entropy_root_fast<DIM, SEV>(g, u, P, lt[e], b.pmin, b.pmin5);
   }
 }
 
@@ -737,13 +822,8 @@ __global__ __launch_bounds__(kBlock) void k_fin(DevGraph G, StageArgs A, Gas g) 
   const uint8_t *__restrict__ trkp = G.trk;
   const double *__restrict__ lt1 = A.lt1;
   const double *__restrict__ lt2 = A.lt2;
-  int32_t jv[C::W];
-  int tv[C::W];
-#pragma unroll
-  for (int k = 0; k < C::W; ++k) {
-    jv[k] = colp[eidx<DIM>(k, i)];
-    tv[k] = trkp[eidx<DIM>(k, i)];
-  }
+  const RowIdx<DIM, int32_t> jv(colp, i);
+  const RowIdx<DIM, uint8_t> tv(trkp, i);
   RowCtx<DIM> R;
   load_row<DIM>(G, A, i, *A.tau, R);
   const double lam = 1.0 / G.lfac[i];
@@ -753,11 +833,13 @@ __global__ __launch_bounds__(kBlock) void k_fin(DevGraph G, StageArgs A, Gas g) 
   for (int ch = 0; ch < C::NCH; ++ch) {
     PIn<DIM> x[C::CH];
     double l1a[C::CH], l1b[C::CH], l2a[C::CH], l2b[C::CH];
+    int32_t jc[C::CH];
 #pragma unroll
     for (int kk = 0; kk < C::CH; ++kk) {
       const int k = ch * C::CH + kk;
       const int64_t e = eidx<DIM>(k, i);
-      const int64_t js = jv[k] >= 0 ? jv[k] : i;
+      jc[kk] = jv[k];
+      const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
       const int64_t et = eidx<DIM>(tv[k], js);
       gather_P<DIM>(G, A, e, js, x[kk]);
       l1a[kk] = lt1[e];
@@ -768,7 +850,7 @@ __global__ __launch_bounds__(kBlock) void k_fin(DevGraph G, StageArgs A, Gas g) 
 #pragma unroll
     for (int kk = 0; kk < C::CH; ++kk) {
       const int k = ch * C::CH + kk;
-      if (jv[k] < 0 || jv[k] == i) continue;
+      if (jc[kk] < 0 || jc[kk] == i) continue;
       const double l1 = fmin(l1a[kk], l1b[kk]);
       const double l2 = fmin(l2a[kk], l2b[kk]);
       double P[NC];
@@ -811,14 +893,14 @@ __global__ __launch_bounds__(kBlock) void k_slip(int nslip,
 __global__ __launch_bounds__(kBlock) void k_copy(const double2 *__restrict__ src,
                                                  double2 *__restrict__ dst,
                                                  int64_t n16) {
-  const int64_t t = row_id();
+  const int64_t t = plain_id();
   if (t < n16) dst[t] = src[t];
 }
 
 __global__ __launch_bounds__(kBlock) void k_copy8(const double *__restrict__ src,
                                                   double *__restrict__ dst,
                                                   int64_t n8) {
-  const int64_t t = row_id();
+  const int64_t t = plain_id();
   if (t < n8) dst[t] = src[t];
 }
 
@@ -856,7 +938,7 @@ __global__ __launch_bounds__(kBlock) void k_check_state(int64_t N,
 
 inline dim3 grid_for(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
 
-template <int DIM>
+template <int DIM, int SEV>
 void stage_impl(const Gas &gas, const DevGraph &G, const StageArgs &A,
                 int indicator, int limiter, int passes, bool auto_dt,
                 double cfl, hipStream_t s, void (*before)(void *, const char *),
@@ -871,13 +953,13 @@ void stage_impl(const Gas &gas, const DevGraph &G, const StageArgs &A,
   NS_LAUNCH("prim", hipLaunchKernelGGL(k_prim<DIM>, grid, block, 0, s, G.N, A.U,
                                        A.aux, gas));
   if (indicator == 0)
-    NS_LAUNCH("visc", hipLaunchKernelGGL((k_visc<DIM, 0>), grid, block, 0, s, G,
+    NS_LAUNCH("visc", hipLaunchKernelGGL((k_visc<DIM, 0, SEV>), grid, block, 0, s, G,
                                          A.U, A.aux, A.d, A.alpha, gas));
   else if (indicator == 1)
-    NS_LAUNCH("visc", hipLaunchKernelGGL((k_visc<DIM, 1>), grid, block, 0, s, G,
+    NS_LAUNCH("visc", hipLaunchKernelGGL((k_visc<DIM, 1, SEV>), grid, block, 0, s, G,
                                          A.U, A.aux, A.d, A.alpha, gas));
   else
-    NS_LAUNCH("visc", hipLaunchKernelGGL((k_visc<DIM, 2>), grid, block, 0, s, G,
+    NS_LAUNCH("visc", hipLaunchKernelGGL((k_visc<DIM, 2, SEV>), grid, block, 0, s, G,
                                          A.U, A.aux, A.d, A.alpha, gas));
   if (auto_dt) {
     NS_LAUNCH("dt_partial", hipLaunchKernelGGL(k_dt_partial<DIM>, grid, block, 0, s,
@@ -891,22 +973,29 @@ void stage_impl(const Gas &gas, const DevGraph &G, const StageArgs &A,
     NS_LAUNCH("combine", hipLaunchKernelGGL(k_combine_low<DIM>, grid, block, 0, s,
                                             G, A));
   } else if (limiter == 2) {
-    NS_LAUNCH("lim2", hipLaunchKernelGGL((k_lim2<DIM, 2>), grid, block, 0, s, G, A,
+    NS_LAUNCH("lim2", hipLaunchKernelGGL((k_lim2<DIM, 2, SEV>), grid, block, 0, s, G, A,
                                          gas));
   } else {
     // the work lists hold a small fraction of the edges: a grid of a few
     // wavefronts per SIMD covers them in one or two passes
     const dim3 rgrid(std::min<unsigned>(grid.x, 1024u));
-    NS_LAUNCH("lim1", hipLaunchKernelGGL(k_lim1<DIM>, grid, block, 0, s, G, A, gas));
-    NS_LAUNCH("root1", hipLaunchKernelGGL((k_root<DIM, 1>), rgrid, block, 0, s, G,
+    NS_LAUNCH("lim1", hipLaunchKernelGGL((k_lim1<DIM, SEV>), grid, block, 0, s, G, A, gas));
+    NS_LAUNCH("root1", hipLaunchKernelGGL((k_root<DIM, 1, SEV>), rgrid, block, 0, s, G,
                                           A, gas));
     if (passes == 1) {
-      NS_LAUNCH("lim2", hipLaunchKernelGGL((k_lim2<DIM, 1>), grid, block, 0, s, G,
+      NS_LAUNCH("lim2", hipLaunchKernelGGL((k_lim2<DIM, 1, SEV>), grid, block, 0, s, G,
                                            A, gas));
     } else {
-      NS_LAUNCH("lim2", hipLaunchKernelGGL((k_lim2<DIM, 0>), grid, block, 0, s, G,
-                                           A, gas));
-      NS_LAUNCH("root2", hipLaunchKernelGGL((k_root<DIM, 2>), rgrid, block, 0, s, G,
+      if constexpr (DIM == 2) {
+        NS_LAUNCH("lim2", hipLaunchKernelGGL((k_lim2<DIM, 0, SEV>), grid, block, 0, s,
+                                             G, A, gas));
+      } else {
+        NS_LAUNCH("lim2", hipLaunchKernelGGL((k_lim2<DIM, 3, SEV>), grid, block, 0, s,
+                                             G, A, gas));
+        NS_LAUNCH("lim2b", hipLaunchKernelGGL((k_lim2b<DIM, SEV>), grid, block, 0, s,
+                                              G, A, gas));
+      }
+      NS_LAUNCH("root2", hipLaunchKernelGGL((k_root<DIM, 2, SEV>), rgrid, block, 0, s, G,
                                             A, gas));
       NS_LAUNCH("fin", hipLaunchKernelGGL(k_fin<DIM>, grid, block, 0, s, G, A, gas));
     }
@@ -914,7 +1003,7 @@ void stage_impl(const Gas &gas, const DevGraph &G, const StageArgs &A,
 #undef NS_LAUNCH
 }
 
-template <int DIM>
+template <int DIM, int SEV>
 void dt_impl(const Gas &gas, const DevGraph &G, const StageArgs &A, double cfl,
              hipStream_t s, void (*before)(void *, const char *),
              void (*after)(void *), void *prof) {
@@ -923,7 +1012,7 @@ void dt_impl(const Gas &gas, const DevGraph &G, const StageArgs &A, double cfl,
   hipLaunchKernelGGL(k_prim<DIM>, grid, block, 0, s, G.N, A.U, A.aux, gas);
   after(prof);
   before(prof, "visc_dt");
-  hipLaunchKernelGGL((k_visc<DIM, 2>), grid, block, 0, s, G, A.U, A.aux, A.d,
+  hipLaunchKernelGGL((k_visc<DIM, 2, SEV>), grid, block, 0, s, G, A.U, A.aux, A.d,
                      A.alpha, gas);
   after(prof);
   before(prof, "dt_partial");
@@ -941,8 +1030,13 @@ void launch_dt_only(int dim, const Gas &gas, const DevGraph &g,
                     const StageArgs &a, double cfl, hipStream_t s,
                     void (*before)(void *, const char *), void (*after)(void *),
                     void *prof) {
-  if (dim == 2) dt_impl<2>(gas, g, a, cfl, s, before, after, prof);
-  else dt_impl<3>(gas, g, a, cfl, s, before, after, prof);
+  if (dim == 2) {
+    if (gas.seven) dt_impl<2, 1>(gas, g, a, cfl, s, before, after, prof);
+    else dt_impl<2, 0>(gas, g, a, cfl, s, before, after, prof);
+  } else {
+    if (gas.seven) dt_impl<3, 1>(gas, g, a, cfl, s, before, after, prof);
+    else dt_impl<3, 0>(gas, g, a, cfl, s, before, after, prof);
+  }
 }
 
 void launch_stage(int dim, const Gas &gas, const DevGraph &g,
@@ -950,12 +1044,16 @@ void launch_stage(int dim, const Gas &gas, const DevGraph &g,
                   bool auto_dt, double cfl, hipStream_t s,
                   void (*before)(void *, const char *), void (*after)(void *),
                   void *prof) {
-  if (dim == 2)
-    stage_impl<2>(gas, g, a, indicator, limiter, passes, auto_dt, cfl, s, before,
-                  after, prof);
-  else
-    stage_impl<3>(gas, g, a, indicator, limiter, passes, auto_dt, cfl, s, before,
-                  after, prof);
+  auto run = [&](auto impl) {
+    impl(gas, g, a, indicator, limiter, passes, auto_dt, cfl, s, before, after, prof);
+  };
+  if (dim == 2) {
+    if (gas.seven) run(stage_impl<2, 1>);
+    else run(stage_impl<2, 0>);
+  } else {
+    if (gas.seven) run(stage_impl<3, 1>);
+    else run(stage_impl<3, 0>);
+  }
 }
 
 void launch_slip(int dim, int64_t N, int nslip, const int32_t *idx,
