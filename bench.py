@@ -30,40 +30,49 @@ from paper_2106_02159_amd import abi, workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes per node per launch of each kernel (FP64, sliced ELL
-# with int32 columns and uint8 transpose slots; every array a kernel touches
-# counted once; W = 3^d slots, nc = d + 2 components).
-def kernel_bytes(name: str, dim: int) -> float:
+# Algorithmic bytes per node per launch of each kernel (sliced ELL with int32
+# columns and uint8 transpose slots; every array a kernel touches counted
+# once; W = 3^d slots, nc = d + 2 components).  With `mixed`, the graph
+# coefficients m_ij, c_ij and alpha, d_ij, F^H and the limiter coefficients
+# are 4-byte values; everything else is FP64.
+def kernel_bytes(name: str, dim: int, mixed: bool = False) -> float:
     Wd = 3 ** dim
     nc = dim + 2
     na = dim + 5
-    col, trk, edge = 4 * Wd, 1 * Wd, 8 * Wd
-    cvec = 8 * dim * Wd
-    node = 8
+    L = 4 if mixed else 8          # storage of the FP32-capable arrays
+    col, trk = 4 * Wd, 1 * Wd
+    eL = L * Wd                    # one per-edge array (d, m_ij, l)
+    cL = L * dim * Wd              # c_ij
+    n8, nL = 8, L
+    rows = nc * (2 * n8 + nL)      # U, U^L (or U^(1)) and F^H of the row
     table = {
-        "prim": nc * node + na * node,
-        "visc": col + cvec + trk / 2 + nc * node + (na - 1) * node + 1 + edge + node,
-        "visc_dt": col + cvec + trk / 2 + (dim + 3) * node + 1 + edge,
-        "dt_partial": col + edge + node,
-        "lo": col + cvec + edge + nc * node + (dim + 2) * node + node + 3 * node
-              + 2 * nc * node + 3 * node,
-        "lim1": col + 2 * edge + 3 * nc * node + 3 * node + 3 * node + edge,
-        "lim2": col + trk + 3 * edge + 3 * nc * node + 3 * node + 3 * node
-                + nc * node + edge,
-        "fin": col + trk + 4 * edge + 4 * nc * node + 3 * node + nc * node,
-        "combine": 2 * nc * node + nc * node,
+        "prim": nc * n8 + na * n8,
+        "visc": col + cL + trk / 2 + nc * n8 + (na - 1) * n8 + 1 + eL + nL,
+        "visc_dt": col + cL + trk / 2 + (dim + 3) * n8 + 1 + eL,
+        "dt_partial": col + eL + n8,
+        "lo": col + cL + eL + nc * n8 + (dim + 2) * n8 + nL + 3 * n8
+              + nc * n8 + nc * nL + 3 * n8,
+        "lim1": col + 2 * eL + rows + nL + 2 * n8 + 3 * n8 + eL,
+        "lim2": (col + trk + 3 * eL + rows + nL + 2 * n8 + 3 * n8 + nc * n8 + eL
+                 if dim == 2 else  # 3D: pass-1 update only
+                 col + trk + 3 * eL + rows + nL + 2 * n8 + nc * n8),
+        "lim2b": col + trk + 3 * eL + rows + nL + 2 * n8 + 3 * n8 + eL,
+        "fin": col + trk + 4 * eL + nc * (3 * n8 + nL) + nL + 2 * n8 + nc * n8,
+        "combine": 2 * nc * n8 + nc * n8,
         "slip": 0.0,
         "dt_final": 0.0,
     }
     return float(table.get(name, 0.0))
 
 
-def stage_algorithmic_bytes(dim: int) -> float:
+def stage_algorithmic_bytes(dim: int, mixed: bool = False) -> float:
     """Bytes per node per forward-Euler stage if the graph (col, c_ij, m_ij,
-    m_i) and the state were each moved once: 345 B in 2D, 1087 B in 3D."""
+    m_i) and the state were each moved once: 345 B in 2D, 1087 B in 3D
+    (237 B and 655 B with c_ij and m_ij in FP32)."""
     Wd = 3 ** dim
     nc = dim + 2
-    return 4 * Wd + 8 * dim * Wd + 8 * Wd + 8 + 2 * 8 * nc + 8 * nc * 2 / 3
+    L = 4 if mixed else 8
+    return 4 * Wd + L * dim * Wd + L * Wd + 8 + 2 * 8 * nc + 8 * nc * 2 / 3
 
 
 def source_sha() -> str:
@@ -144,6 +153,12 @@ def main():
                     help="Navier-Stokes: Strang steps (hyperbolic tau, parabolic "
                          "2 tau, hyperbolic tau) with mu = 1e-4, lambda = 0, "
                          "kappa = 1.4e-4, cv = 1/(gamma-1), CG rtol 1e-10")
+    ap.add_argument("--mixed", action="store_true",
+                    help="mixed precision: FP32 storage of the graph coefficients "
+                         "and of alpha, d_ij, F^H and the limiter coefficients, "
+                         "FP64 state and arithmetic; after the timed steps the FP64 "
+                         "path is run with the same time steps and the L1 relative "
+                         "error is reported")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="oracle sample, nodes per direction (default 1024 in "
@@ -160,7 +175,8 @@ def main():
     t0 = time.perf_counter()
     mesh, U = workload(dim, n, args.seed)
     graph = abi.Graph(mesh)
-    solver = abi.Solver(graph, gamma=1.4, cfl=0.5)
+    solver = abi.Solver(graph, gamma=1.4, cfl=0.5,
+                        precision=abi.PREC_MIXED if args.mixed else abi.PREC_FP64)
     solver.set_state(U)
     del U
     if args.ns:
@@ -175,9 +191,12 @@ def main():
     solver.profile(True)
     solver.sync()
     cg_iters = []
+    taus = []
+    U_warm = solver.get_state() if args.mixed else None
+    solver.sync()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        advance()
+        taus.append(advance())
         if args.ns:
             info = solver.parabolic_info()
             cg_iters.append((info.it_v, info.it_e, info.it_l, info.fct))
@@ -197,18 +216,19 @@ def main():
     stages_per_step = 6 if args.ns else 3
     stages = stages_per_step * args.steps
     value = N * stages / elapsed
-    tag = f"{dim}d_{n}"
+    tag = f"{dim}d_{n}" + ("_mixed" if args.mixed else "") + ("_ns" if args.ns else "")
     # dominant kernel by summed time
     dom = max(rep.items(), key=lambda kv: kv[1][1])
     dname, (dlaunch, dms) = dom
     avg_s = dms / dlaunch * 1e-3
-    kb = kernel_bytes(dname, dim) * N
+    kb = kernel_bytes(dname, dim, args.mixed) * N
     achieved = kb / avg_s / 1e9
     kern = {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1),
-                "algorithmic_GBs": kernel_bytes(k, dim) * N / (v[1] / max(v[0], 1) * 1e-3) / 1e9
-                if kernel_bytes(k, dim) > 0 else None}
+                "algorithmic_GBs": kernel_bytes(k, dim, args.mixed) * N
+                / (v[1] / max(v[0], 1) * 1e-3) / 1e9
+                if kernel_bytes(k, dim, args.mixed) > 0 else None}
             for k, v in rep.items()}
-    stage_frac = stage_algorithmic_bytes(dim) * value / (HBM_PEAK_GBS * 1e9)
+    stage_frac = stage_algorithmic_bytes(dim, args.mixed) * value / (HBM_PEAK_GBS * 1e9)
     out = {
         "metric": "DoF-updates/s per SSP-RK stage",
         "value": value,
@@ -232,6 +252,8 @@ def main():
                        f"2D Euler gamma=1.4, Q1 {n}x{n} nodes on [0,1]^2, "
                        f"reflecting walls, seeded four-quadrant Riemann data "
                        f"(seed {args.seed}), SSPRK3 + 2-pass convex limiting, CFL 0.5"
+                       + (", mixed precision (FP32 storage of m_ij, c_ij, alpha, "
+                          "d_ij, F^H, limiter coefficients)" if args.mixed else "")
                        if dim == 2 else
                        f"3D Euler gamma=1.4 (hyperbolic step of the Navier-Stokes "
                        f"configuration), Q1 {n}^3 nodes on [0,1]^3, reflecting walls, "
@@ -249,6 +271,25 @@ def main():
         "setup_s": setup_s,
         "device_bytes": solver.device_bytes(),
     }
+    if args.mixed:
+        # the FP64 path (parity-tested against the oracle) from the same state
+        # with the same time steps
+        U_mp = solver.get_state()
+        solver.close()
+        ref = abi.Solver(graph, gamma=1.4, cfl=0.5, precision=abi.PREC_FP64)
+        ref.set_state(U_warm, project=False)
+        for t in taus:
+            ref.step(t)
+        U_64 = ref.get_state()
+        ref.close()
+        nrm = lambda a: float(np.abs(a).sum())
+        out["error_vs_fp64"] = {
+            "rho": nrm(U_mp[0] - U_64[0]) / nrm(U_64[0]),
+            "m": nrm(U_mp[1:1 + dim] - U_64[1:1 + dim]) / nrm(U_64[1:1 + dim]),
+            "E": nrm(U_mp[dim + 1] - U_64[dim + 1]) / nrm(U_64[dim + 1]),
+            "steps": args.steps, "norm": "L1 relative",
+            "reference": "the FP64 path of this library on the same time steps"}
+        out["dtype"] = "f64 (f32 storage)"
     if args.ns:
         out["cg_iterations"] = {"velocity": [c[0] for c in cg_iters],
                                 "energy": [c[1] for c in cg_iters],

@@ -109,7 +109,16 @@ typedef struct ns_params {
                      rho in [(1-r_i) rho_min, (1+r_i) rho_max] and
                      Phi >= (1-r_i) Phi_min, r_i = r0 (m_i/|Omega|)^(3/(2d));
                      0 = the strict bounds of Sec. 3.3                      */
+  int precision;  /* NS_PREC_FP64, or NS_PREC_MIXED: the graph coefficients
+                     m_ij, c_ij and the intermediates alpha_i, d^L_ij, F^H_i
+                     and the limiter coefficients are stored in FP32 (d_ij
+                     rounded up, so it stays an upper bound of the wave-speed
+                     term; limiter coefficients rounded down, so they stay
+                     feasible); the state, the bounds, the line search and
+                     all arithmetic stay FP64                               */
 } ns_params;
+
+enum { NS_PREC_FP64 = 0, NS_PREC_MIXED = 1 };
 
 typedef struct ns_solver ns_solver;
 

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libns.so")
 NS_OK, NS_EINVAL, NS_ENOMEM, NS_EHIP = 0, -1, -2, -3
 NS_ENOTADMISSIBLE, NS_ECFL, NS_EBOUNDS, NS_ESTATE, NS_ECG = -4, -5, -6, -7, -8
 FCT_AUTO, FCT_ALWAYS = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
 IND_ENTROPY, IND_ONE, IND_ZERO = 0, 1, 2
 LIM_CONVEX, LIM_LOW, LIM_HIGH = 0, 1, 2
 ON_DEVICE, NO_PROJECT = 1, 2
@@ -51,7 +52,7 @@ class MeshDesc(C.Structure):
 class Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("cfl", C.c_double),
                 ("indicator", C.c_int), ("limiter", C.c_int), ("passes", C.c_int),
-                ("relax", C.c_double)]
+                ("relax", C.c_double), ("precision", C.c_int)]
 
 
 _lib = None
@@ -176,10 +177,11 @@ class Solver:
     """ns_solver_create and the per-solver calls."""
 
     def __init__(self, graph: Graph, gamma=1.4, cfl=0.5, indicator=IND_ENTROPY,
-                 limiter=LIM_CONVEX, passes=2, relax=1.0, stream=None):
+                 limiter=LIM_CONVEX, passes=2, relax=1.0, precision=PREC_FP64,
+                 stream=None):
         L = lib()
         self.graph = graph  # keep alive
-        self.prm = Params(gamma, cfl, indicator, limiter, passes, relax)
+        self.prm = Params(gamma, cfl, indicator, limiter, passes, relax, precision)
         h = C.c_void_p()
         rc = L.ns_solver_create(graph.h, C.byref(self.prm),
                                 C.c_void_p(stream) if stream else None, C.byref(h))

@@ -26,6 +26,8 @@ double S(int dim, const double *h, int p, int q, int a, int b) {
 
 }  // namespace
 
+void build_interior_stencils(Q1Tables *t);
+
 void build_q1_tables(int dim, const double *h, double mu, double lambda,
                      double kappa_over_cv, Q1Tables *t) {
   const int n = 1 << dim;
@@ -71,6 +73,37 @@ void build_q1_tables(int dim, const double *h, double mu, double lambda,
         t->dphi[((size_t)q * n + a) * dim + p] = d;
       }
     }
+  build_interior_stencils(t);
+}
+
+namespace {
+// neighbourhood slot of local node b seen from local node a of the same cell
+int slot_of(int dim, int a, int b) {
+  int s = 0, m = 1;
+  for (int d = 0; d < dim; ++d) {
+    s += (((b >> d) & 1) - ((a >> d) & 1) + 1) * m;
+    m *= 3;
+  }
+  return s;
+}
+}  // namespace
+
+void build_interior_stencils(Q1Tables *t) {
+  const int dim = t->dim, n = t->nloc;
+  int S = 1;
+  for (int d = 0; d < dim; ++d) S *= 3;
+  t->stencil_stress.assign((size_t)S * dim * dim, 0.0);
+  t->stencil_heat.assign((size_t)S, 0.0);
+  // node i is local node a of one of its 2^dim cells; b runs over that cell
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      const int s = slot_of(dim, a, b);
+      t->stencil_heat[s] += t->heat[(size_t)a * n + b];
+      for (int k = 0; k < dim; ++k)
+        for (int l = 0; l < dim; ++l)
+          t->stencil_stress[((size_t)s * dim + k) * dim + l] +=
+              t->stress[(((size_t)k * dim + l) * n + a) * n + b];
+    }
 }
 
 std::vector<double> Q1Tables::packed() const {
@@ -81,6 +114,8 @@ std::vector<double> Q1Tables::packed() const {
   v.insert(v.end(), phi.begin(), phi.end());
   v.insert(v.end(), dphi.begin(), dphi.end());
   v.push_back(w);
+  v.insert(v.end(), stencil_stress.begin(), stencil_stress.end());
+  v.insert(v.end(), stencil_heat.begin(), stencil_heat.end());
   return v;
 }
 

@@ -32,12 +32,20 @@ struct Q1Tables {
   // all points), phi[q*nloc + a], dphi[(q*nloc + a)*dim + p]
   double w = 0.0;
   std::vector<double> phi, dphi;
+  // The operators' rows at a node all of whose 2^dim cells exist, summed
+  // over the cells: stencil_stress[(s*dim + k)*dim + l] couples component k
+  // of the node with component l of its neighbour in slot s (offset
+  // o_d = (s / 3^d) % 3 - 1), stencil_heat[s] likewise.
+  std::vector<double> stencil_stress, stencil_heat;
 
-  // layout of the single device table: stress | heat | phi | dphi | w
+  // layout of the single device table:
+  // stress | heat | phi | dphi | w | stencil_stress | stencil_heat
   std::size_t off_heat() const { return stress.size(); }
   std::size_t off_phi() const { return off_heat() + heat.size(); }
   std::size_t off_dphi() const { return off_phi() + phi.size(); }
   std::size_t off_w() const { return off_dphi() + dphi.size(); }
+  std::size_t off_sst() const { return off_w() + 1; }
+  std::size_t off_sht() const { return off_sst() + stencil_stress.size(); }
   std::vector<double> packed() const;
 };
 

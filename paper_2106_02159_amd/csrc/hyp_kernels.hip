@@ -83,15 +83,27 @@ __device__ __forceinline__ int64_t plain_id() {
   return (int64_t)blockIdx.x * kBlock + threadIdx.x;
 }
 
-template <int DIM>
-__device__ __forceinline__ void load_c(const DevGraph &G, int64_t e, double *c) {
+// FP64 value to the storage type: nearest, upwards (graph viscosity stays an
+// upper bound) or downwards (a limiter coefficient stays feasible)
+template <typename LT> __device__ __forceinline__ LT to_lt(double x) { return (LT)x; }
+template <typename LT> __device__ __forceinline__ LT to_lt_up(double x) {
+  if constexpr (sizeof(LT) == 4) return __double2float_ru(x);
+  else return x;
+}
+template <typename LT> __device__ __forceinline__ LT to_lt_down(double x) {
+  if constexpr (sizeof(LT) == 4) return __double2float_rd(x);
+  else return x;
+}
+
+template <int DIM, typename LT>
+__device__ __forceinline__ void load_c(const DevGraphT<LT> &G, int64_t e, double *c) {
   c[0] = G.c0[e];
   c[1] = G.c1[e];
   if constexpr (DIM == 3) c[2] = G.c2[e];
 }
 
-template <int NC>
-__device__ __forceinline__ void load_state(const double *__restrict__ U,
+template <int NC, typename T>
+__device__ __forceinline__ void load_state(const T *__restrict__ U,
                                            int64_t N, int64_t i, double *u) {
 #pragma unroll
   for (int q = 0; q < NC; ++q) u[q] = U[q * N + i];
@@ -161,12 +173,12 @@ __global__ __launch_bounds__(kBlock) void k_prim(int64_t N,
 // gathers its neighbour data unconditionally (absent entries read row i
 // itself) so that the loads of a chunk are in flight together, and the
 // arithmetic is predicated on the entry being present.
-template <int DIM, int IND, int SEV>
-__global__ __launch_bounds__(kBlock) void k_visc(DevGraph G,
+template <int DIM, int IND, int SEV, typename LT>
+__global__ __launch_bounds__(kBlock) void k_visc(DevGraphT<LT> G,
                                                  const double *__restrict__ U,
                                                  const double *__restrict__ aux,
-                                                 double *__restrict__ d,
-                                                 double *__restrict__ alpha,
+                                                 LT *__restrict__ d,
+                                                 LT *__restrict__ alpha,
                                                  Gas g) {
   using X = Aux<DIM>;
   using C = Cfg<DIM, NS_CH_VISC>;
@@ -274,21 +286,22 @@ __global__ __launch_bounds__(kBlock) void k_visc(DevGraph G,
           }
           dij = fmax(dij, lambda_max<SEV>(g, uLt, pj[kk], aj[kk], bj[kk], uRt, pi, ai, bi) * ctn);
         }
-        d[e] = dij;
-        d[et] = dij;
+        const LT dst = to_lt_up<LT>(dij);
+        d[e] = dst;
+        d[et] = dst;
       }
     }
   }
-  if constexpr (IND == 0) alpha[i] = fabs(num) / (den + 1e-2 * scl);
-  else if constexpr (IND == 1) alpha[i] = 1.0;
-  else alpha[i] = 0.0;
+  if constexpr (IND == 0) alpha[i] = to_lt<LT>(fabs(num) / (den + 1e-2 * scl));
+  else if constexpr (IND == 1) alpha[i] = LT(1);
+  else alpha[i] = LT(0);
 }
 
 // ---------------------------------------------------------------------------
 // Time step: per-block min of m_i / (2 sum_{j != i} d_ij) = -m_i / (2 d_ii).
-template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_dt_partial(DevGraph G,
-                                                       const double *__restrict__ d,
+template <int DIM, typename LT>
+__global__ __launch_bounds__(kBlock) void k_dt_partial(DevGraphT<LT> G,
+                                                       const LT *__restrict__ d,
                                                        double *__restrict__ partial) {
   using C = Cfg<DIM>;
   const int64_t N = G.N;
@@ -327,8 +340,8 @@ __global__ __launch_bounds__(1024) void k_dt_final(const double *__restrict__ pa
 
 // ---------------------------------------------------------------------------
 // Low-order update, bounds and high-order flux (stored divided by m_i).
-template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_lo(DevGraph G, StageArgs A, Gas g) {
+template <int DIM, typename LT>
+__global__ __launch_bounds__(kBlock) void k_lo(DevGraphT<LT> G, StageArgsT<LT> A, Gas g) {
   using X = Aux<DIM>;
   using C = Cfg<DIM, NS_CH_LO>;
   constexpr int NC = C::NC;
@@ -341,8 +354,8 @@ __global__ __launch_bounds__(kBlock) void k_lo(DevGraph G, StageArgs A, Gas g) {
   }
   const double *__restrict__ U = A.U;
   const double *__restrict__ aux = A.aux;
-  const double *__restrict__ alpha = A.alpha;
-  const double *__restrict__ dd = A.d;
+  const LT *__restrict__ alpha = A.alpha;
+  const LT *__restrict__ dd = A.d;
   const int32_t *__restrict__ colp = G.col;
   const RowIdx<DIM, int32_t> jv(colp, i);
   double ui[NC], vi[DIM];
@@ -411,7 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_lo(DevGraph G, StageArgs A, Gas g) {
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
     A.UL[q * N + i] = ui[q] + tm * acc[q];
-    A.FH[q * N + i] = fh[q] * rmi;
+    A.FH[q * N + i] = to_lt<LT>(fh[q] * rmi);
   }
   if (A.check_cfl && tau > G.mi[i] / (2.0 * dsum)) A.flags[0] = 1;
   const double r = G.rrel[i];
@@ -430,8 +443,8 @@ struct RowCtx {
   double ali, coef;
 };
 
-template <int DIM>
-__device__ __forceinline__ void load_row(const DevGraph &G, const StageArgs &A,
+template <int DIM, typename LT>
+__device__ __forceinline__ void load_row(const DevGraphT<LT> &G, const StageArgsT<LT> &A,
                                          int64_t i, double tau, RowCtx<DIM> &R) {
   constexpr int NC = DIM + 2;
   const int64_t N = G.N;
@@ -449,8 +462,8 @@ struct PIn {
   double u[NC], f[NC], al, d, m;
 };
 
-template <int DIM>
-__device__ __forceinline__ void gather_P(const DevGraph &G, const StageArgs &A,
+template <int DIM, typename LT>
+__device__ __forceinline__ void gather_P(const DevGraphT<LT> &G, const StageArgsT<LT> &A,
                                          int64_t e, int64_t js, PIn<DIM> &x) {
   constexpr int NC = DIM + 2;
   const int64_t N = G.N;
@@ -471,8 +484,8 @@ __device__ __forceinline__ void make_P(const RowCtx<DIM> &R, const PIn<DIM> &x,
     P[q] = R.coef * (x.m * (R.fi[q] - x.f[q]) + (dH - x.d) * (x.u[q] - R.ui[q]));
 }
 
-template <int DIM>
-__device__ __forceinline__ void compute_P(const DevGraph &G, const StageArgs &A,
+template <int DIM, typename LT>
+__device__ __forceinline__ void compute_P(const DevGraphT<LT> &G, const StageArgsT<LT> &A,
                                           const RowCtx<DIM> &R, int64_t e,
                                           int32_t j, double *P) {
   PIn<DIM> x;
@@ -480,8 +493,8 @@ __device__ __forceinline__ void compute_P(const DevGraph &G, const StageArgs &A,
   make_P<DIM>(R, x, P);
 }
 
-template <int DIM>
-__device__ __forceinline__ void finish(const DevGraph &G, const StageArgs &A,
+template <int DIM, typename LT>
+__device__ __forceinline__ void finish(const DevGraphT<LT> &G, const StageArgsT<LT> &A,
                                        int64_t i, const double *u) {
   constexpr int NC = DIM + 2;
   const int64_t N = G.N;
@@ -508,7 +521,8 @@ struct Bounds {
   double rmin, rmax, pmin, pmin5;
 };
 
-__device__ __forceinline__ Bounds load_bounds(const StageArgs &A, int64_t N,
+template <typename LT>
+__device__ __forceinline__ Bounds load_bounds(const StageArgsT<LT> &A, int64_t N,
                                               int64_t i) {
   Bounds b;
   b.rmin = A.bnds[i];
@@ -541,8 +555,8 @@ __device__ __forceinline__ int limit_fast(const Gas &g, const double *u,
   return 1;  // root of psi in (0, lr) still to be found
 }
 
-template <int DIM, int SEV>
-__global__ __launch_bounds__(kBlock) void k_lim1(DevGraph G, StageArgs A, Gas g) {
+template <int DIM, int SEV, typename LT>
+__global__ __launch_bounds__(kBlock) void k_lim1(DevGraphT<LT> G, StageArgsT<LT> A, Gas g) {
   using C = Cfg<DIM, NS_CH_LIM1>;
   constexpr int NC = C::NC;
   const int64_t N = G.N;
@@ -555,7 +569,7 @@ __global__ __launch_bounds__(kBlock) void k_lim1(DevGraph G, StageArgs A, Gas g)
   double ul[NC];
   load_state<NC>(A.UL, N, i, ul);
   const Bounds b = load_bounds(A, N, i);
-  double *__restrict__ lt1 = A.lt1;
+  LT *__restrict__ lt1 = A.lt1;
   uint32_t slow = 0;
 #pragma unroll
   for (int ch = 0; ch < C::NCH; ++ch) {
@@ -574,7 +588,7 @@ __global__ __launch_bounds__(kBlock) void k_lim1(DevGraph G, StageArgs A, Gas g)
       double P[NC], l;
       make_P<DIM>(R, x[kk], P);
       if (limit_fast<DIM, SEV>(g, ul, P, b, &l)) slow |= 1u << k;
-      lt1[eidx<DIM>(k, i)] = l;
+      lt1[eidx<DIM>(k, i)] = to_lt_down<LT>(l);
     }
   }
   if (slow) {
@@ -591,8 +605,8 @@ __global__ __launch_bounds__(kBlock) void k_lim1(DevGraph G, StageArgs A, Gas g)
 // pass, final; 2: l = 1 (unlimited high order), final; 3: convex, pass-1
 // update only (3D: the pass-2 search is k_lim2b, since both in one kernel
 // need more registers than a SIMD lane has).
-template <int DIM, int MODE, int SEV>
-__global__ __launch_bounds__(kBlock) void k_lim2(DevGraph G, StageArgs A, Gas g) {
+template <int DIM, int MODE, int SEV, typename LT>
+__global__ __launch_bounds__(kBlock) void k_lim2(DevGraphT<LT> G, StageArgsT<LT> A, Gas g) {
   using C = Cfg<DIM, NS_CH_LIM2>;
   constexpr int NC = C::NC;
   const int64_t N = G.N;
@@ -600,7 +614,7 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraph G, StageArgs A, Gas g)
   if (i >= N) return;
   const int32_t *__restrict__ colp = G.col;
   const uint8_t *__restrict__ trkp = G.trk;
-  const double *__restrict__ lt1 = A.lt1;
+  const LT *__restrict__ lt1 = A.lt1;
   const RowIdx<DIM, int32_t> colk(colp, i);
   const RowIdx<DIM, uint8_t> trkk(trkp, i);
   RowCtx<DIM> R;
@@ -654,7 +668,7 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraph G, StageArgs A, Gas g)
 #pragma unroll
     for (int q = 0; q < NC; ++q) A.U1[q * N + i] = u1[q];
     const Bounds b = load_bounds(A, N, i);
-    double *__restrict__ lt2 = A.lt2;
+    LT *__restrict__ lt2 = A.lt2;
     uint32_t slow = 0;
     if constexpr (!CACHE) {
       // reload the neighbour data rather than keep a whole row of it live
@@ -702,7 +716,7 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraph G, StageArgs A, Gas g)
 #pragma unroll
         for (int q = 0; q < NC; ++q) P[kk][q] *= (1.0 - l[kk]);
         if (limit_fast<DIM, SEV>(g, u1, P[kk], b, &l2)) slow |= 1u << k;
-        lt2[eidx<DIM>(k, i)] = l2;
+        lt2[eidx<DIM>(k, i)] = to_lt_down<LT>(l2);
       }
     }
     if (slow) {
@@ -717,8 +731,8 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraph G, StageArgs A, Gas g)
 }
 
 // Pass-2 line search on (1 - l_ij) P_ij from U^(1) (stored by k_lim2<3>).
-template <int DIM, int SEV>
-__global__ __launch_bounds__(kBlock) void k_lim2b(DevGraph G, StageArgs A, Gas g) {
+template <int DIM, int SEV, typename LT>
+__global__ __launch_bounds__(kBlock) void k_lim2b(DevGraphT<LT> G, StageArgsT<LT> A, Gas g) {
   using C = Cfg<DIM, NS_CH_LIM2>;
   constexpr int NC = C::NC;
   const int64_t N = G.N;
@@ -726,8 +740,8 @@ __global__ __launch_bounds__(kBlock) void k_lim2b(DevGraph G, StageArgs A, Gas g
   if (i >= N) return;
   const int32_t *__restrict__ colp = G.col;
   const uint8_t *__restrict__ trkp = G.trk;
-  const double *__restrict__ lt1 = A.lt1;
-  double *__restrict__ lt2 = A.lt2;
+  const LT *__restrict__ lt1 = A.lt1;
+  LT *__restrict__ lt2 = A.lt2;
   RowCtx<DIM> R;
   load_row<DIM>(G, A, i, *A.tau, R);
   double u1[NC];
@@ -759,7 +773,7 @@ __global__ __launch_bounds__(kBlock) void k_lim2b(DevGraph G, StageArgs A, Gas g
 #pragma unroll
       for (int q = 0; q < NC; ++q) P[q] *= (1.0 - l);
       if (limit_fast<DIM, SEV>(g, u1, P, b, &l2)) slow |= 1u << k;
-      lt2[eidx<DIM>(k, i)] = l2;
+      lt2[eidx<DIM>(k, i)] = to_lt_down<LT>(l2);
     }
   }
   if (slow) {
@@ -783,13 +797,13 @@ __device__ __forceinline__ int64_t edge_row(int64_t e) {
 // one lane per listed entry, grid-stride over the list, so the rare root
 // finder runs at full occupancy instead of stalling a row sweep's wavefront.
 // The line search's density limit l_rho was stored in lt by the sweep.
-template <int DIM, int PASS, int SEV>
-__global__ __launch_bounds__(kBlock) void k_root(DevGraph G, StageArgs A, Gas g) {
+template <int DIM, int PASS, int SEV, typename LT>
+__global__ __launch_bounds__(kBlock) void k_root(DevGraphT<LT> G, StageArgsT<LT> A, Gas g) {
   constexpr int NC = DIM + 2;
   const int64_t N = G.N;
   const uint32_t n = A.qcnt[PASS - 1];
   const uint32_t *__restrict__ q = A.q;
-  double *__restrict__ lt = PASS == 1 ? A.lt1 : A.lt2;
+  LT *__restrict__ lt = PASS == 1 ? A.lt1 : A.lt2;
   const double tau = *A.tau;
   for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < n;
        t += gridDim.x * kBlock) {
@@ -807,12 +821,12 @@ __global__ __launch_bounds__(kBlock) void k_root(DevGraph G, StageArgs A, Gas g)
 #pragma unroll
       for (int c = 0; c < NC; ++c) P[c] *= (1.0 - l);
     }
-    lt[e] = entropy_root_fast<DIM, SEV>(g, u, P, lt[e], b.pmin, b.pmin5);
+    lt[e] = to_lt_down<LT>(entropy_root_fast<DIM, SEV>(g, u, P, lt[e], b.pmin, b.pmin5));
   }
 }
 
-template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_fin(DevGraph G, StageArgs A, Gas g) {
+template <int DIM, typename LT>
+__global__ __launch_bounds__(kBlock) void k_fin(DevGraphT<LT> G, StageArgsT<LT> A, Gas g) {
   using C = Cfg<DIM, NS_CH_FIN>;
   constexpr int NC = C::NC;
   const int64_t N = G.N;
@@ -820,8 +834,8 @@ __global__ __launch_bounds__(kBlock) void k_fin(DevGraph G, StageArgs A, Gas g) 
   if (i >= N) return;
   const int32_t *__restrict__ colp = G.col;
   const uint8_t *__restrict__ trkp = G.trk;
-  const double *__restrict__ lt1 = A.lt1;
-  const double *__restrict__ lt2 = A.lt2;
+  const LT *__restrict__ lt1 = A.lt1;
+  const LT *__restrict__ lt2 = A.lt2;
   const RowIdx<DIM, int32_t> jv(colp, i);
   const RowIdx<DIM, uint8_t> tv(trkp, i);
   RowCtx<DIM> R;
@@ -862,8 +876,8 @@ __global__ __launch_bounds__(kBlock) void k_fin(DevGraph G, StageArgs A, Gas g) 
   finish<DIM>(G, A, i, u2);
 }
 
-template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_combine_low(DevGraph G, StageArgs A) {
+template <int DIM, typename LT>
+__global__ __launch_bounds__(kBlock) void k_combine_low(DevGraphT<LT> G, StageArgsT<LT> A) {
   constexpr int NC = DIM + 2;
   const int64_t i = row_id();
   if (i >= G.N) return;
@@ -938,8 +952,8 @@ __global__ __launch_bounds__(kBlock) void k_check_state(int64_t N,
 
 inline dim3 grid_for(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
 
-template <int DIM, int SEV>
-void stage_impl(const Gas &gas, const DevGraph &G, const StageArgs &A,
+template <int DIM, int SEV, typename LT>
+void stage_impl(const Gas &gas, const DevGraphT<LT> &G, const StageArgsT<LT> &A,
                 int indicator, int limiter, int passes, bool auto_dt,
                 double cfl, hipStream_t s, void (*before)(void *, const char *),
                 void (*after)(void *), void *prof) {
@@ -953,58 +967,58 @@ void stage_impl(const Gas &gas, const DevGraph &G, const StageArgs &A,
   NS_LAUNCH("prim", hipLaunchKernelGGL(k_prim<DIM>, grid, block, 0, s, G.N, A.U,
                                        A.aux, gas));
   if (indicator == 0)
-    NS_LAUNCH("visc", hipLaunchKernelGGL((k_visc<DIM, 0, SEV>), grid, block, 0, s, G,
+    NS_LAUNCH("visc", hipLaunchKernelGGL((k_visc<DIM, 0, SEV, LT>), grid, block, 0, s, G,
                                          A.U, A.aux, A.d, A.alpha, gas));
   else if (indicator == 1)
-    NS_LAUNCH("visc", hipLaunchKernelGGL((k_visc<DIM, 1, SEV>), grid, block, 0, s, G,
+    NS_LAUNCH("visc", hipLaunchKernelGGL((k_visc<DIM, 1, SEV, LT>), grid, block, 0, s, G,
                                          A.U, A.aux, A.d, A.alpha, gas));
   else
-    NS_LAUNCH("visc", hipLaunchKernelGGL((k_visc<DIM, 2, SEV>), grid, block, 0, s, G,
+    NS_LAUNCH("visc", hipLaunchKernelGGL((k_visc<DIM, 2, SEV, LT>), grid, block, 0, s, G,
                                          A.U, A.aux, A.d, A.alpha, gas));
   if (auto_dt) {
-    NS_LAUNCH("dt_partial", hipLaunchKernelGGL(k_dt_partial<DIM>, grid, block, 0, s,
+    NS_LAUNCH("dt_partial", hipLaunchKernelGGL((k_dt_partial<DIM, LT>), grid, block, 0, s,
                                                G, A.d, A.partial));
     NS_LAUNCH("dt_final", hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1024), 0, s,
                                              A.partial, (int64_t)grid.x, cfl,
                                              A.tau));
   }
-  NS_LAUNCH("lo", hipLaunchKernelGGL(k_lo<DIM>, grid, block, 0, s, G, A, gas));
+  NS_LAUNCH("lo", hipLaunchKernelGGL((k_lo<DIM, LT>), grid, block, 0, s, G, A, gas));
   if (limiter == 1) {
-    NS_LAUNCH("combine", hipLaunchKernelGGL(k_combine_low<DIM>, grid, block, 0, s,
+    NS_LAUNCH("combine", hipLaunchKernelGGL((k_combine_low<DIM, LT>), grid, block, 0, s,
                                             G, A));
   } else if (limiter == 2) {
-    NS_LAUNCH("lim2", hipLaunchKernelGGL((k_lim2<DIM, 2, SEV>), grid, block, 0, s, G, A,
+    NS_LAUNCH("lim2", hipLaunchKernelGGL((k_lim2<DIM, 2, SEV, LT>), grid, block, 0, s, G, A,
                                          gas));
   } else {
     // the work lists hold a small fraction of the edges: a grid of a few
     // wavefronts per SIMD covers them in one or two passes
     const dim3 rgrid(std::min<unsigned>(grid.x, 1024u));
-    NS_LAUNCH("lim1", hipLaunchKernelGGL((k_lim1<DIM, SEV>), grid, block, 0, s, G, A, gas));
-    NS_LAUNCH("root1", hipLaunchKernelGGL((k_root<DIM, 1, SEV>), rgrid, block, 0, s, G,
+    NS_LAUNCH("lim1", hipLaunchKernelGGL((k_lim1<DIM, SEV, LT>), grid, block, 0, s, G, A, gas));
+    NS_LAUNCH("root1", hipLaunchKernelGGL((k_root<DIM, 1, SEV, LT>), rgrid, block, 0, s, G,
                                           A, gas));
     if (passes == 1) {
-      NS_LAUNCH("lim2", hipLaunchKernelGGL((k_lim2<DIM, 1, SEV>), grid, block, 0, s, G,
+      NS_LAUNCH("lim2", hipLaunchKernelGGL((k_lim2<DIM, 1, SEV, LT>), grid, block, 0, s, G,
                                            A, gas));
     } else {
       if constexpr (DIM == 2) {
-        NS_LAUNCH("lim2", hipLaunchKernelGGL((k_lim2<DIM, 0, SEV>), grid, block, 0, s,
+        NS_LAUNCH("lim2", hipLaunchKernelGGL((k_lim2<DIM, 0, SEV, LT>), grid, block, 0, s,
                                              G, A, gas));
       } else {
-        NS_LAUNCH("lim2", hipLaunchKernelGGL((k_lim2<DIM, 3, SEV>), grid, block, 0, s,
+        NS_LAUNCH("lim2", hipLaunchKernelGGL((k_lim2<DIM, 3, SEV, LT>), grid, block, 0, s,
                                              G, A, gas));
-        NS_LAUNCH("lim2b", hipLaunchKernelGGL((k_lim2b<DIM, SEV>), grid, block, 0, s,
+        NS_LAUNCH("lim2b", hipLaunchKernelGGL((k_lim2b<DIM, SEV, LT>), grid, block, 0, s,
                                               G, A, gas));
       }
-      NS_LAUNCH("root2", hipLaunchKernelGGL((k_root<DIM, 2, SEV>), rgrid, block, 0, s, G,
+      NS_LAUNCH("root2", hipLaunchKernelGGL((k_root<DIM, 2, SEV, LT>), rgrid, block, 0, s, G,
                                             A, gas));
-      NS_LAUNCH("fin", hipLaunchKernelGGL(k_fin<DIM>, grid, block, 0, s, G, A, gas));
+      NS_LAUNCH("fin", hipLaunchKernelGGL((k_fin<DIM, LT>), grid, block, 0, s, G, A, gas));
     }
   }
 #undef NS_LAUNCH
 }
 
-template <int DIM, int SEV>
-void dt_impl(const Gas &gas, const DevGraph &G, const StageArgs &A, double cfl,
+template <int DIM, int SEV, typename LT>
+void dt_impl(const Gas &gas, const DevGraphT<LT> &G, const StageArgsT<LT> &A, double cfl,
              hipStream_t s, void (*before)(void *, const char *),
              void (*after)(void *), void *prof) {
   const dim3 grid = grid_for(G.N), block(kBlock);
@@ -1012,11 +1026,11 @@ void dt_impl(const Gas &gas, const DevGraph &G, const StageArgs &A, double cfl,
   hipLaunchKernelGGL(k_prim<DIM>, grid, block, 0, s, G.N, A.U, A.aux, gas);
   after(prof);
   before(prof, "visc_dt");
-  hipLaunchKernelGGL((k_visc<DIM, 2, SEV>), grid, block, 0, s, G, A.U, A.aux, A.d,
+  hipLaunchKernelGGL((k_visc<DIM, 2, SEV, LT>), grid, block, 0, s, G, A.U, A.aux, A.d,
                      A.alpha, gas);
   after(prof);
   before(prof, "dt_partial");
-  hipLaunchKernelGGL(k_dt_partial<DIM>, grid, block, 0, s, G, A.d, A.partial);
+  hipLaunchKernelGGL((k_dt_partial<DIM, LT>), grid, block, 0, s, G, A.d, A.partial);
   after(prof);
   before(prof, "dt_final");
   hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1024), 0, s, A.partial,
@@ -1026,21 +1040,23 @@ void dt_impl(const Gas &gas, const DevGraph &G, const StageArgs &A, double cfl,
 
 }  // namespace
 
-void launch_dt_only(int dim, const Gas &gas, const DevGraph &g,
-                    const StageArgs &a, double cfl, hipStream_t s,
+template <typename LT>
+void launch_dt_only(int dim, const Gas &gas, const DevGraphT<LT> &g,
+                    const StageArgsT<LT> &a, double cfl, hipStream_t s,
                     void (*before)(void *, const char *), void (*after)(void *),
                     void *prof) {
   if (dim == 2) {
-    if (gas.seven) dt_impl<2, 1>(gas, g, a, cfl, s, before, after, prof);
-    else dt_impl<2, 0>(gas, g, a, cfl, s, before, after, prof);
+    if (gas.seven) dt_impl<2, 1, LT>(gas, g, a, cfl, s, before, after, prof);
+    else dt_impl<2, 0, LT>(gas, g, a, cfl, s, before, after, prof);
   } else {
-    if (gas.seven) dt_impl<3, 1>(gas, g, a, cfl, s, before, after, prof);
-    else dt_impl<3, 0>(gas, g, a, cfl, s, before, after, prof);
+    if (gas.seven) dt_impl<3, 1, LT>(gas, g, a, cfl, s, before, after, prof);
+    else dt_impl<3, 0, LT>(gas, g, a, cfl, s, before, after, prof);
   }
 }
 
-void launch_stage(int dim, const Gas &gas, const DevGraph &g,
-                  const StageArgs &a, int indicator, int limiter, int passes,
+template <typename LT>
+void launch_stage(int dim, const Gas &gas, const DevGraphT<LT> &g,
+                  const StageArgsT<LT> &a, int indicator, int limiter, int passes,
                   bool auto_dt, double cfl, hipStream_t s,
                   void (*before)(void *, const char *), void (*after)(void *),
                   void *prof) {
@@ -1048,13 +1064,30 @@ void launch_stage(int dim, const Gas &gas, const DevGraph &g,
     impl(gas, g, a, indicator, limiter, passes, auto_dt, cfl, s, before, after, prof);
   };
   if (dim == 2) {
-    if (gas.seven) run(stage_impl<2, 1>);
-    else run(stage_impl<2, 0>);
+    if (gas.seven) run(stage_impl<2, 1, LT>);
+    else run(stage_impl<2, 0, LT>);
   } else {
-    if (gas.seven) run(stage_impl<3, 1>);
-    else run(stage_impl<3, 0>);
+    if (gas.seven) run(stage_impl<3, 1, LT>);
+    else run(stage_impl<3, 0, LT>);
   }
 }
+
+template void launch_stage<double>(int, const Gas &, const DevGraphT<double> &,
+                                   const StageArgsT<double> &, int, int, int, bool,
+                                   double, hipStream_t, void (*)(void *, const char *),
+                                   void (*)(void *), void *);
+template void launch_stage<float>(int, const Gas &, const DevGraphT<float> &,
+                                  const StageArgsT<float> &, int, int, int, bool,
+                                  double, hipStream_t, void (*)(void *, const char *),
+                                  void (*)(void *), void *);
+template void launch_dt_only<double>(int, const Gas &, const DevGraphT<double> &,
+                                     const StageArgsT<double> &, double, hipStream_t,
+                                     void (*)(void *, const char *), void (*)(void *),
+                                     void *);
+template void launch_dt_only<float>(int, const Gas &, const DevGraphT<float> &,
+                                    const StageArgsT<float> &, double, hipStream_t,
+                                    void (*)(void *, const char *), void (*)(void *),
+                                    void *);
 
 void launch_slip(int dim, int64_t N, int nslip, const int32_t *idx,
                  const double *nrm, double *U, hipStream_t s) {

@@ -34,14 +34,17 @@ namespace ns {
 
 constexpr int kBlock = 256;
 
-// Np: N rounded up to a multiple of 64 (whole slices).
-struct DevGraph {
+// Np: N rounded up to a multiple of 64 (whole slices).  LT is the storage
+// type of the graph coefficients and of the per-edge and flux intermediates:
+// double, or float in the mixed-precision mode (all arithmetic stays FP64).
+template <typename LT>
+struct DevGraphT {
   int64_t N;
   int W;
   const int32_t *col;   // W*Np
   const uint8_t *trk;   // W*Np: slot of the transposed entry in row col
-  const double *mij;    // W*Np
-  const double *c0, *c1, *c2;  // W*Np each (c2 unused in 2D)
+  const LT *mij;        // W*Np
+  const LT *c0, *c1, *c2;  // W*Np each (c2 unused in 2D)
   const double *mi;     // N
   const double *rmi;    // N: 1 / m_i
   const double *lfac;   // N: |I(i)| - 1 = 1 / lambda_i
@@ -49,18 +52,19 @@ struct DevGraph {
   const uint8_t *wall;  // N
 };
 
-struct StageArgs {
+template <typename LT>
+struct StageArgsT {
   const double *U;   // stage input, nc*N
   const double *Un;  // state at the start of the step (SSP combination)
   double *out;       // stage output, nc*N
   double *aux;       // (dim+5)*N
-  double *alpha;     // N
-  double *d;         // W*Np
+  LT *alpha;         // N
+  LT *d;             // W*Np (FP32: rounded up, still an upper bound)
   double *UL;        // nc*N
-  double *FH;        // nc*N
+  LT *FH;            // nc*N
   double *bnds;      // 3*N
-  double *lt1;       // W*Np
-  double *lt2;       // W*Np
+  LT *lt1;           // W*Np (FP32: rounded down, still feasible)
+  LT *lt2;           // W*Np
   double *U1;        // nc*N
   double *partial;   // per-block minima for the time step
   double *tau;       // device scalar
@@ -75,15 +79,20 @@ struct StageArgs {
   uint32_t *qcnt;
 };
 
-void launch_stage(int dim, const Gas &gas, const DevGraph &g,
-                  const StageArgs &a, int indicator, int limiter, int passes,
+using DevGraph = DevGraphT<double>;
+using StageArgs = StageArgsT<double>;
+
+template <typename LT>
+void launch_stage(int dim, const Gas &gas, const DevGraphT<LT> &g,
+                  const StageArgsT<LT> &a, int indicator, int limiter, int passes,
                   bool auto_dt, double cfl, hipStream_t s,
                   void (*before)(void *, const char *), void (*after)(void *),
                   void *prof);
 
 // prim + graph viscosity + time-step reduction only (writes *a.tau).
-void launch_dt_only(int dim, const Gas &gas, const DevGraph &g,
-                    const StageArgs &a, double cfl, hipStream_t s,
+template <typename LT>
+void launch_dt_only(int dim, const Gas &gas, const DevGraphT<LT> &g,
+                    const StageArgsT<LT> &a, double cfl, hipStream_t s,
                     void (*before)(void *, const char *), void (*after)(void *),
                     void *prof);
 

@@ -115,6 +115,12 @@ struct ns_solver {
   int32_t *col = nullptr;
   uint8_t *trk = nullptr;
   double *mij = nullptr, *c[3] = {nullptr, nullptr, nullptr};
+  // mixed precision: FP32 storage of the graph coefficients and of alpha,
+  // d_ij, F^H and the limiter coefficients (the FP64 arrays stay null)
+  bool mixed = false;
+  float *mijf = nullptr, *cf[3] = {nullptr, nullptr, nullptr};
+  float *alphaf = nullptr, *df = nullptr, *FHf = nullptr, *lt1f = nullptr,
+        *lt2f = nullptr;
   double *mi = nullptr, *rmi = nullptr, *lfac = nullptr, *rrel = nullptr;
   uint8_t *wall = nullptr;
   int nslip = 0;
@@ -150,6 +156,22 @@ struct ns_solver {
     g.c0 = c[0]; g.c1 = c[1]; g.c2 = c[2] ? c[2] : c[1];
     g.mi = mi; g.rmi = rmi; g.lfac = lfac; g.rrel = rrel; g.wall = wall;
     return g;
+  }
+  ns::DevGraphT<float> devgraph32() const {
+    ns::DevGraphT<float> g;
+    g.N = N; g.W = W; g.col = col; g.trk = trk; g.mij = mijf;
+    g.c0 = cf[0]; g.c1 = cf[1]; g.c2 = cf[2] ? cf[2] : cf[1];
+    g.mi = mi; g.rmi = rmi; g.lfac = lfac; g.rrel = rrel; g.wall = wall;
+    return g;
+  }
+  ns::StageArgsT<float> args32(int in, int out, double sa, double sb, int check) const {
+    const ns::StageArgs a = args(in, out, sa, sb, check);
+    ns::StageArgsT<float> b;
+    b.U = a.U; b.Un = a.Un; b.out = a.out; b.aux = a.aux; b.UL = a.UL; b.bnds = a.bnds;
+    b.U1 = a.U1; b.partial = a.partial; b.tau = a.tau; b.flags = a.flags;
+    b.sa = a.sa; b.sb = a.sb; b.check_cfl = a.check_cfl; b.q = a.q; b.qcnt = a.qcnt;
+    b.alpha = alphaf; b.d = df; b.FH = FHf; b.lt1 = lt1f; b.lt2 = lt2f;
+    return b;
   }
   ns::StageArgs args(int in, int out, double sa, double sb, int check) const {
     ns::StageArgs a;
@@ -214,10 +236,16 @@ int read_flags(ns_solver *s) {
 
 void run_stage(ns_solver *s, int in, int out, double sa, double sb, int check,
                bool auto_dt) {
-  ns::launch_stage(s->dim, s->gas, s->devgraph(), s->args(in, out, sa, sb, check),
-                   s->prm.indicator, s->prm.limiter, s->prm.passes, auto_dt,
-                   s->prm.cfl, s->stream, &Profiler::before, &Profiler::after,
-                   &s->prof);
+  if (s->mixed)
+    ns::launch_stage(s->dim, s->gas, s->devgraph32(), s->args32(in, out, sa, sb, check),
+                     s->prm.indicator, s->prm.limiter, s->prm.passes, auto_dt,
+                     s->prm.cfl, s->stream, &Profiler::before, &Profiler::after,
+                     &s->prof);
+  else
+    ns::launch_stage(s->dim, s->gas, s->devgraph(), s->args(in, out, sa, sb, check),
+                     s->prm.indicator, s->prm.limiter, s->prm.passes, auto_dt,
+                     s->prm.cfl, s->stream, &Profiler::before, &Profiler::after,
+                     &s->prof);
 }
 
 void run_slip(ns_solver *s, int buf) {
@@ -450,9 +478,11 @@ int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
   if (!(p->gamma > 1.0 && p->gamma <= 5.0 / 3.0 + 1e-12) ||
       !(p->cfl > 0.0 && p->cfl <= 1.0) || p->indicator < 0 || p->indicator > 2 ||
       p->limiter < 0 || p->limiter > 2 || (p->passes != 1 && p->passes != 2) ||
-      !(p->relax >= 0.0) || !std::isfinite(p->relax)) {
+      !(p->relax >= 0.0) || !std::isfinite(p->relax) ||
+      (p->precision != NS_PREC_FP64 && p->precision != NS_PREC_MIXED)) {
     g_create_error = "invalid parameters (need 1 < gamma <= 5/3, 0 < cfl <= 1, "
-                     "indicator/limiter in range, passes 1 or 2, relax >= 0)";
+                     "indicator/limiter in range, passes 1 or 2, relax >= 0, "
+                     "precision NS_PREC_FP64 or NS_PREC_MIXED)";
     return NS_EINVAL;
   }
   if ((int64_t)g->mg.W * ((g->mg.N + 63) / 64 * 64) > (int64_t)UINT32_MAX) {
@@ -463,6 +493,7 @@ int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
   if (!s) { g_create_error = "host allocation"; return NS_ENOMEM; }
   s->mg = g->mg;
   s->prm = *p;
+  s->mixed = p->precision == NS_PREC_MIXED;
   s->dim = g->mg.dim;
   s->nc = s->dim + 2;
   s->N = g->mg.N;
@@ -504,8 +535,13 @@ int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
   } while (0)
   NS_ALLOC(s->col, W * Np);
   NS_ALLOC(s->trk, W * Np);
-  NS_ALLOC(s->mij, W * Np);
-  for (int k = 0; k < dim; ++k) NS_ALLOC(s->c[k], W * Np);
+  if (s->mixed) {
+    NS_ALLOC(s->mijf, W * Np);
+    for (int k = 0; k < dim; ++k) NS_ALLOC(s->cf[k], W * Np);
+  } else {
+    NS_ALLOC(s->mij, W * Np);
+    for (int k = 0; k < dim; ++k) NS_ALLOC(s->c[k], W * Np);
+  }
   NS_ALLOC(s->mi, N);
   NS_ALLOC(s->rmi, N);
   NS_ALLOC(s->lfac, N);
@@ -513,13 +549,21 @@ int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
   NS_ALLOC(s->wall, N);
   for (int b = 0; b < 3; ++b) NS_ALLOC(s->S[b], nc * N);
   NS_ALLOC(s->aux, (dim + 5) * N);
-  NS_ALLOC(s->alpha, N);
-  NS_ALLOC(s->d, W * Np);
+  if (s->mixed) {
+    NS_ALLOC(s->alphaf, N);
+    NS_ALLOC(s->df, W * Np);
+    NS_ALLOC(s->FHf, nc * N);
+    NS_ALLOC(s->lt1f, W * Np);
+    NS_ALLOC(s->lt2f, W * Np);
+  } else {
+    NS_ALLOC(s->alpha, N);
+    NS_ALLOC(s->d, W * Np);
+    NS_ALLOC(s->FH, nc * N);
+    NS_ALLOC(s->lt1, W * Np);
+    NS_ALLOC(s->lt2, W * Np);
+  }
   NS_ALLOC(s->UL, nc * N);
-  NS_ALLOC(s->FH, nc * N);
   NS_ALLOC(s->bnds, 3 * N);
-  NS_ALLOC(s->lt1, W * Np);
-  NS_ALLOC(s->lt2, W * Np);
   NS_ALLOC(s->U1, nc * N);
   NS_ALLOC(s->partial, nblocks);
   NS_ALLOC(s->tau, 1);
@@ -553,8 +597,15 @@ int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
           }
         }
       }
-      e = hipMemcpy(a < 0 ? s->mij : s->c[a], sv.data(), W * Np * sizeof(double),
-                    hipMemcpyHostToDevice);
+      if (s->mixed) {
+        // FP32 storage: rounding to nearest keeps c_ij = -c_ji and m_ij = m_ji
+        const std::vector<float> svf(sv.begin(), sv.end());
+        e = hipMemcpy(a < 0 ? s->mijf : s->cf[a], svf.data(), W * Np * sizeof(float),
+                      hipMemcpyHostToDevice);
+      } else {
+        e = hipMemcpy(a < 0 ? s->mij : s->c[a], sv.data(), W * Np * sizeof(double),
+                      hipMemcpyHostToDevice);
+      }
       if (e != hipSuccess) return bail(NS_EHIP, "graph upload failed");
     }
     e = hipMemcpy(s->col, scol.data(), W * Np * sizeof(int32_t), hipMemcpyHostToDevice);
@@ -600,8 +651,10 @@ int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
     }
   }
   // zero the scratch edge arrays once: entries never written stay zero
-  for (double *z : {s->d, s->lt1, s->lt2}) {
-    e = hipMemset(z, 0, (size_t)W * Np * sizeof(double));
+  for (void *z : {(void *)s->d, (void *)s->lt1, (void *)s->lt2, (void *)s->df,
+                  (void *)s->lt1f, (void *)s->lt2f}) {
+    if (!z) continue;
+    e = hipMemset(z, 0, (size_t)W * Np * (s->mixed ? sizeof(float) : sizeof(double)));
     if (e != hipSuccess) return bail(NS_EHIP, "memset failed");
   }
   e = hipHostMalloc(reinterpret_cast<void **>(&s->hflags), 4 * sizeof(int));
@@ -667,11 +720,16 @@ int ns_compute_dt(ns_solver *s, double *dt) {
   if (!s || !dt) return NS_EINVAL;
   if (!s->has_state) return s->fail(NS_ESTATE, "no state set");
   // prim + graph viscosity + reduction, without the rest of the stage
-  const ns::DevGraph g = s->devgraph();
-  ns::StageArgs a = s->args(s->cur, others(s->cur, 0), 0.0, 1.0, 0);
+  const int o1 = others(s->cur, 0);
   ns::launch_clear_flags(s->flags, s->stream);
-  ns::launch_dt_only(s->dim, s->gas, g, a, s->prm.cfl, s->stream,
-                     &Profiler::before, &Profiler::after, &s->prof);
+  if (s->mixed)
+    ns::launch_dt_only(s->dim, s->gas, s->devgraph32(), s->args32(s->cur, o1, 0.0, 1.0, 0),
+                       s->prm.cfl, s->stream, &Profiler::before, &Profiler::after,
+                       &s->prof);
+  else
+    ns::launch_dt_only(s->dim, s->gas, s->devgraph(), s->args(s->cur, o1, 0.0, 1.0, 0),
+                       s->prm.cfl, s->stream, &Profiler::before, &Profiler::after,
+                       &s->prof);
   int rc = read_flags(s);
   if (rc != NS_OK) return rc;
   *dt = *s->htau;
@@ -713,6 +771,7 @@ int ns_set_viscous(ns_solver *s, const ns_viscous *v) {
       if (e == hipSuccess) e = s->alloc(d, dN);
     for (double **d : nvecs)
       if (e == hipSuccess) e = s->alloc(d, N);
+    if (e == hipSuccess) e = s->alloc(&B.cellK, (int64_t)(1 << s->dim) * N);
     if (e == hipSuccess) e = s->alloc(&B.partial, 3 * nblocks);
     if (e == hipSuccess) e = s->alloc(&B.cg, 1);
     if (e == hipSuccess) e = s->alloc(&B.scal, 4);
@@ -786,25 +845,34 @@ int ns_get_debug(ns_solver *s, int what, double *out) {
   if (!s || !out) return NS_EINVAL;
   const int64_t N = s->N, W = s->W, nc = s->nc, Np = s->Np;
   const double *src = nullptr;
+  const float *srcf = nullptr;  // FP32 storage in the mixed-precision mode
   int64_t count = 0;
   bool edge = false;
   switch (what) {
     case NS_DBG_STAGE_OUT: src = s->S[s->last_out]; count = nc * N; break;
-    case NS_DBG_D: src = s->d; count = W * Np; edge = true; break;
-    case NS_DBG_ALPHA: src = s->alpha; count = N; break;
+    case NS_DBG_D: src = s->d; srcf = s->df; count = W * Np; edge = true; break;
+    case NS_DBG_ALPHA: src = s->alpha; srcf = s->alphaf; count = N; break;
     case NS_DBG_UL: src = s->UL; count = nc * N; break;
-    case NS_DBG_FH: src = s->FH; count = nc * N; break;
+    case NS_DBG_FH: src = s->FH; srcf = s->FHf; count = nc * N; break;
     case NS_DBG_BOUNDS: src = s->bnds; count = 3 * N; break;
-    case NS_DBG_LT1: src = s->lt1; count = W * Np; edge = true; break;
-    case NS_DBG_LT2: src = s->lt2; count = W * Np; edge = true; break;
+    case NS_DBG_LT1: src = s->lt1; srcf = s->lt1f; count = W * Np; edge = true; break;
+    case NS_DBG_LT2: src = s->lt2; srcf = s->lt2f; count = W * Np; edge = true; break;
     case NS_DBG_U1: src = s->U1; count = nc * N; break;
     default: return s->fail(NS_EINVAL, "unknown debug array");
   }
-  std::vector<double> tmp(edge ? count : 0);
-  hipError_t e = hipMemcpyAsync(edge ? tmp.data() : out, src, count * sizeof(double),
-                                hipMemcpyDeviceToHost, s->stream);
+  const bool f32 = s->mixed && srcf != nullptr;
+  std::vector<double> tmp(edge || f32 ? count : 0);
+  std::vector<float> tmpf(f32 ? count : 0);
+  hipError_t e = f32 ? hipMemcpyAsync(tmpf.data(), srcf, count * sizeof(float),
+                                      hipMemcpyDeviceToHost, s->stream)
+                     : hipMemcpyAsync(edge ? tmp.data() : out, src, count * sizeof(double),
+                                      hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return s->hipfail(e, "debug download");
+  if (f32) {
+    for (int64_t t = 0; t < count; ++t) tmp[t] = tmpf[t];
+    if (!edge) std::copy(tmp.begin(), tmp.end(), out);
+  }
   if (edge) {
     for (int k = 0; k < W; ++k)
       for (int64_t i = 0; i < N; ++i)

@@ -66,45 +66,69 @@ __host__ __device__ constexpr int slot_of(int a, int b) {
   return s;
 }
 
-// gather NC components of the neighbourhood (0 where a neighbour is absent)
-template <int DIM, int NC>
-__device__ __forceinline__ void gather(const ParGrid &G, const double *__restrict__ x,
-                                       const int64_t c[3],
-                                       double (&v)[P<DIM>::S][NC]) {
-  const int64_t N = G.N;
+// offsets into the element table (element.hpp, Q1Tables::packed)
+template <int DIM> struct TabOff {
+  static constexpr int L = 1 << DIM, S = DIM == 2 ? 9 : 27;
+  static constexpr int heat = DIM * DIM * L * L;
+  static constexpr int phi = heat + L * L;
+  static constexpr int dphi = phi + L * L;
+  static constexpr int w = dphi + L * L * DIM;
+  static constexpr int sst = w + 1;
+  static constexpr int sht = sst + S * DIM * DIM;
+};
+
+// all 2^dim cells of the node exist (no wall face through it)
+template <int DIM>
+__device__ __forceinline__ bool interior(const ParGrid &G, const int64_t c[3]) {
+  bool in = true;
 #pragma unroll
-  for (int s = 0; s < P<DIM>::S; ++s) {
-    const int64_t j = nb_index<DIM>(G, c, s);
-    const int64_t js = j >= 0 ? j : 0;
-#pragma unroll
-    for (int l = 0; l < NC; ++l) {
-      const double t = x[l * N + js];
-      v[s][l] = j >= 0 ? t : 0.0;
-    }
-  }
+  for (int d = 0; d < DIM; ++d)
+    if (!G.per[d] && (c[d] == 0 || c[d] == G.n[d] - 1)) in = false;
+  return in;
 }
 
-// acc_k = sum over the node's cells and their nodes b of E^kl_ab v_b,l
-// (E: stress table for NC = DIM, heat table for NC = 1)
+// acc_k = (operator row of the node applied to x), without the mass term:
+// at interior nodes by the pre-summed 3^dim-point stencil, at wall nodes
+// cell by cell with the element matrix (NC = dim: stress, NC = 1: heat)
 template <int DIM, int NC>
-__device__ __forceinline__ void op_row(const ParGrid &G, const double *__restrict__ E,
-                                       const int64_t c[3],
-                                       const double (&v)[P<DIM>::S][NC],
-                                       double (&acc)[NC]) {
-  constexpr int L = P<DIM>::L;
+__device__ __forceinline__ void op_apply(const ParGrid &G, const double *__restrict__ tab,
+                                         const double *__restrict__ x,
+                                         const int64_t c[3], double (&acc)[NC]) {
+  using T = TabOff<DIM>;
+  constexpr int L = T::L, S = T::S;
+  const int64_t N = G.N;
 #pragma unroll
   for (int k = 0; k < NC; ++k) acc[k] = 0.0;
+  if (interior<DIM>(G, c)) {
+    const double *__restrict__ st = tab + (NC > 1 ? T::sst : T::sht);
+    // a plane of 3^(dim-1) neighbours at a time (all 27 gathers of the 3D
+    // stencil in flight at once would cut the occupancy to 2 waves)
+#pragma unroll 9
+    for (int s = 0; s < S; ++s) {
+      const int64_t j = nb_index<DIM>(G, c, s);
+      double xj[NC];
 #pragma unroll
-  for (int a = 0; a < L; ++a) {
-    if (!cell_exists<DIM>(G, c, a)) continue;
-#pragma unroll
-    for (int b = 0; b < L; ++b) {
-      const int s = slot_of<DIM>(a, b);
+      for (int l = 0; l < NC; ++l) xj[l] = x[l * N + j];
 #pragma unroll
       for (int k = 0; k < NC; ++k)
 #pragma unroll
-        for (int l = 0; l < NC; ++l)
-          acc[k] += E[((k * NC + l) * L + a) * L + b] * v[s][l];
+        for (int l = 0; l < NC; ++l) acc[k] += st[(s * NC + k) * NC + l] * xj[l];
+    }
+  } else {
+    const double *__restrict__ E = tab + (NC > 1 ? 0 : T::heat);
+    for (int a = 0; a < L; ++a) {
+      if (!cell_exists<DIM>(G, c, a)) continue;
+      for (int b = 0; b < L; ++b) {
+        const int64_t j = nb_index<DIM>(G, c, slot_of<DIM>(a, b));
+        double xj[NC];
+#pragma unroll
+        for (int l = 0; l < NC; ++l) xj[l] = x[l * N + j];
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+#pragma unroll
+          for (int l = 0; l < NC; ++l)
+            acc[k] += E[((k * NC + l) * L + a) * L + b] * xj[l];
+      }
     }
   }
 }
@@ -179,7 +203,6 @@ __global__ __launch_bounds__(kParBlock) void k_prep(ParGrid G, ParBufs B,
 // residual and first direction from the start value x; partial r.z, r.r, b.b
 template <int DIM, int NC>
 __global__ __launch_bounds__(kParBlock) void k_cg_start(ParGrid G, ParBufs B,
-                                                        const double *__restrict__ E,
                                                         double cdt) {
   constexpr bool VEL = NC > 1;
   const int64_t i = gid();
@@ -188,14 +211,13 @@ __global__ __launch_bounds__(kParBlock) void k_cg_start(ParGrid G, ParBufs B,
   if (i < N) {
     int64_t c[3];
     decode(G, i, c);
-    double v[P<DIM>::S][NC], acc[NC];
-    gather<DIM, NC>(G, B.x, c, v);
-    op_row<DIM, NC>(G, E, c, v, acc);
+    double acc[NC];
+    op_apply<DIM, NC>(G, B.tab, B.x, c, acc);
     const bool fx = VEL && B.fixed[i] != 0;
     const double rm = B.rm[i];
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      const double xi = v[P<DIM>::C][k];
+      const double xi = B.x[k * N + i];
       const double y = fx ? xi : rm * xi + cdt * acc[k];
       const double bi = B.b[k * N + i];
       const double r = bi - y;
@@ -213,7 +235,6 @@ __global__ __launch_bounds__(kParBlock) void k_cg_start(ParGrid G, ParBufs B,
 // q = Op(p); partial p.q
 template <int DIM, int NC>
 __global__ __launch_bounds__(kParBlock) void k_cg_apply(ParGrid G, ParBufs B,
-                                                        const double *__restrict__ E,
                                                         double cdt) {
   if (B.cg->done) return;
   constexpr bool VEL = NC > 1;
@@ -223,14 +244,13 @@ __global__ __launch_bounds__(kParBlock) void k_cg_apply(ParGrid G, ParBufs B,
   if (i < N) {
     int64_t c[3];
     decode(G, i, c);
-    double v[P<DIM>::S][NC], acc[NC];
-    gather<DIM, NC>(G, B.p, c, v);
-    op_row<DIM, NC>(G, E, c, v, acc);
+    double acc[NC];
+    op_apply<DIM, NC>(G, B.tab, B.p, c, acc);
     const bool fx = VEL && B.fixed[i] != 0;
     const double rm = B.rm[i];
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      const double pi = v[P<DIM>::C][k];
+      const double pi = B.p[k * N + i];
       const double q = fx ? pi : rm * pi + cdt * acc[k];
       B.q[k * N + i] = q;
       sums[0] += pi * q;
@@ -333,69 +353,99 @@ __global__ __launch_bounds__(kParBlock) void k_cg_scalars(const double *__restri
   }
 }
 
-// V^{n+1} = 2 V^{1/2} - V^n (0 at no-slip nodes) stored in Vn and as
-// momentum rho V^{n+1} in out; K_i = (1/m_i) int sigma(V^{1/2}) :
-// eps(V^{1/2}) phi_i by the tensor Gauss rule on each of the node's cells
+// Dissipation, once per cell: the thread of node i handles the cell whose
+// lowest corner is i (if it exists): sigma(V^{1/2}) : eps(V^{1/2}) at the
+// 2^dim Gauss points, and for each node a of the cell its share
+// sum_q w phi_a(x_q) (sigma : eps)(x_q), stored in cellK[a*N + i].
 template <int DIM>
-__global__ __launch_bounds__(kParBlock) void k_vel_done(ParGrid G, ParBufs B,
-                                                        const double *__restrict__ U,
-                                                        double *__restrict__ out,
-                                                        double mu, double lam23) {
-  constexpr int L = P<DIM>::L;
+__global__ __launch_bounds__(kParBlock) void k_cell_diss(ParGrid G, ParBufs B,
+                                                         double mu, double lam23) {
+  using T = TabOff<DIM>;
+  constexpr int L = T::L;
   const int64_t i = gid();
   const int64_t N = G.N;
   if (i >= N) return;
   int64_t c[3];
   decode(G, i, c);
-  double v[P<DIM>::S][DIM];
-  gather<DIM, DIM>(G, B.x, c, v);
+  bool has = true;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d)
+    if (!G.per[d] && c[d] > G.n[d] - 2) has = false;
+  if (!has) return;
+  double v[L][DIM];
+#pragma unroll
+  for (int b = 0; b < L; ++b) {
+    const int64_t j = nb_index<DIM>(G, c, slot_of<DIM>(0, b));
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) v[b][k] = B.x[k * N + j];
+  }
+  const double *__restrict__ tab = B.tab;
+  const double wq = tab[T::w];
+  double share[L];
+#pragma unroll
+  for (int a = 0; a < L; ++a) share[a] = 0.0;
+#pragma unroll
+  for (int q = 0; q < L; ++q) {
+    double Gm[DIM][DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+#pragma unroll
+      for (int p = 0; p < DIM; ++p) Gm[k][p] = 0.0;
+#pragma unroll
+    for (int b = 0; b < L; ++b)
+#pragma unroll
+      for (int p = 0; p < DIM; ++p) {
+        const double dp = tab[T::dphi + (q * L + b) * DIM + p];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) Gm[k][p] += v[b][k] * dp;
+      }
+    double tr = 0.0, ee = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) tr += Gm[k][k];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+#pragma unroll
+      for (int p = 0; p < DIM; ++p) {
+        const double e = 0.5 * (Gm[k][p] + Gm[p][k]);
+        ee += e * e;
+      }
+    // sigma : eps = 2 mu eps : eps + (lambda - 2/3 mu) (tr eps)^2
+    const double se = wq * (2.0 * mu * ee + lam23 * tr * tr);
+#pragma unroll
+    for (int a = 0; a < L; ++a) share[a] += tab[T::phi + q * L + a] * se;
+  }
+#pragma unroll
+  for (int a = 0; a < L; ++a) B.cellK[a * N + i] = share[a];
+}
+
+// V^{n+1} = 2 V^{1/2} - V^n (0 at no-slip nodes) stored in Vn and as
+// momentum rho V^{n+1} in out; K_i = (1/m_i) sum over the node's cells of
+// the node's share of int sigma : eps phi_i
+template <int DIM>
+__global__ __launch_bounds__(kParBlock) void k_vel_done(ParGrid G, ParBufs B,
+                                                        const double *__restrict__ U,
+                                                        double *__restrict__ out) {
+  constexpr int L = 1 << DIM;
+  const int64_t i = gid();
+  const int64_t N = G.N;
+  if (i >= N) return;
+  int64_t c[3];
+  decode(G, i, c);
   const bool fx = B.fixed[i] != 0;
   const double rho = U[i];
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
-    const double vn = fx ? 0.0 : 2.0 * v[P<DIM>::C][k] - B.Vn[k * N + i];
+    const double vn = fx ? 0.0 : 2.0 * B.x[k * N + i] - B.Vn[k * N + i];
     B.Vn[k * N + i] = vn;
     out[(1 + k) * N + i] = rho * vn;
   }
-  const double *__restrict__ tab = B.tab;
-  const int off_phi = DIM * DIM * L * L + L * L;
-  const int off_dphi = off_phi + L * L;
-  const double wq = tab[off_dphi + L * L * DIM];
   double K = 0.0;
 #pragma unroll
   for (int a = 0; a < L; ++a) {
     if (!cell_exists<DIM>(G, c, a)) continue;
-#pragma unroll
-    for (int q = 0; q < L; ++q) {
-      double Gm[DIM][DIM];
-#pragma unroll
-      for (int k = 0; k < DIM; ++k)
-#pragma unroll
-        for (int p = 0; p < DIM; ++p) Gm[k][p] = 0.0;
-#pragma unroll
-      for (int b = 0; b < L; ++b) {
-        const int s = slot_of<DIM>(a, b);
-#pragma unroll
-        for (int p = 0; p < DIM; ++p) {
-          const double dp = tab[off_dphi + (q * L + b) * DIM + p];
-#pragma unroll
-          for (int k = 0; k < DIM; ++k) Gm[k][p] += v[s][k] * dp;
-        }
-      }
-      double tr = 0.0, ee = 0.0;
-#pragma unroll
-      for (int k = 0; k < DIM; ++k) tr += Gm[k][k];
-#pragma unroll
-      for (int k = 0; k < DIM; ++k)
-#pragma unroll
-        for (int p = 0; p < DIM; ++p) {
-          const double e = 0.5 * (Gm[k][p] + Gm[p][k]);
-          ee += e * e;
-        }
-      // sigma : eps = 2 mu eps : eps + (lambda - 2/3 mu) (tr eps)^2
-      const double se = 2.0 * mu * ee + lam23 * tr * tr;
-      K += wq * tab[off_phi + q * L + a] * se;
-    }
+    // the cell's lowest corner is the node at offset -a
+    const int64_t j = nb_index<DIM>(G, c, slot_of<DIM>(a, 0));
+    K += B.cellK[a * N + j];
   }
   B.K[i] = K / B.mi[i];
 }
@@ -567,9 +617,7 @@ template <int DIM, int NC>
 void cg_start(const ParGrid &g, const ParBufs &B, double cdt, double rtol, int maxit,
               hipStream_t s) {
   const dim3 grid = grid_of(g.N), blk(kParBlock);
-  constexpr int L = 1 << DIM;
-  const double *E = NC > 1 ? B.tab : B.tab + DIM * DIM * L * L;
-  hipLaunchKernelGGL((k_cg_start<DIM, NC>), grid, blk, 0, s, g, B, E, cdt);
+  hipLaunchKernelGGL((k_cg_start<DIM, NC>), grid, blk, 0, s, g, B, cdt);
   hipLaunchKernelGGL(k_cg_scalars<0>, dim3(1), blk, 0, s, B.partial, (int)grid.x,
                      B.cg, rtol * rtol, maxit);
 }
@@ -578,10 +626,8 @@ template <int DIM, int NC>
 void cg_iterate(const ParGrid &g, const ParBufs &B, double cdt, int iters,
                 hipStream_t s) {
   const dim3 grid = grid_of(g.N), blk(kParBlock);
-  constexpr int L = 1 << DIM;
-  const double *E = NC > 1 ? B.tab : B.tab + DIM * DIM * L * L;
   for (int it = 0; it < iters; ++it) {
-    hipLaunchKernelGGL((k_cg_apply<DIM, NC>), grid, blk, 0, s, g, B, E, cdt);
+    hipLaunchKernelGGL((k_cg_apply<DIM, NC>), grid, blk, 0, s, g, B, cdt);
     hipLaunchKernelGGL(k_cg_scalars<1>, dim3(1), blk, 0, s, B.partial, (int)grid.x,
                        B.cg, 0.0, 0);
     hipLaunchKernelGGL(k_cg_update<NC>, grid, blk, 0, s, g, B);
@@ -618,12 +664,14 @@ void par_velocity_done(int dim, const ParGrid &g, const ParBufs &B,
                        const double *U, double *out, double mu, double lambda,
                        hipStream_t s) {
   const double lam23 = lambda - 2.0 / 3.0 * mu;
-  if (dim == 2)
-    hipLaunchKernelGGL(k_vel_done<2>, grid_of(g.N), dim3(kParBlock), 0, s, g, B, U, out,
-                       mu, lam23);
-  else
-    hipLaunchKernelGGL(k_vel_done<3>, grid_of(g.N), dim3(kParBlock), 0, s, g, B, U, out,
-                       mu, lam23);
+  const dim3 grid = grid_of(g.N), blk(kParBlock);
+  if (dim == 2) {
+    hipLaunchKernelGGL(k_cell_diss<2>, grid, blk, 0, s, g, B, mu, lam23);
+    hipLaunchKernelGGL(k_vel_done<2>, grid, blk, 0, s, g, B, U, out);
+  } else {
+    hipLaunchKernelGGL(k_cell_diss<3>, grid, blk, 0, s, g, B, mu, lam23);
+    hipLaunchKernelGGL(k_vel_done<3>, grid, blk, 0, s, g, B, U, out);
+  }
 }
 
 void par_energy_setup(int dim, const ParGrid &g, const ParBufs &B, double cdt,

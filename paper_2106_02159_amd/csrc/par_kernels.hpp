@@ -46,6 +46,7 @@ struct ParBufs {
   double *en;           // N: e^n
   double *K;            // N: dissipation K_i
   double *eH, *eL, *w, *Rp, *Rm;  // N: limiting
+  double *cellK;        // 2^dim * N: per-cell shares of the dissipation
   double *partial;      // 3 * nblocks block partial sums
   CGState *cg;
   double *scal;         // [0] min e^H
