@@ -139,6 +139,75 @@ def cpu_baseline(dim: int, n_sample: int, seed: int, ns: bool = False):
                       f"{dt:.2f} s"}
 
 
+def serve_bench(args):
+    """Serving workload: `requests` independent four-quadrant problems, N x N
+    nodes with N log-uniform in [64, 1024], `serve_steps` SSPRK(3,3) steps
+    each, Poisson arrivals at `rate` per second, admitted by device-memory
+    footprint; reports request latency (submission to completion)
+    percentiles and the whole-job throughput."""
+    prec = abi.PREC_MIXED if args.mixed else abi.PREC_FP64
+    reqs = W.serving_requests(args.requests, seed=args.seed, rate=args.rate)
+    states = [W.four_quadrant_state(n, seed=sd) for _, n, sd in reqs]
+    mem = int(args.serve_mem_gb * 2 ** 30)
+    # warm-up: one small request through a server (first HIP use, module load)
+    warm = abi.Server(mem, max_running=1, precision=prec)
+    wid = warm.submit(states[0][0], states[0][1], 2)
+    while warm.request(wid).state != abi.REQ_FINISHED:
+        warm.progress()
+        time.sleep(1e-3)
+    warm.close()
+    sv = abi.Server(mem, max_running=args.max_running, precision=prec,
+                    chunk=args.serve_chunk, depth=2)
+    t0 = time.perf_counter()
+    pending = list(range(len(reqs)))
+    ids, info = {}, {}
+    while len(info) < len(reqs):
+        now = time.perf_counter() - t0
+        while pending and reqs[pending[0]][0] <= now:
+            k = pending.pop(0)
+            ids[sv.submit(states[k][0], states[k][1], args.serve_steps)] = k
+        sv.progress()
+        for rid in list(ids):
+            r = sv.request(rid)
+            if r.state == abi.REQ_FINISHED:
+                _, st = sv.result(rid)
+                if st != abi.NS_OK:
+                    raise RuntimeError(f"request {ids[rid]} failed: {sv.error(rid)}")
+                info[ids.pop(rid)] = (r.t_submit, r.t_finish, r.n_nodes)
+        time.sleep(2e-4)
+    stats = sv.stats()
+    sv.close()
+    lat = np.array([f - s for s, f, _ in info.values()]) * 1e3
+    t_first = min(s for s, _, _ in info.values())
+    t_last = max(f for _, f, _ in info.values())
+    dof = sum(n for _, _, n in info.values()) * 3 * args.serve_steps
+    value = dof / (t_last - t_first)
+    return {
+        "metric": "DoF-updates/s per SSP-RK stage; p50/p99 request latency",
+        "value": value,
+        "unit": "DoF-updates/s per SSP-RK stage",
+        "n_gpus": 1, "steps": args.serve_steps, "warmup": 1,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64 (f32 storage)" if args.mixed else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"serving: {args.requests} independent 2D Euler Q1 requests, "
+                               f"N x N nodes with N log-uniform in [64, 1024], seeded "
+                               f"four-quadrant data, {args.serve_steps} SSPRK3 steps "
+                               f"each, Poisson arrivals at {args.rate}/s, admission by "
+                               f"device footprint (budget {args.serve_mem_gb} GiB, at "
+                               f"most {args.max_running} running), chunks of "
+                               f"{args.serve_chunk} steps, {args.hw_queues} hardware "
+                               f"queues",
+                   "requests": args.requests},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                       "p99": float(np.percentile(lat, 99)),
+                       "mean": float(lat.mean()), "max": float(lat.max())},
+        "makespan_s": t_last - t_first,
+        "peak_running": stats.peak_running,
+        "peak_bytes": stats.peak_bytes,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +228,19 @@ def main():
                          "FP64 state and arithmetic; after the timed steps the FP64 "
                          "path is run with the same time steps and the L1 relative "
                          "error is reported")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving workload (continuous batching of independent "
+                         "requests); prints latency percentiles and throughput")
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--serve-steps", type=int, default=200)
+    ap.add_argument("--max-running", type=int, default=64)
+    ap.add_argument("--serve-mem-gb", type=float, default=160.0)
+    ap.add_argument("--serve-chunk", type=int, default=2,
+                    help="steps per enqueued chunk of a running request")
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="hardware queues for the serving streams (GPU_MAX_HW_QUEUES, "
+                         "at most 32)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="oracle sample, nodes per direction (default 1024 in "
@@ -170,6 +252,12 @@ def main():
               "on a single MI355X (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
+    if args.serve:
+        # set before the first HIP call of the process; the running requests'
+        # streams are spread over these hardware queues
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(max(args.hw_queues, 1), 32))
+        print(json.dumps(serve_bench(args)), flush=True)
+        return
     dim = 3 if args.ns else args.dim
     n = args.n or (4096 if dim == 2 else 256)
     t0 = time.perf_counter()

@@ -134,6 +134,11 @@ int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
                      ns_solver **out);
 void ns_solver_destroy(ns_solver *s);
 
+/* Device bytes ns_solver_create would allocate for this graph and these
+ * parameters (without ns_set_viscous); equals ns_device_bytes of the
+ * created solver.  Used to admit work by memory footprint. */
+int ns_solver_footprint(const ns_graph *g, const ns_params *p, int64_t *bytes);
+
 /* Copies a state in (host or, with NS_ON_DEVICE, device buffer of nc*N
  * doubles).  The state is checked: NS_ENOTADMISSIBLE if any rho <= 0,
  * eps = E - |m|^2/(2 rho) <= 0 or a value is not finite (ns_last_error
@@ -225,6 +230,81 @@ typedef struct ns_par_info {
 } ns_par_info;
 /* Diagnostics of the last parabolic step. */
 int ns_parabolic_info(ns_solver *s, ns_par_info *out);
+
+/* ---- asynchronous stepping (serving) ------------------------------------
+ * ns_step_cfl_async enqueues nsteps SSPRK(3,3) steps, each with its own CFL
+ * time step computed on the device as in ns_step_cfl, and returns without
+ * waiting for the device.  The status of all steps enqueued since the last
+ * ns_async_finish is kept on the device (sticky): the steps are not
+ * transactional -- after a failure the state is that of the failed run.
+ * ns_query tells without blocking whether the enqueued work has finished;
+ * ns_async_finish waits for it and returns NS_OK, NS_ECFL or NS_EBOUNDS for
+ * the whole run and the time advanced (sum of the steps' dt) in *t. */
+int ns_step_cfl_async(ns_solver *s, int nsteps);
+int ns_query(ns_solver *s, int *done);
+/* Number of ns_step_cfl_async calls whose steps have not all finished. */
+int ns_inflight(ns_solver *s, int *calls);
+int ns_async_finish(ns_solver *s, double *t);
+
+/* ---- serving: continuous batching of independent simulations ------------
+ * A server holds a FIFO queue of requests (uniform-mesh Euler problems: mesh,
+ * initial state, number of SSPRK(3,3) steps with the CFL time step).  A
+ * request is admitted, in order, when its device footprint
+ * (ns_solver_footprint) fits in mem_bytes beside the running ones and fewer
+ * than max_running are running; it then gets its own solver on its own HIP
+ * stream; its steps are enqueued in chunks of `chunk` steps, at most
+ * `depth` chunks in flight, one new chunk per request per progress call
+ * (round robin), so running requests advance together and overlap on the
+ * device.  ns_server_progress never blocks on the device: it tops up the
+ * running requests' chunks, collects finished requests (their states are
+ * copied to host memory and their device memory freed) and admits queued
+ * ones.  A
+ * request's result depends only on its input (deterministic kernels, no
+ * shared device data): it is bit-identical alone and in any mix. */
+typedef struct ns_server ns_server;
+typedef struct ns_server_params {
+  int64_t mem_bytes;  /* device memory the running requests may use        */
+  int max_running;    /* running requests at most, >= 1                    */
+  int chunk;          /* steps per enqueued chunk, >= 1                    */
+  int depth;          /* chunks in flight per request, >= 1                */
+  ns_params solver;   /* parameters of every request's solver              */
+} ns_server_params;
+enum { NS_REQ_QUEUED = 0, NS_REQ_RUNNING = 1, NS_REQ_FINISHED = 2 };
+typedef struct ns_request_info {
+  int state;          /* NS_REQ_*                                          */
+  int status;         /* status of a finished request (NS_OK, NS_ECFL...)  */
+  int steps;
+  int64_t bytes;      /* device footprint                                  */
+  int64_t n_nodes;
+  double t_submit, t_admit, t_finish;  /* host steady clock, seconds       */
+  double t_sim;       /* simulated time reached (sum of the steps' dt)     */
+} ns_request_info;
+typedef struct ns_server_stats {
+  int64_t submitted, finished, queued, running;
+  int64_t peak_running, peak_bytes, bytes_in_use;
+} ns_server_stats;
+
+/* NS_EINVAL for bad parameters. */
+int ns_server_create(const ns_server_params *p, ns_server **out);
+/* Waits for running requests, frees everything. */
+void ns_server_destroy(ns_server *sv);
+/* Queues a request; U0 (host, nc*N doubles for the mesh's N) is copied.
+ * NS_EINVAL for a bad mesh, NS_ENOMEM if the request alone exceeds
+ * mem_bytes.  *id identifies the request. */
+int ns_server_submit(ns_server *sv, const ns_mesh_desc *mesh, const double *U0,
+                     int steps, int64_t *id);
+/* Collects finished requests and admits queued ones; *n_finished (may be
+ * NULL) is the number of requests that finished in this call. */
+int ns_server_progress(ns_server *sv, int *n_finished);
+/* State and timing of a request (until its result is taken). */
+int ns_server_request(ns_server *sv, int64_t id, ns_request_info *info);
+/* Copies the final state of a finished request into U (host) and forgets
+ * the request; returns the request's status, NS_ESTATE if it has not
+ * finished, NS_EINVAL for an unknown id. */
+int ns_server_result(ns_server *sv, int64_t id, double *U);
+int ns_server_stats_get(const ns_server *sv, ns_server_stats *out);
+/* Error message of a request, or of the last failed submit (id <= 0). */
+const char *ns_server_error(const ns_server *sv, int64_t id);
 
 /* Test access: one forward-Euler stage of size dt from the current state,
  * without SSP combination or post-processing; the result and every

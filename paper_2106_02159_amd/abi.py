@@ -34,7 +34,11 @@ EXPORTED = [
     "ns_profile_get", "ns_copy_bench", "ns_device_bytes", "ns_last_error",
     "ns_create_error",
     "ns_strerror", "ns_set_viscous", "ns_step_parabolic", "ns_step_strang",
-    "ns_step_strang_cfl", "ns_parabolic_info",
+    "ns_step_strang_cfl", "ns_parabolic_info", "ns_step_cfl_async", "ns_query",
+    "ns_inflight",
+    "ns_async_finish", "ns_solver_footprint", "ns_server_create", "ns_server_destroy",
+    "ns_server_submit", "ns_server_progress", "ns_server_request", "ns_server_result",
+    "ns_server_stats_get", "ns_server_error",
 ]
 
 
@@ -97,6 +101,19 @@ def lib() -> C.CDLL:
             "ns_step_strang": (C.c_int, [vp, C.c_double]),
             "ns_step_strang_cfl": (C.c_int, [vp, dp]),
             "ns_parabolic_info": (C.c_int, [vp, C.POINTER(ParInfo)]),
+            "ns_step_cfl_async": (C.c_int, [vp, C.c_int]),
+            "ns_query": (C.c_int, [vp, C.POINTER(C.c_int)]),
+            "ns_inflight": (C.c_int, [vp, C.POINTER(C.c_int)]),
+            "ns_async_finish": (C.c_int, [vp, dp]),
+            "ns_solver_footprint": (C.c_int, [vp, C.POINTER(Params), i64p]),
+            "ns_server_create": (C.c_int, [C.POINTER(ServerParams), C.POINTER(vp)]),
+            "ns_server_destroy": (None, [vp]),
+            "ns_server_submit": (C.c_int, [vp, C.POINTER(MeshDesc), vp, C.c_int, i64p]),
+            "ns_server_progress": (C.c_int, [vp, C.POINTER(C.c_int)]),
+            "ns_server_request": (C.c_int, [vp, C.c_int64, C.POINTER(RequestInfo)]),
+            "ns_server_result": (C.c_int, [vp, C.c_int64, vp]),
+            "ns_server_stats_get": (C.c_int, [vp, C.POINTER(ServerStats)]),
+            "ns_server_error": (C.c_char_p, [vp, C.c_int64]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -173,6 +190,103 @@ class ParInfo(C.Structure):
                 ("fct", C.c_int), ("min_eH", C.c_double)]
 
 
+class ServerParams(C.Structure):
+    _fields_ = [("mem_bytes", C.c_int64), ("max_running", C.c_int), ("chunk", C.c_int),
+                ("depth", C.c_int), ("solver", Params)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("state", C.c_int), ("status", C.c_int), ("steps", C.c_int),
+                ("bytes", C.c_int64), ("n_nodes", C.c_int64), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_finish", C.c_double), ("t_sim", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("submitted", "finished", "queued", "running",
+                                        "peak_running", "peak_bytes", "bytes_in_use")]
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_FINISHED = 0, 1, 2
+
+
+def footprint(graph, gamma=1.4, cfl=0.5, precision=PREC_FP64, **kw) -> int:
+    """Device bytes a solver of these parameters would allocate."""
+    prm = Params(gamma, cfl, kw.get("indicator", IND_ENTROPY), kw.get("limiter", LIM_CONVEX),
+                 kw.get("passes", 2), kw.get("relax", 1.0), precision)
+    b = C.c_int64()
+    rc = lib().ns_solver_footprint(graph.h, C.byref(prm), C.byref(b))
+    if rc != NS_OK:
+        raise NSError(rc, "footprint")
+    return b.value
+
+
+class Server:
+    """ns_server_*: continuous batching of independent simulations."""
+
+    def __init__(self, mem_bytes, max_running=64, gamma=1.4, cfl=0.5,
+                 precision=PREC_FP64, chunk=2, depth=2):
+        L = lib()
+        self.prm = ServerParams(int(mem_bytes), int(max_running), int(chunk), int(depth),
+                                Params(gamma, cfl, IND_ENTROPY, LIM_CONVEX, 2, 1.0,
+                                       precision))
+        h = C.c_void_p()
+        rc = L.ns_server_create(C.byref(self.prm), C.byref(h))
+        if rc != NS_OK:
+            raise NSError(rc, "server create")
+        self.h = h
+        self.meshes = {}
+
+    def submit(self, mesh, U, steps: int) -> int:
+        U = np.ascontiguousarray(U, np.float64)
+        d = mesh_desc(mesh)
+        rid = C.c_int64()
+        rc = lib().ns_server_submit(self.h, C.byref(d), _ptr(U), int(steps), C.byref(rid))
+        if rc != NS_OK:
+            raise NSError(rc, lib().ns_server_error(self.h, 0).decode())
+        self.meshes[rid.value] = (mesh.dim + 2, mesh.N)
+        return rid.value
+
+    def progress(self) -> int:
+        n = C.c_int()
+        rc = lib().ns_server_progress(self.h, C.byref(n))
+        if rc != NS_OK:
+            raise NSError(rc, "server progress")
+        return n.value
+
+    def request(self, rid: int) -> RequestInfo:
+        info = RequestInfo()
+        rc = lib().ns_server_request(self.h, int(rid), C.byref(info))
+        if rc != NS_OK:
+            raise NSError(rc, "unknown request")
+        return info
+
+    def result(self, rid: int):
+        """(state, status) of a finished request; forgets the request."""
+        nc, N = self.meshes.pop(rid)
+        out = np.empty((nc, N))
+        rc = lib().ns_server_result(self.h, int(rid), _ptr(out))
+        return out, rc
+
+    def error(self, rid: int) -> str:
+        return lib().ns_server_error(self.h, int(rid)).decode()
+
+    def stats(self) -> ServerStats:
+        st = ServerStats()
+        lib().ns_server_stats_get(self.h, C.byref(st))
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ns_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Solver:
     """ns_solver_create and the per-solver calls."""
 
@@ -247,6 +361,21 @@ class Solver:
         info = ParInfo()
         self._check(lib().ns_parabolic_info(self.h, C.byref(info)))
         return info
+
+    # -- asynchronous stepping ---------------------------------------------
+    def step_cfl_async(self, nsteps: int):
+        return self._check(lib().ns_step_cfl_async(self.h, int(nsteps)))
+
+    def query(self) -> bool:
+        done = C.c_int()
+        self._check(lib().ns_query(self.h, C.byref(done)))
+        return bool(done.value)
+
+    def async_finish(self):
+        """(status, time advanced) of the steps enqueued since the last call."""
+        t = C.c_double()
+        rc = lib().ns_async_finish(self.h, C.byref(t))
+        return rc, t.value
 
     def fe_stage(self, dt: float) -> int:
         return lib().ns_fe_stage(self.h, float(dt))

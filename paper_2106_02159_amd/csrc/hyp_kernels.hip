@@ -391,7 +391,6 @@ __global__ __launch_bounds__(kBlock) void k_lo(DevGraphT<LT> G, StageArgsT<LT> A
     }
 #pragma unroll
     for (int kk = 0; kk < C::CH; ++kk) {
-      const int k = ch * C::CH + kk;
       const int32_t j = jc[kk];
       if (j < 0) continue;
       double fci[NC];
@@ -863,7 +862,6 @@ __global__ __launch_bounds__(kBlock) void k_fin(DevGraphT<LT> G, StageArgsT<LT> 
     }
 #pragma unroll
     for (int kk = 0; kk < C::CH; ++kk) {
-      const int k = ch * C::CH + kk;
       if (jc[kk] < 0 || jc[kk] == i) continue;
       const double l1 = fmin(l1a[kk], l1b[kk]);
       const double l2 = fmin(l2a[kk], l2b[kk]);
@@ -920,6 +918,10 @@ __global__ __launch_bounds__(kBlock) void k_copy8(const double *__restrict__ src
 
 __global__ void k_set_scalar(double *p, double v) {
   if (threadIdx.x == 0) p[0] = v;
+}
+
+__global__ void k_add_scalar(double *acc, const double *v) {
+  if (threadIdx.x == 0) acc[0] += v[0];
 }
 
 __global__ void k_clear_flags(int *flags) {
@@ -1101,6 +1103,10 @@ void launch_slip(int dim, int64_t N, int nslip, const int32_t *idx,
 
 void launch_set_scalar(double *p, double v, hipStream_t s) {
   hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(64), 0, s, p, v);
+}
+
+void launch_add_scalar(double *acc, const double *v, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_scalar, dim3(1), dim3(64), 0, s, acc, v);
 }
 
 void launch_copy(const void *src, void *dst, int64_t n16, int word,

@@ -99,6 +99,7 @@ void launch_dt_only(int dim, const Gas &gas, const DevGraphT<LT> &g,
 void launch_slip(int dim, int64_t N, int nslip, const int32_t *idx,
                  const double *nrm, double *U, hipStream_t s);
 void launch_set_scalar(double *p, double v, hipStream_t s);
+void launch_add_scalar(double *acc, const double *v, hipStream_t s);  // acc += *v
 // plain streaming copy of 16*n16 bytes, `word` (8 or 16) bytes per lane
 // (bandwidth and counter calibration)
 void launch_copy(const void *src, void *dst, int64_t n16, int word,

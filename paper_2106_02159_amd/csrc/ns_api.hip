@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <new>
 #include <string>
@@ -135,8 +136,16 @@ struct ns_solver {
          *U1 = nullptr, *partial = nullptr, *tau = nullptr;
   int *flags = nullptr;
   uint32_t *q = nullptr, *qcnt = nullptr;
-  int *hflags = nullptr;   // pinned
-  double *htau = nullptr;  // pinned
+  // host copies of device scalars (pageable: no pinned allocation, whose
+  // release would synchronize the whole device)
+  int hflags[4] = {0, 0, 0, 0};
+  double *tacc = nullptr;  // device: time advanced by the asynchronous steps
+  // one event per ns_step_cfl_async call still running, oldest first, and
+  // a pool of finished ones for reuse
+  std::deque<hipEvent_t> inflight;
+  std::vector<hipEvent_t> ev_pool;
+  bool async_open = false;
+  double htau[1] = {0.0};
   int last_out = 1;        // buffer holding the last stage output
   // parabolic step (allocated by ns_set_viscous)
   bool viscous = false;
@@ -144,8 +153,8 @@ struct ns_solver {
   ns::ParBufs pb{};
   double *ptab = nullptr;
   double *backup = nullptr;       // nc*N: state at the start of a Strang step
-  ns::CGState *hcg = nullptr;     // pinned
-  double *hscal = nullptr;        // pinned
+  ns::CGState hcg[1] = {};
+  double hscal[4] = {0, 0, 0, 0};
   ns_par_info pinfo{};
   std::string err = "no error";
   Profiler prof;
@@ -187,9 +196,13 @@ struct ns_solver {
     err = std::string(what) + ": " + hipGetErrorString(e);
     return NS_EHIP;
   }
+  // Device memory is stream-ordered (hipMallocAsync / hipFreeAsync on the
+  // solver's stream): creating and destroying solvers while others run, as
+  // the server does, never waits for the whole device.
   template <typename T> hipError_t alloc(T **p, size_t count) {
     void *q = nullptr;
-    hipError_t e = hipMalloc(&q, count * sizeof(T) > 0 ? count * sizeof(T) : 1);
+    hipError_t e = hipMallocAsync(&q, count * sizeof(T) > 0 ? count * sizeof(T) : 1,
+                                  stream);
     if (e != hipSuccess) return e;
     allocs.push_back(q);
     bytes += (int64_t)(count * sizeof(T));
@@ -204,12 +217,13 @@ void release(ns_solver *s) {
   if (!s) return;
   if (s->stream) (void)hipStreamSynchronize(s->stream);
   s->prof.destroy();
-  for (void *p : s->allocs) (void)hipFree(p);
+  for (void *p : s->allocs) (void)hipFreeAsync(p, s->stream);
   s->allocs.clear();
-  if (s->hflags) (void)hipHostFree(s->hflags);
-  if (s->htau) (void)hipHostFree(s->htau);
-  if (s->hcg) (void)hipHostFree(s->hcg);
-  if (s->hscal) (void)hipHostFree(s->hscal);
+
+  for (hipEvent_t ev : s->inflight) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : s->ev_pool) (void)hipEventDestroy(ev);
+  s->inflight.clear();
+  s->ev_pool.clear();
   if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
 }
 
@@ -256,10 +270,10 @@ void run_slip(ns_solver *s, int buf) {
 }
 
 // One SSPRK(3,3) step; dt either given (auto_dt false) or computed in stage 1.
-int ssprk3(ns_solver *s, double dt, bool auto_dt, double *dt_out) {
-  if (!s->has_state) return s->fail(NS_ESTATE, "no state set");
+// Enqueues one SSPRK(3,3) step from S[cur] into S[o1] (eq. SPPRK33; dt given
+// or computed in the first stage); the status flags are not cleared.
+int ssprk3_enqueue(ns_solver *s, double dt, bool auto_dt) {
   const int o1 = others(s->cur, 0), o2 = others(s->cur, 1);
-  ns::launch_clear_flags(s->flags, s->stream);
   if (!auto_dt) ns::launch_set_scalar(s->tau, dt, s->stream);
   // w1 = E(u^n)
   run_stage(s, s->cur, o1, 0.0, 1.0, auto_dt ? 0 : 1, auto_dt);
@@ -271,6 +285,13 @@ int ssprk3(ns_solver *s, double dt, bool auto_dt, double *dt_out) {
   run_stage(s, o2, o1, 1.0 / 3.0, 2.0 / 3.0, 1, false);
   run_slip(s, o1);
   s->last_out = o1;
+  return o1;
+}
+
+int ssprk3(ns_solver *s, double dt, bool auto_dt, double *dt_out) {
+  if (!s->has_state) return s->fail(NS_ESTATE, "no state set");
+  ns::launch_clear_flags(s->flags, s->stream);
+  const int o1 = ssprk3_enqueue(s, dt, auto_dt);
   int rc = read_flags(s);
   if (rc != NS_OK) return rc;
   if (dt_out) *dt_out = *s->htau;
@@ -472,6 +493,49 @@ int ns_graph_export(const ns_graph *g, int32_t *col, double *mij, double *cij,
   return NS_OK;
 }
 
+int ns_solver_footprint(const ns_graph *g, const ns_params *p, int64_t *bytes) {
+  if (!g || !p || !bytes) return NS_EINVAL;
+  const ns::MeshGraph &m = g->mg;
+  const int64_t N = m.N, W = m.W, dim = m.dim, nc = dim + 2;
+  const int64_t Np = (N + 63) / 64 * 64;
+  const int64_t L = p->precision == NS_PREC_MIXED ? 4 : 8;
+  const int64_t nblocks = (N + ns::kBlock - 1) / ns::kBlock;
+  int64_t interior = 1;
+  for (int d = 0; d < dim; ++d)
+    interior *= m.periodic[d] ? m.n[d] : std::max<int64_t>(m.n[d] - 2, 0);
+  const int64_t nslip = N - interior;
+  int64_t b = 0;
+  b += W * Np * (4 + 1) + W * Np * L * (1 + dim);   // col, trk, m_ij, c_ij
+  b += 4 * N * 8 + N;                                // m_i, 1/m_i, lfac, r_i, wall
+  b += 3 * nc * N * 8 + (dim + 5) * N * 8;           // states, aux
+  b += N * L + W * Np * L + nc * N * 8 + nc * N * L;  // alpha, d, U^L, F^H
+  b += 3 * N * 8 + 2 * W * Np * L + nc * N * 8;      // bounds, l~ (2), U^(1)
+  b += nblocks * 8 + 8 + 4 * 4 + 8;                  // partial, tau, flags, time
+  b += W * Np * 4 + 2 * 4;                           // root work list
+  b += nslip * 4 + dim * nslip * 8;                  // slip list
+  *bytes = b;
+  return NS_OK;
+}
+
+namespace {
+// Keep memory freed by hipFreeAsync in the device's default pool instead of
+// returning it to the driver, so that solvers created after others were
+// destroyed reuse it without new driver allocations.
+void keep_pool_memory() {
+  static bool done = false;
+  if (done) return;
+  int dev = 0;
+  hipMemPool_t pool;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t thr = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  (void)hipGetLastError();
+  done = true;
+}
+}  // namespace
+
 int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
                      ns_solver **out) {
   if (!g || !p || !out) { g_create_error = "null argument"; return NS_EINVAL; }
@@ -491,6 +555,7 @@ int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
   }
   ns_solver *s = new (std::nothrow) ns_solver;
   if (!s) { g_create_error = "host allocation"; return NS_ENOMEM; }
+  keep_pool_memory();
   s->mg = g->mg;
   s->prm = *p;
   s->mixed = p->precision == NS_PREC_MIXED;
@@ -568,9 +633,14 @@ int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
   NS_ALLOC(s->partial, nblocks);
   NS_ALLOC(s->tau, 1);
   NS_ALLOC(s->flags, 4);
+  NS_ALLOC(s->tacc, 1);
   // limiter root work list, large enough for every edge
   NS_ALLOC(s->q, W * Np);
   NS_ALLOC(s->qcnt, 2);
+  // the uploads below are synchronous copies: the stream-ordered allocations
+  // must have completed
+  e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return bail(NS_EHIP, "stream synchronize");
 
   // --- upload the graph: generate slot by slot, place into the sliced ELL
   // layout (entry (k, i) at ((i/64)*W + k)*64 + i%64) on the host, upload
@@ -644,6 +714,8 @@ int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
         {s->wall, wall.data(), (size_t)N},
         {s->slip_idx, sidx.data(), sidx.size() * sizeof(int32_t)},
         {s->slip_n, snrm.data(), snrm.size() * sizeof(double)}};
+    e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return bail(NS_EHIP, "stream synchronize");
     for (auto &u : ups) {
       if (u.n == 0) continue;
       e = hipMemcpy(u.dst, u.src, u.n, hipMemcpyHostToDevice);
@@ -657,10 +729,6 @@ int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
     e = hipMemset(z, 0, (size_t)W * Np * (s->mixed ? sizeof(float) : sizeof(double)));
     if (e != hipSuccess) return bail(NS_EHIP, "memset failed");
   }
-  e = hipHostMalloc(reinterpret_cast<void **>(&s->hflags), 4 * sizeof(int));
-  if (e == hipSuccess)
-    e = hipHostMalloc(reinterpret_cast<void **>(&s->htau), sizeof(double));
-  if (e != hipSuccess) return bail(NS_ENOMEM, "pinned host allocation failed");
   e = hipDeviceSynchronize();
   if (e != hipSuccess) return bail(NS_EHIP, hipGetErrorString(e));
 #undef NS_ALLOC
@@ -777,10 +845,6 @@ int ns_set_viscous(ns_solver *s, const ns_viscous *v) {
     if (e == hipSuccess) e = s->alloc(&B.scal, 4);
     if (e == hipSuccess) e = s->alloc(&s->ptab, tab.size());
     if (e == hipSuccess) e = s->alloc(&s->backup, (size_t)s->nc * N);
-    if (e == hipSuccess)
-      e = hipHostMalloc(reinterpret_cast<void **>(&s->hcg), sizeof(ns::CGState));
-    if (e == hipSuccess)
-      e = hipHostMalloc(reinterpret_cast<void **>(&s->hscal), 4 * sizeof(double));
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return s->fail(NS_ENOMEM, std::string("parabolic buffers: ") + hipGetErrorString(e));
@@ -790,7 +854,9 @@ int ns_set_viscous(ns_solver *s, const ns_viscous *v) {
     B.fixed = s->wall;
     B.flags = s->flags;
   }
-  e = hipMemcpy(s->ptab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice);
+  e = hipStreamSynchronize(s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpy(s->ptab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice);
   if (e != hipSuccess) return s->hipfail(e, "element table upload");
   s->vprm = *v;
   s->viscous = true;
@@ -822,6 +888,77 @@ int ns_step_strang_cfl(ns_solver *s, double *tau) {
 int ns_parabolic_info(ns_solver *s, ns_par_info *out) {
   if (!s || !out) return NS_EINVAL;
   *out = s->pinfo;
+  return NS_OK;
+}
+
+int ns_step_cfl_async(ns_solver *s, int nsteps) {
+  if (!s || nsteps < 0) return NS_EINVAL;
+  if (!s->has_state) return s->fail(NS_ESTATE, "no state set");
+  hipEvent_t ev = nullptr;
+  if (!s->ev_pool.empty()) {
+    ev = s->ev_pool.back();
+    s->ev_pool.pop_back();
+  } else {
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return s->hipfail(e, "event create");
+  }
+  if (!s->async_open) {  // a new run: the sticky status and the time start at 0
+    ns::launch_clear_flags(s->flags, s->stream);
+    ns::launch_set_scalar(s->tacc, 0.0, s->stream);
+    s->async_open = true;
+  }
+  for (int k = 0; k < nsteps; ++k) {
+    const int o1 = ssprk3_enqueue(s, 0.0, true);
+    ns::launch_add_scalar(s->tacc, s->tau, s->stream);
+    s->cur = o1;
+  }
+  hipError_t e = hipEventRecord(ev, s->stream);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) {
+    s->ev_pool.push_back(ev);
+    return s->hipfail(e, "asynchronous step launch");
+  }
+  s->inflight.push_back(ev);
+  return NS_OK;
+}
+
+int ns_inflight(ns_solver *s, int *calls) {
+  if (!s || !calls) return NS_EINVAL;
+  while (!s->inflight.empty()) {
+    const hipError_t e = hipEventQuery(s->inflight.front());
+    if (e == hipErrorNotReady) break;
+    if (e != hipSuccess) return s->hipfail(e, "event query");
+    s->ev_pool.push_back(s->inflight.front());
+    s->inflight.pop_front();
+  }
+  *calls = (int)s->inflight.size();
+  return NS_OK;
+}
+
+int ns_query(ns_solver *s, int *done) {
+  if (!s || !done) return NS_EINVAL;
+  int n = 0;
+  const int rc = ns_inflight(s, &n);
+  *done = n == 0;
+  return rc;
+}
+
+int ns_async_finish(ns_solver *s, double *t) {
+  if (!s) return NS_EINVAL;
+  if (!s->async_open) return s->fail(NS_ESTATE, "no asynchronous steps enqueued");
+  s->async_open = false;
+  hipError_t e = hipMemcpyAsync(s->hflags, s->flags, 4 * sizeof(int), hipMemcpyDeviceToHost,
+                                s->stream);
+  double tt = 0.0;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->htau, s->tacc, sizeof(double), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return s->hipfail(e, "asynchronous step status");
+  tt = *s->htau;
+  if (t) *t = tt;
+  if (s->hflags[0]) return s->fail(NS_ECFL, "a step exceeded the stage CFL limit");
+  if (s->hflags[1]) return s->fail(NS_EBOUNDS, "a stage produced an inadmissible state");
   return NS_OK;
 }
 

@@ -209,3 +209,19 @@ def random_rough_state(mesh: Mesh, seed: int = 0, gamma: float = 1.4):
     p = rng.uniform(0.05, 1.0, size=mesh.N)
     vel = tuple(rng.uniform(-1.0, 1.0, size=mesh.N) for _ in range(mesh.dim))
     return conserved(rho, vel, p, gamma)
+
+
+# ---------------------------------------------------------------------------
+# Serving: independent four-quadrant requests of different sizes.
+# ---------------------------------------------------------------------------
+def serving_requests(count: int = 256, seed: int = 0, nmin: int = 64,
+                     nmax: int = 1024, rate: float = 20.0):
+    """Request stream: arrival times of a Poisson process with `rate` per
+    second, mesh sizes N x N with N log-uniform in [nmin, nmax] (rounded),
+    and a data seed per request.  Returns a list of (t_arrival, n, seed)."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=count)
+    t = np.cumsum(gaps) - gaps[0]
+    n = np.rint(np.exp(rng.uniform(np.log(nmin), np.log(nmax), size=count))).astype(int)
+    seeds = rng.integers(0, 2 ** 31 - 1, size=count)
+    return [(float(t[k]), int(n[k]), int(seeds[k])) for k in range(count)]

@@ -1,0 +1,115 @@
+"""Serving (continuous batching of independent simulations): asynchronous
+steps equal synchronous ones bit for bit; the footprint estimate equals the
+allocation; the server admits by memory and never exceeds its budget;
+every request's result is bit-identical alone and in the mix."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2106_02159_amd import abi, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("precision", [abi.PREC_FP64, abi.PREC_MIXED])
+def test_footprint_equals_allocation(precision):
+    for mesh, _ in (W.four_quadrant_state(67, seed=0), W.shock_tube_state(9, seed=0),
+                    (W.Mesh(2, (33, 20), (0, 0), (1, 1), (True, False)), None)):
+        g = abi.Graph(mesh)
+        s = abi.Solver(g, precision=precision)
+        assert abi.footprint(g, precision=precision) == s.device_bytes()
+
+
+def test_async_steps_equal_sync_steps():
+    mesh, U = W.four_quadrant_state(97, seed=4)
+    g = abi.Graph(mesh)
+    a = abi.Solver(g)
+    a.set_state(U)
+    t_sync = sum(a.step_cfl() for _ in range(7))
+    b = abi.Solver(g)
+    b.set_state(U)
+    b.step_cfl_async(3)
+    b.step_cfl_async(4)
+    while not b.query():
+        time.sleep(1e-3)
+    rc, t_async = b.async_finish()
+    assert rc == abi.NS_OK
+    assert t_async == pytest.approx(t_sync, rel=1e-15)
+    assert np.array_equal(a.get_state(), b.get_state())
+
+
+def run_server(reqs, mem_bytes, max_running, precision=abi.PREC_FP64, stagger=0.0):
+    sv = abi.Server(mem_bytes, max_running=max_running, precision=precision)
+    ids = []
+    for mesh, U, steps in reqs:
+        ids.append(sv.submit(mesh, U, steps))
+        sv.progress()
+        if stagger:
+            time.sleep(stagger)
+    left = set(ids)
+    out = {}
+    t0 = time.time()
+    while left:
+        sv.progress()
+        for rid in list(left):
+            if sv.request(rid).state == abi.REQ_FINISHED:
+                info = sv.request(rid)
+                U, st = sv.result(rid)
+                assert st == abi.NS_OK, sv.error(rid)
+                out[rid] = (U, info.t_sim)
+                left.discard(rid)
+        assert time.time() - t0 < 120, "server did not finish"
+        time.sleep(1e-3)
+    st = sv.stats()
+    sv.close()
+    return [out[r] for r in ids], st
+
+
+def mix(count=6, steps=12, seed=0):
+    reqs = []
+    for k, n in enumerate([48, 131, 64, 160, 77, 100][:count]):
+        mesh, U = W.four_quadrant_state(n, seed=seed + k)
+        reqs.append((mesh, U, steps))
+    return reqs
+
+
+@pytest.mark.parametrize("precision", [abi.PREC_FP64, abi.PREC_MIXED])
+def test_alone_and_in_the_mix_are_identical(precision):
+    reqs = mix()
+    alone = []
+    for r in reqs:
+        res, _ = run_server([r], 1 << 34, 1, precision)
+        alone.append(res[0])
+    together, st = run_server(reqs, 1 << 34, 6, precision, stagger=0.002)
+    say("peak running", st.peak_running)
+    assert st.peak_running >= 2
+    for (ua, ta), (ub, tb) in zip(alone, together):
+        assert np.array_equal(ua, ub)
+        assert ta == tb
+    # and equal to a plain solver run
+    mesh, U, steps = reqs[1]
+    s = abi.Solver(abi.Graph(mesh), precision=precision)
+    s.set_state(U)
+    for _ in range(steps):
+        s.step_cfl()
+    assert np.array_equal(s.get_state(), together[1][0])
+
+
+def test_admission_by_memory():
+    reqs = [(*W.four_quadrant_state(90, seed=k), 10) for k in range(5)]
+    fp = abi.footprint(abi.Graph(reqs[0][0]))
+    res, st = run_server(reqs, int(2.5 * fp), 16)
+    say("peak running", st.peak_running, "peak bytes", st.peak_bytes, "budget", 2.5 * fp)
+    assert st.peak_running == 2
+    assert st.peak_bytes <= 2.5 * fp
+    assert st.finished == 5
+    # a request larger than the budget is refused at submission
+    sv = abi.Server(fp // 2)
+    with pytest.raises(abi.NSError):
+        sv.submit(reqs[0][0], reqs[0][1], 3)
+    sv.close()
