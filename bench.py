@@ -292,6 +292,7 @@ def main():
     elapsed = time.perf_counter() - t0
     rep = solver.profile_report()
     solver.profile(False)
+    roots = solver.debug("roots")
     # plain device copy of 1 GiB: the achievable streaming bandwidth, and a
     # kernel of known traffic for calibrating hardware byte counters
     copy_bytes = 1 << 30
@@ -356,6 +357,8 @@ def main():
         "copy_GBs": copy_gbs,
         "copy8_GBs": copy8_gbs,
         "kernels": kern,
+        "root_edges_last_stage": {"pass1": int(roots[0]), "pass2": int(roots[1]),
+                                  "edges": int(graph.nnz - N)},
         "setup_s": setup_s,
         "device_bytes": solver.device_bytes(),
     }

@@ -24,7 +24,7 @@ IND_ENTROPY, IND_ONE, IND_ZERO = 0, 1, 2
 LIM_CONVEX, LIM_LOW, LIM_HIGH = 0, 1, 2
 ON_DEVICE, NO_PROJECT = 1, 2
 DBG = {"stage_out": 0, "d": 1, "alpha": 2, "UL": 3, "FH": 4, "bounds": 5,
-       "lt1": 6, "lt2": 7, "U1": 8}
+       "lt1": 6, "lt2": 7, "U1": 8, "roots": 9}
 
 EXPORTED = [
     "ns_graph_create", "ns_graph_destroy", "ns_graph_info", "ns_graph_export",
@@ -384,7 +384,7 @@ class Solver:
         N, W, nc = self.N, self.W, self.nc
         shape = {"stage_out": (nc, N), "d": (W, N), "alpha": (N,), "UL": (nc, N),
                  "FH": (nc, N), "bounds": (3, N), "lt1": (W, N), "lt2": (W, N),
-                 "U1": (nc, N)}[what]
+                 "U1": (nc, N), "roots": (2,)}[what]
         out = np.empty(shape)
         self._check(lib().ns_get_debug(self.h, DBG[what], _ptr(out)))
         return out

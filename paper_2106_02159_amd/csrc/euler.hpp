@@ -214,9 +214,12 @@ __device__ __forceinline__ double entropy_root_seven(const double *u,
 // Root of the entropy bound to the accuracy of psi itself.  For gamma = 7/5
 // the polynomial root (whose own rounding can leave it ~1e-12 away) is
 // followed by one Newton step on psi: psi is concave, so the tangent root x1
-// is infeasible and, from such a close start, within round-off of the root;
-// the feasible point just below it is returned once psi confirms it.
-// Otherwise (or if that check fails) the bracketing search on psi runs.
+// lies at or beyond the root (within round-off of it from such a close
+// start).  A point a below x1 with psi(a) >= 0 is then within x1 - a of the
+// root; the rounding of psi blurs its sign change over a band whose width
+// grows as psi flattens, so the step back from x1 grows (2e-15, 1.6e-14,
+// 1.3e-13, 1e-12) until psi confirms a feasible point.  If none is confirmed
+// (x1 was not close), the bracketing search on psi runs.
 template <int DIM, int SEV>
 __device__ __forceinline__ double entropy_root_fast(const Gas &g, const double *u,
                                                    const double *P, double lr,
@@ -228,8 +231,11 @@ __device__ __forceinline__ double entropy_root_fast(const Gas &g, const double *
     if (d < 0.0) {
       const double x1 = x - f / d;
       if (x1 > 0.0 && x1 <= lr) {
-        const double a = fmax(x1 - 2e-15, 0.0);
-        if (psi_eval<DIM>(g, u, P, a, pmin, nullptr) >= 0.0) return a;
+        double h = 2e-15;
+        for (int k = 0; k < 4; ++k, h *= 8.0) {
+          const double a = fmax(x1 - h, 0.0);
+          if (psi_eval<DIM>(g, u, P, a, pmin, nullptr) >= 0.0) return a;
+        }
       }
     }
   }

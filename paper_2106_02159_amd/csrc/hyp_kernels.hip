@@ -52,6 +52,23 @@ __device__ __forceinline__ int64_t eidx(int k, int64_t i) {
   return ((i >> 6) * W + k) * 64 + (i & 63);
 }
 
+// Loads of arrays that a sweep reads once per entry (graph coefficients,
+// indices, d_ij of the row): with NS_NT they carry the non-temporal hint so
+// that they do not push the neighbour rows' node data out of L2.
+#ifndef NS_NT
+#define NS_NT 2
+#endif
+template <typename T>
+__device__ __forceinline__ T ld_once(const T *p) {
+  if constexpr (NS_NT >= 1) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <typename T>
+__device__ __forceinline__ void st_once(T *p, T v) {
+  if constexpr (NS_NT >= 2) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
 // Column (or transpose-slot) indices of a row: in 2D all W are loaded at
 // the start so that a chunk's gathers can be issued at once; in 3D each is
 // loaded where its chunk starts (27 of them would hold 27 registers through
@@ -66,12 +83,12 @@ struct RowIdx {
   __device__ __forceinline__ RowIdx(const T *ptr, int64_t row) : p(ptr), i(row) {
     if constexpr (PRE) {
 #pragma unroll
-      for (int k = 0; k < W; ++k) v[k] = p[eidx<DIM>(k, i)];
+      for (int k = 0; k < W; ++k) v[k] = ld_once(&p[eidx<DIM>(k, i)]);
     }
   }
   __device__ __forceinline__ int operator[](int k) const {
     if constexpr (PRE) return v[k];
-    else return p[eidx<DIM>(k, i)];
+    else return ld_once(&p[eidx<DIM>(k, i)]);
   }
 };
 
@@ -97,9 +114,9 @@ template <typename LT> __device__ __forceinline__ LT to_lt_down(double x) {
 
 template <int DIM, typename LT>
 __device__ __forceinline__ void load_c(const DevGraphT<LT> &G, int64_t e, double *c) {
-  c[0] = G.c0[e];
-  c[1] = G.c1[e];
-  if constexpr (DIM == 3) c[2] = G.c2[e];
+  c[0] = ld_once(&G.c0[e]);
+  c[1] = ld_once(&G.c1[e]);
+  if constexpr (DIM == 3) c[2] = ld_once(&G.c2[e]);
 }
 
 template <int NC, typename T>
@@ -142,7 +159,7 @@ __global__ __launch_bounds__(kBlock) void k_prim(int64_t N,
                                                  const double *__restrict__ U,
                                                  double *__restrict__ aux,
                                                  Gas g) {
-  const int64_t i = row_id();
+  const int64_t i = plain_id();
   if (i >= N) return;
   using X = Aux<DIM>;
   const double r = U[i];
@@ -287,8 +304,8 @@ __global__ __launch_bounds__(kBlock) void k_visc(DevGraphT<LT> G,
           dij = fmax(dij, lambda_max<SEV>(g, uLt, pj[kk], aj[kk], bj[kk], uRt, pi, ai, bi) * ctn);
         }
         const LT dst = to_lt_up<LT>(dij);
-        d[e] = dst;
-        d[et] = dst;
+        st_once(&d[e], dst);
+        st_once(&d[et], dst);
       }
     }
   }
@@ -387,7 +404,7 @@ __global__ __launch_bounds__(kBlock) void k_lo(DevGraphT<LT> G, StageArgsT<LT> A
       pj[kk] = aux[X::P * N + js];
       phij[kk] = aux[X::PHI * N + js];
       alj[kk] = alpha[js];
-      dij[kk] = dd[e];
+      dij[kk] = ld_once(&dd[e]);
     }
 #pragma unroll
     for (int kk = 0; kk < C::CH; ++kk) {
@@ -469,8 +486,8 @@ __device__ __forceinline__ void gather_P(const DevGraphT<LT> &G, const StageArgs
   load_state<NC>(A.U, N, js, x.u);
   load_state<NC>(A.FH, N, js, x.f);
   x.al = A.alpha[js];
-  x.d = A.d[e];
-  x.m = G.mij[e];
+  x.d = ld_once(&A.d[e]);
+  x.m = ld_once(&G.mij[e]);
 }
 
 template <int DIM>
@@ -587,7 +604,7 @@ __global__ __launch_bounds__(kBlock) void k_lim1(DevGraphT<LT> G, StageArgsT<LT>
       double P[NC], l;
       make_P<DIM>(R, x[kk], P);
       if (limit_fast<DIM, SEV>(g, ul, P, b, &l)) slow |= 1u << k;
-      lt1[eidx<DIM>(k, i)] = to_lt_down<LT>(l);
+      st_once(&lt1[eidx<DIM>(k, i)], to_lt_down<LT>(l));
     }
   }
   if (slow) {
@@ -715,7 +732,7 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraphT<LT> G, StageArgsT<LT>
 #pragma unroll
         for (int q = 0; q < NC; ++q) P[kk][q] *= (1.0 - l[kk]);
         if (limit_fast<DIM, SEV>(g, u1, P[kk], b, &l2)) slow |= 1u << k;
-        lt2[eidx<DIM>(k, i)] = to_lt_down<LT>(l2);
+        st_once(&lt2[eidx<DIM>(k, i)], to_lt_down<LT>(l2));
       }
     }
     if (slow) {
@@ -756,11 +773,11 @@ __global__ __launch_bounds__(kBlock) void k_lim2b(DevGraphT<LT> G, StageArgsT<LT
     for (int kk = 0; kk < C::CH; ++kk) {
       const int k = ch * C::CH + kk;
       const int64_t e = eidx<DIM>(k, i);
-      jc[kk] = colp[e];
+      jc[kk] = ld_once(&colp[e]);
       const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
       gather_P<DIM>(G, A, e, js, x[kk]);
       la[kk] = lt1[e];
-      lb[kk] = lt1[eidx<DIM>(trkp[e], js)];
+      lb[kk] = lt1[eidx<DIM>(ld_once(&trkp[e]), js)];
     }
 #pragma unroll
     for (int kk = 0; kk < C::CH; ++kk) {
@@ -772,7 +789,7 @@ __global__ __launch_bounds__(kBlock) void k_lim2b(DevGraphT<LT> G, StageArgsT<LT
 #pragma unroll
       for (int q = 0; q < NC; ++q) P[q] *= (1.0 - l);
       if (limit_fast<DIM, SEV>(g, u1, P, b, &l2)) slow |= 1u << k;
-      lt2[eidx<DIM>(k, i)] = to_lt_down<LT>(l2);
+      st_once(&lt2[eidx<DIM>(k, i)], to_lt_down<LT>(l2));
     }
   }
   if (slow) {
@@ -934,7 +951,7 @@ __global__ __launch_bounds__(kBlock) void k_check_state(int64_t N,
                                                         const double *__restrict__ U,
                                                         int *__restrict__ flags) {
   constexpr int NC = DIM + 2;
-  const int64_t i = row_id();
+  const int64_t i = plain_id();
   if (i >= N) return;
   double u[NC];
   load_state<NC>(U, N, i, u);
@@ -992,9 +1009,10 @@ void stage_impl(const Gas &gas, const DevGraphT<LT> &G, const StageArgsT<LT> &A,
     NS_LAUNCH("lim2", hipLaunchKernelGGL((k_lim2<DIM, 2, SEV, LT>), grid, block, 0, s, G, A,
                                          gas));
   } else {
-    // the work lists hold a small fraction of the edges: a grid of a few
-    // wavefronts per SIMD covers them in one or two passes
-    const dim3 rgrid(std::min<unsigned>(grid.x, 1024u));
+    // the work lists hold a small fraction of the edges (~1.5% of them in the
+    // 3D shock tube); up to 4M lanes cover a list without striding, and
+    // blocks past its end exit at once
+    const dim3 rgrid(std::min<unsigned>(grid.x, 16384u));
     NS_LAUNCH("lim1", hipLaunchKernelGGL((k_lim1<DIM, SEV, LT>), grid, block, 0, s, G, A, gas));
     NS_LAUNCH("root1", hipLaunchKernelGGL((k_root<DIM, 1, SEV, LT>), rgrid, block, 0, s, G,
                                           A, gas));

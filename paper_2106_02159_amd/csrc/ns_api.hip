@@ -995,6 +995,15 @@ int ns_get_debug(ns_solver *s, int what, double *out) {
     case NS_DBG_LT1: src = s->lt1; srcf = s->lt1f; count = W * Np; edge = true; break;
     case NS_DBG_LT2: src = s->lt2; srcf = s->lt2f; count = W * Np; edge = true; break;
     case NS_DBG_U1: src = s->U1; count = nc * N; break;
+    case NS_DBG_ROOTS: {
+      uint32_t c[2];
+      hipError_t e = hipMemcpyAsync(c, s->qcnt, sizeof(c), hipMemcpyDeviceToHost, s->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+      if (e != hipSuccess) return s->hipfail(e, "debug download");
+      out[0] = c[0];
+      out[1] = c[1];
+      return NS_OK;
+    }
     default: return s->fail(NS_EINVAL, "unknown debug array");
   }
   const bool f32 = s->mixed && srcf != nullptr;

@@ -33,6 +33,10 @@ CASES = {
     "tube3d_12": lambda: W.shock_tube_state(12, seed=0),
     "rough3d_7x5x6": lambda: rough(W.Mesh(3, (7, 5, 6), (0,) * 3, (1.0, 0.7, 0.9),
                                          (False, True, False)), 5),
+    # 3D meshes whose z-planes are whole 256-row workgroups
+    "tube3d_16": lambda: W.shock_tube_state(16, seed=2),
+    "rough3d_32x16x24": lambda: rough(W.Mesh(3, (32, 16, 24), (0,) * 3, (1.0, 0.5, 0.75),
+                                            (False, True, False)), 10),
     "tiny2d_2x2": lambda: rough(W.Mesh(2, (2, 2), (0, 0), (1, 1), (False, False)), 6),
     "tiny2d_3x3per": lambda: rough(W.Mesh(2, (3, 3), (0, 0), (1, 1), (True, True)), 7),
     "tiny3d_2x2x2": lambda: rough(W.Mesh(3, (2, 2, 2), (0,) * 3, (1,) * 3, (False,) * 3), 8),
@@ -101,6 +105,10 @@ def test_stage(case, mode):
     if kw.get("limiter", abi.LIM_CONVEX) == abi.LIM_CONVEX:
         lt1 = s.debug("lt1")[mask]
         assert np.abs(lt1[off] - dbg["lt1"][idx][off]).max() <= 1e-10
+        # edges sent to the root finder: a subset of the off-diagonal ones
+        roots = s.debug("roots")
+        assert np.all(roots == np.round(roots)) and np.all(roots >= 0)
+        assert roots.max() <= off.sum()
         if kw.get("passes", 2) == 2:
             lt2 = s.debug("lt2")[mask]
             assert np.abs(lt2[off] - dbg["lt2"][idx][off]).max() <= 1e-10
