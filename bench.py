@@ -161,12 +161,15 @@ def serve_bench(args):
     t0 = time.perf_counter()
     pending = list(range(len(reqs)))
     ids, info = {}, {}
+    t_progress = 0.0
     while len(info) < len(reqs):
         now = time.perf_counter() - t0
         while pending and reqs[pending[0]][0] <= now:
             k = pending.pop(0)
             ids[sv.submit(states[k][0], states[k][1], args.serve_steps)] = k
+        tp = time.perf_counter()
         sv.progress()
+        t_progress += time.perf_counter() - tp
         for rid in list(ids):
             r = sv.request(rid)
             if r.state == abi.REQ_FINISHED:
@@ -203,6 +206,7 @@ def serve_bench(args):
                        "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean()), "max": float(lat.max())},
         "makespan_s": t_last - t_first,
+        "host_progress_s": t_progress,
         "peak_running": stats.peak_running,
         "peak_bytes": stats.peak_bytes,
     }

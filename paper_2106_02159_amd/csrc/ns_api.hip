@@ -144,6 +144,11 @@ struct ns_solver {
   // a pool of finished ones for reuse
   std::deque<hipEvent_t> inflight;
   std::vector<hipEvent_t> ev_pool;
+  // asynchronous CFL steps: one step (plus the time accumulation) from start
+  // buffer S[b], captured as a graph on its first use and replayed after;
+  // graphs_off once a capture failed (then kernels are launched one by one)
+  hipGraphExec_t step_graph[3] = {nullptr, nullptr, nullptr};
+  bool graphs_off = false;
   bool async_open = false;
   double htau[1] = {0.0};
   int last_out = 1;        // buffer holding the last stage output
@@ -220,6 +225,10 @@ void release(ns_solver *s) {
   for (void *p : s->allocs) (void)hipFreeAsync(p, s->stream);
   s->allocs.clear();
 
+  for (hipGraphExec_t &g : s->step_graph) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
   for (hipEvent_t ev : s->inflight) (void)hipEventDestroy(ev);
   for (hipEvent_t ev : s->ev_pool) (void)hipEventDestroy(ev);
   s->inflight.clear();
@@ -891,6 +900,38 @@ int ns_parabolic_info(ns_solver *s, ns_par_info *out) {
   return NS_OK;
 }
 
+namespace {
+// The graph of one CFL step from the current buffer (see ns_solver), or null
+// if it cannot be captured (or the profiler, which records events around
+// every launch, is on).  A replay launches the same kernels with the same
+// arguments in the same order as ssprk3_enqueue + launch_add_scalar.
+hipGraphExec_t step_graph(ns_solver *s) {
+  if (s->graphs_off || s->prof.on) return nullptr;
+  hipGraphExec_t &ex = s->step_graph[s->cur];
+  if (ex) return ex;
+  hipError_t e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    s->graphs_off = true;
+    return nullptr;
+  }
+  const int last = s->last_out;
+  (void)ssprk3_enqueue(s, 0.0, true);
+  ns::launch_add_scalar(s->tacc, s->tau, s->stream);
+  s->last_out = last;
+  hipGraph_t gr = nullptr;
+  e = hipStreamEndCapture(s->stream, &gr);
+  if (e == hipSuccess) e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+  if (gr) (void)hipGraphDestroy(gr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    ex = nullptr;
+    s->graphs_off = true;
+  }
+  return ex;
+}
+}  // namespace
+
 int ns_step_cfl_async(ns_solver *s, int nsteps) {
   if (!s || nsteps < 0) return NS_EINVAL;
   if (!s->has_state) return s->fail(NS_ESTATE, "no state set");
@@ -907,12 +948,21 @@ int ns_step_cfl_async(ns_solver *s, int nsteps) {
     ns::launch_set_scalar(s->tacc, 0.0, s->stream);
     s->async_open = true;
   }
-  for (int k = 0; k < nsteps; ++k) {
-    const int o1 = ssprk3_enqueue(s, 0.0, true);
-    ns::launch_add_scalar(s->tacc, s->tau, s->stream);
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
+    const hipGraphExec_t g = step_graph(s);
+    const int o1 = others(s->cur, 0);
+    if (g) {
+      e = hipGraphLaunch(g, s->stream);
+      if (e != hipSuccess) break;
+    } else {
+      (void)ssprk3_enqueue(s, 0.0, true);
+      ns::launch_add_scalar(s->tacc, s->tau, s->stream);
+    }
+    s->last_out = o1;
     s->cur = o1;
   }
-  hipError_t e = hipEventRecord(ev, s->stream);
+  if (e == hipSuccess) e = hipEventRecord(ev, s->stream);
   if (e == hipSuccess) e = hipGetLastError();
   if (e != hipSuccess) {
     s->ev_pool.push_back(ev);

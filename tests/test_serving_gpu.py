@@ -43,6 +43,36 @@ def test_async_steps_equal_sync_steps():
     assert np.array_equal(a.get_state(), b.get_state())
 
 
+@pytest.mark.parametrize("dim,precision", [(2, abi.PREC_FP64), (3, abi.PREC_FP64),
+                                           (2, abi.PREC_MIXED)])
+def test_graph_replays_equal_eager_steps(dim, precision):
+    """Asynchronous steps replay a captured graph of one step per start
+    buffer; every replay, with eager work and host synchronisation between
+    them, equals the eagerly launched synchronous steps bit for bit."""
+    mesh, U = (W.four_quadrant_state(75, seed=5) if dim == 2
+               else W.shock_tube_state(14, seed=5))
+    g = abi.Graph(mesh)
+    a = abi.Solver(g, precision=precision)
+    b = abi.Solver(g, precision=precision)
+    a.set_state(U)
+    b.set_state(U)
+    for rnd in range(4):
+        say("graph replay round", rnd, "dim", dim, "precision", precision)
+        t_sync = a.step_cfl() + a.step_cfl() + a.step_cfl()
+        b.step_cfl_async(2)
+        b.step_cfl_async(1)
+        rc, t_async = b.async_finish()
+        assert rc == abi.NS_OK
+        assert t_async == t_sync
+        assert np.array_equal(a.get_state(), b.get_state())
+        # eager work on b between replays: a profiled (eager) step and back
+        b.profile(True)
+        b.step_cfl()
+        b.profile(False)
+        a.step_cfl()
+        assert np.array_equal(a.get_state(), b.get_state())
+
+
 def run_server(reqs, mem_bytes, max_running, precision=abi.PREC_FP64, stagger=0.0):
     sv = abi.Server(mem_bytes, max_running=max_running, precision=precision)
     ids = []
