@@ -246,6 +246,41 @@ int ns_query(ns_solver *s, int *done);
 int ns_inflight(ns_solver *s, int *calls);
 int ns_async_finish(ns_solver *s, double *t);
 
+/* ---- packs: several meshes advanced by the same kernel launches ---------
+ * A pack holds `count` independent problems (graphs of one dimension) in one
+ * solver.  Every member's rows start at a 256-row workgroup boundary (the
+ * rows up to the next member are isolated padding nodes holding a constant
+ * state), so each workgroup belongs to one member; the CFL time step, the
+ * CFL and admissibility status and the time advanced are per member.  One
+ * ns_pack_step_cfl_async call enqueues nsteps SSPRK(3,3) steps of all
+ * members, each step with each member's own CFL time step.  A member's
+ * result is bit-identical to that of its own solver stepped with
+ * ns_step_cfl: the kernels see the same rows, neighbours and time steps.
+ * For serving many small meshes, whose own launches would leave most of
+ * the device idle.  Parameters as ns_solver_create (NS_EINVAL also for
+ * count < 1 or graphs of different dimensions). */
+typedef struct ns_pack ns_pack;
+int ns_pack_footprint(const ns_graph *const *graphs, int count, const ns_params *p,
+                      int64_t *bytes);
+int ns_pack_create(const ns_graph *const *graphs, int count, const ns_params *p,
+                   void *hip_stream, ns_pack **out);
+/* Waits for the pack's work and frees it. */
+void ns_pack_destroy(ns_pack *k);
+/* State of member r from host memory (nc*N_r doubles, SoA): checked
+ * (NS_ENOTADMISSIBLE) and its wall nodes projected, as ns_set_state.  Every
+ * member needs a state before the first step. */
+int ns_pack_set_state(ns_pack *k, int r, const double *U);
+/* State of member r into host memory; waits for the enqueued steps. */
+int ns_pack_get_state(ns_pack *k, int r, double *U);
+/* As ns_step_cfl_async / ns_inflight, for all members. */
+int ns_pack_step_cfl_async(ns_pack *k, int nsteps);
+int ns_pack_inflight(ns_pack *k, int *calls);
+/* Waits for the enqueued steps; for every member r, status[r] (NS_OK,
+ * NS_ECFL or NS_EBOUNDS, sticky since the last finish) and t[r] (time
+ * advanced since then).  Returns NS_OK, or NS_EHIP if the device failed. */
+int ns_pack_finish(ns_pack *k, int *status, double *t);
+const char *ns_pack_error(const ns_pack *k);
+
 /* ---- serving: continuous batching of independent simulations ------------
  * A server holds a FIFO queue of requests (uniform-mesh Euler problems: mesh,
  * initial state, number of SSPRK(3,3) steps with the CFL time step).  A

@@ -38,7 +38,9 @@ EXPORTED = [
     "ns_inflight",
     "ns_async_finish", "ns_solver_footprint", "ns_server_create", "ns_server_destroy",
     "ns_server_submit", "ns_server_progress", "ns_server_request", "ns_server_result",
-    "ns_server_stats_get", "ns_server_error",
+    "ns_server_stats_get", "ns_server_error", "ns_pack_footprint", "ns_pack_create",
+    "ns_pack_destroy", "ns_pack_set_state", "ns_pack_get_state", "ns_pack_step_cfl_async",
+    "ns_pack_inflight", "ns_pack_finish", "ns_pack_error",
 ]
 
 
@@ -114,6 +116,16 @@ def lib() -> C.CDLL:
             "ns_server_result": (C.c_int, [vp, C.c_int64, vp]),
             "ns_server_stats_get": (C.c_int, [vp, C.POINTER(ServerStats)]),
             "ns_server_error": (C.c_char_p, [vp, C.c_int64]),
+            "ns_pack_footprint": (C.c_int, [vp, C.c_int, C.POINTER(Params), i64p]),
+            "ns_pack_create": (C.c_int, [vp, C.c_int, C.POINTER(Params), vp,
+                                         C.POINTER(vp)]),
+            "ns_pack_destroy": (None, [vp]),
+            "ns_pack_set_state": (C.c_int, [vp, C.c_int, vp]),
+            "ns_pack_get_state": (C.c_int, [vp, C.c_int, vp]),
+            "ns_pack_step_cfl_async": (C.c_int, [vp, C.c_int]),
+            "ns_pack_inflight": (C.c_int, [vp, C.POINTER(C.c_int)]),
+            "ns_pack_finish": (C.c_int, [vp, C.POINTER(C.c_int), dp]),
+            "ns_pack_error": (C.c_char_p, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -218,6 +230,78 @@ def footprint(graph, gamma=1.4, cfl=0.5, precision=PREC_FP64, **kw) -> int:
     if rc != NS_OK:
         raise NSError(rc, "footprint")
     return b.value
+
+
+def _params(gamma, cfl, precision, kw) -> Params:
+    return Params(gamma, cfl, kw.get("indicator", IND_ENTROPY), kw.get("limiter", LIM_CONVEX),
+                  kw.get("passes", 2), kw.get("relax", 1.0), precision)
+
+
+def pack_footprint(graphs, gamma=1.4, cfl=0.5, precision=PREC_FP64, **kw) -> int:
+    """Device bytes a pack of these graphs would allocate."""
+    prm = _params(gamma, cfl, precision, kw)
+    hs = (C.c_void_p * len(graphs))(*[g.h.value for g in graphs])
+    b = C.c_int64()
+    rc = lib().ns_pack_footprint(hs, len(graphs), C.byref(prm), C.byref(b))
+    if rc != NS_OK:
+        raise NSError(rc, "pack footprint")
+    return b.value
+
+
+class Pack:
+    """ns_pack_*: several meshes advanced by the same kernel launches."""
+
+    def __init__(self, graphs, gamma=1.4, cfl=0.5, precision=PREC_FP64, stream=None, **kw):
+        L = lib()
+        self.graphs = list(graphs)
+        prm = _params(gamma, cfl, precision, kw)
+        hs = (C.c_void_p * len(self.graphs))(*[g.h.value for g in self.graphs])
+        h = C.c_void_p()
+        rc = L.ns_pack_create(hs, len(self.graphs), C.byref(prm), stream, C.byref(h))
+        if rc != NS_OK:
+            raise NSError(rc, L.ns_create_error().decode())
+        self.h = h
+
+    def _check(self, rc):
+        if rc != NS_OK:
+            raise NSError(rc, lib().ns_pack_error(self.h).decode())
+        return rc
+
+    def set_state(self, r: int, U):
+        U = np.ascontiguousarray(U, np.float64)
+        g = self.graphs[r]
+        assert U.shape == (g.dim + 2, g.N)
+        self._check(lib().ns_pack_set_state(self.h, int(r), _ptr(U)))
+
+    def get_state(self, r: int) -> np.ndarray:
+        g = self.graphs[r]
+        out = np.empty((g.dim + 2, g.N))
+        self._check(lib().ns_pack_get_state(self.h, int(r), _ptr(out)))
+        return out
+
+    def step_cfl_async(self, nsteps: int):
+        self._check(lib().ns_pack_step_cfl_async(self.h, int(nsteps)))
+
+    def inflight(self) -> int:
+        n = C.c_int()
+        self._check(lib().ns_pack_inflight(self.h, C.byref(n)))
+        return n.value
+
+    def finish(self):
+        """(status per member, time advanced per member)."""
+        n = len(self.graphs)
+        st = (C.c_int * n)()
+        t = np.zeros(n)
+        self._check(lib().ns_pack_finish(self.h, st, t.ctypes.data_as(C.POINTER(C.c_double))))
+        return list(st), t
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ns_pack_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
 
 
 class Server:

@@ -100,6 +100,12 @@ __device__ __forceinline__ int64_t plain_id() {
   return (int64_t)blockIdx.x * kBlock + threadIdx.x;
 }
 
+// Member of a pack that row i belongs to (0 for one mesh).
+template <typename LT>
+__device__ __forceinline__ int member(const StageArgsT<LT> &A, int64_t i) {
+  return A.seg ? A.seg[i / kBlock] : 0;
+}
+
 // FP64 value to the storage type: nearest, upwards (graph viscosity stays an
 // upper bound) or downwards (a limiter coefficient stays feasible)
 template <typename LT> __device__ __forceinline__ LT to_lt(double x) { return (LT)x; }
@@ -309,7 +315,9 @@ __global__ __launch_bounds__(kBlock) void k_visc(DevGraphT<LT> G,
       }
     }
   }
-  if constexpr (IND == 0) alpha[i] = to_lt<LT>(fabs(num) / (den + 1e-2 * scl));
+  // (an isolated node -- a padding row of a pack -- has den = scl = 0)
+  if constexpr (IND == 0)
+    alpha[i] = to_lt<LT>(den + scl > 0.0 ? fabs(num) / (den + 1e-2 * scl) : 0.0);
   else if constexpr (IND == 1) alpha[i] = LT(1);
   else alpha[i] = LT(0);
 }
@@ -337,6 +345,26 @@ __global__ __launch_bounds__(kBlock) void k_dt_partial(DevGraphT<LT> G,
   }
   r = block_min(r);
   if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+// One workgroup per member of a pack: the member's workgroups are
+// [mblk[m], mblk[m+1]); min is exact, so tau equals the one-mesh value.
+__global__ __launch_bounds__(1024) void k_dt_final_members(const double *__restrict__ partial,
+                                                           const int32_t *__restrict__ mblk,
+                                                           double cfl,
+                                                           double *__restrict__ tau) {
+  __shared__ double red[16];
+  const int m = blockIdx.x;
+  double v = INFINITY;
+  for (int64_t b = mblk[m] + threadIdx.x; b < mblk[m + 1]; b += 1024) v = fmin(v, partial[b]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 16; ++w) v = fmin(v, red[w]);
+    tau[m] = cfl * v;
+  }
 }
 
 __global__ __launch_bounds__(1024) void k_dt_final(const double *__restrict__ partial,
@@ -381,7 +409,8 @@ __global__ __launch_bounds__(kBlock) void k_lo(DevGraphT<LT> G, StageArgsT<LT> A
   for (int k = 0; k < DIM; ++k) vi[k] = aux[k * N + i];
   const double pi = aux[X::P * N + i];
   const double ali = alpha[i];
-  const double tau = *A.tau;
+  const int mem = member(A, i);
+  const double tau = A.tau[mem];
   double acc[NC], fh[NC];
 #pragma unroll
   for (int q = 0; q < NC; ++q) { acc[q] = 0.0; fh[q] = 0.0; }
@@ -442,7 +471,7 @@ __global__ __launch_bounds__(kBlock) void k_lo(DevGraphT<LT> G, StageArgsT<LT> A
     A.UL[q * N + i] = ui[q] + tm * acc[q];
     A.FH[q * N + i] = to_lt<LT>(fh[q] * rmi);
   }
-  if (A.check_cfl && tau > G.mi[i] / (2.0 * dsum)) A.flags[0] = 1;
+  if (A.check_cfl && tau > G.mi[i] / (2.0 * dsum)) A.flags[4 * mem] = 1;
   const double r = G.rrel[i];
   A.bnds[i] = (1.0 - r) * rmin;
   A.bnds[N + i] = (1.0 + r) * rmax;
@@ -528,7 +557,7 @@ __device__ __forceinline__ void finish(const DevGraphT<LT> &G, const StageArgsT<
 #pragma unroll
   for (int k = 0; k < DIM; ++k) m2 += w[1 + k] * w[1 + k];
   const double eps = w[NC - 1] - 0.5 * m2 / w[0];
-  if (!(w[0] > 0.0) || !(eps > 0.0)) A.flags[1] = 1;
+  if (!(w[0] > 0.0) || !(eps > 0.0)) A.flags[4 * member(A, i) + 1] = 1;
 #pragma unroll
   for (int q = 0; q < NC; ++q) A.out[q * N + i] = w[q];
 }
@@ -581,7 +610,7 @@ __global__ __launch_bounds__(kBlock) void k_lim1(DevGraphT<LT> G, StageArgsT<LT>
   const int32_t *__restrict__ colp = G.col;
   const RowIdx<DIM, int32_t> jv(colp, i);
   RowCtx<DIM> R;
-  load_row<DIM>(G, A, i, *A.tau, R);
+  load_row<DIM>(G, A, i, A.tau[member(A, i)], R);
   double ul[NC];
   load_state<NC>(A.UL, N, i, ul);
   const Bounds b = load_bounds(A, N, i);
@@ -634,7 +663,7 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraphT<LT> G, StageArgsT<LT>
   const RowIdx<DIM, int32_t> colk(colp, i);
   const RowIdx<DIM, uint8_t> trkk(trkp, i);
   RowCtx<DIM> R;
-  load_row<DIM>(G, A, i, *A.tau, R);
+  load_row<DIM>(G, A, i, A.tau[member(A, i)], R);
   const double lam = 1.0 / G.lfac[i];
   double u1[NC];
   load_state<NC>(A.UL, N, i, u1);
@@ -759,7 +788,7 @@ __global__ __launch_bounds__(kBlock) void k_lim2b(DevGraphT<LT> G, StageArgsT<LT
   const LT *__restrict__ lt1 = A.lt1;
   LT *__restrict__ lt2 = A.lt2;
   RowCtx<DIM> R;
-  load_row<DIM>(G, A, i, *A.tau, R);
+  load_row<DIM>(G, A, i, A.tau[member(A, i)], R);
   double u1[NC];
   load_state<NC>(A.U1, N, i, u1);
   const Bounds b = load_bounds(A, N, i);
@@ -820,14 +849,13 @@ __global__ __launch_bounds__(kBlock) void k_root(DevGraphT<LT> G, StageArgsT<LT>
   const uint32_t n = A.qcnt[PASS - 1];
   const uint32_t *__restrict__ q = A.q;
   LT *__restrict__ lt = PASS == 1 ? A.lt1 : A.lt2;
-  const double tau = *A.tau;
   for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < n;
        t += gridDim.x * kBlock) {
     const int64_t e = q[t];
     const int64_t i = edge_row<DIM>(e);
     const int32_t j = G.col[e];
     RowCtx<DIM> R;
-    load_row<DIM>(G, A, i, tau, R);
+    load_row<DIM>(G, A, i, A.tau[member(A, i)], R);
     double u[NC], P[NC];
     load_state<NC>(PASS == 1 ? A.UL : A.U1, N, i, u);
     const Bounds b = load_bounds(A, N, i);
@@ -855,7 +883,7 @@ __global__ __launch_bounds__(kBlock) void k_fin(DevGraphT<LT> G, StageArgsT<LT> 
   const RowIdx<DIM, int32_t> jv(colp, i);
   const RowIdx<DIM, uint8_t> tv(trkp, i);
   RowCtx<DIM> R;
-  load_row<DIM>(G, A, i, *A.tau, R);
+  load_row<DIM>(G, A, i, A.tau[member(A, i)], R);
   const double lam = 1.0 / G.lfac[i];
   double u2[NC];
   load_state<NC>(A.U1, N, i, u2);
@@ -905,14 +933,15 @@ template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_slip(int nslip,
                                                  const int32_t *__restrict__ idx,
                                                  const double *__restrict__ nrm,
-                                                 int64_t N, double *__restrict__ U) {
+                                                 int stride, int64_t N,
+                                                 double *__restrict__ U) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
   if (t >= nslip) return;
   const int64_t i = idx[t];
   double n[DIM], mn = 0.0;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
-    n[k] = nrm[(int64_t)k * nslip + t];
+    n[k] = nrm[(int64_t)k * stride + t];
     mn += U[(1 + k) * N + i] * n[k];
   }
 #pragma unroll
@@ -933,17 +962,19 @@ __global__ __launch_bounds__(kBlock) void k_copy8(const double *__restrict__ src
   if (t < n8) dst[t] = src[t];
 }
 
-__global__ void k_set_scalar(double *p, double v) {
-  if (threadIdx.x == 0) p[0] = v;
+__global__ void k_set_scalar(double *p, double v, int n) {
+  const int t = blockIdx.x * 64 + threadIdx.x;
+  if (t < n) p[t] = v;
 }
 
-__global__ void k_add_scalar(double *acc, const double *v) {
-  if (threadIdx.x == 0) acc[0] += v[0];
+__global__ void k_add_scalar(double *acc, const double *v, int n) {
+  const int t = blockIdx.x * 64 + threadIdx.x;
+  if (t < n) acc[t] += v[t];
 }
 
-__global__ void k_clear_flags(int *flags) {
-  const int t = threadIdx.x;
-  if (t < 4) flags[t] = t == 2 ? INT_MAX : 0;
+__global__ void k_clear_flags(int *flags, int n) {
+  const int t = blockIdx.x * 64 + threadIdx.x;
+  if (t < 4 * n) flags[t] = (t & 3) == 2 ? INT_MAX : 0;
 }
 
 template <int DIM>
@@ -997,9 +1028,13 @@ void stage_impl(const Gas &gas, const DevGraphT<LT> &G, const StageArgsT<LT> &A,
   if (auto_dt) {
     NS_LAUNCH("dt_partial", hipLaunchKernelGGL((k_dt_partial<DIM, LT>), grid, block, 0, s,
                                                G, A.d, A.partial));
-    NS_LAUNCH("dt_final", hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1024), 0, s,
-                                             A.partial, (int64_t)grid.x, cfl,
-                                             A.tau));
+    if (A.seg)
+      NS_LAUNCH("dt_final", hipLaunchKernelGGL(k_dt_final_members, dim3((unsigned)A.nmem),
+                                               dim3(1024), 0, s, A.partial, A.mblk, cfl,
+                                               A.tau));
+    else
+      NS_LAUNCH("dt_final", hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1024), 0, s,
+                                               A.partial, (int64_t)grid.x, cfl, A.tau));
   }
   NS_LAUNCH("lo", hipLaunchKernelGGL((k_lo<DIM, LT>), grid, block, 0, s, G, A, gas));
   if (limiter == 1) {
@@ -1053,8 +1088,12 @@ void dt_impl(const Gas &gas, const DevGraphT<LT> &G, const StageArgsT<LT> &A, do
   hipLaunchKernelGGL((k_dt_partial<DIM, LT>), grid, block, 0, s, G, A.d, A.partial);
   after(prof);
   before(prof, "dt_final");
-  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1024), 0, s, A.partial,
-                     (int64_t)grid.x, cfl, A.tau);
+  if (A.seg)
+    hipLaunchKernelGGL(k_dt_final_members, dim3((unsigned)A.nmem), dim3(1024), 0, s,
+                       A.partial, A.mblk, cfl, A.tau);
+  else
+    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1024), 0, s, A.partial, (int64_t)grid.x,
+                       cfl, A.tau);
   after(prof);
 }
 
@@ -1110,21 +1149,23 @@ template void launch_dt_only<float>(int, const Gas &, const DevGraphT<float> &,
                                     void *);
 
 void launch_slip(int dim, int64_t N, int nslip, const int32_t *idx,
-                 const double *nrm, double *U, hipStream_t s) {
+                 const double *nrm, double *U, hipStream_t s, int stride) {
   if (nslip <= 0) return;
+  if (stride < 0) stride = nslip;
   const dim3 grid((unsigned)((nslip + kBlock - 1) / kBlock)), block(kBlock);
   if (dim == 2)
-    hipLaunchKernelGGL(k_slip<2>, grid, block, 0, s, nslip, idx, nrm, N, U);
+    hipLaunchKernelGGL(k_slip<2>, grid, block, 0, s, nslip, idx, nrm, stride, N, U);
   else
-    hipLaunchKernelGGL(k_slip<3>, grid, block, 0, s, nslip, idx, nrm, N, U);
+    hipLaunchKernelGGL(k_slip<3>, grid, block, 0, s, nslip, idx, nrm, stride, N, U);
 }
 
-void launch_set_scalar(double *p, double v, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(64), 0, s, p, v);
+void launch_set_scalar(double *p, double v, hipStream_t s, int n) {
+  hipLaunchKernelGGL(k_set_scalar, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, p, v, n);
 }
 
-void launch_add_scalar(double *acc, const double *v, hipStream_t s) {
-  hipLaunchKernelGGL(k_add_scalar, dim3(1), dim3(64), 0, s, acc, v);
+void launch_add_scalar(double *acc, const double *v, hipStream_t s, int n) {
+  hipLaunchKernelGGL(k_add_scalar, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, acc, v,
+                     n);
 }
 
 void launch_copy(const void *src, void *dst, int64_t n16, int word,
@@ -1139,8 +1180,9 @@ void launch_copy(const void *src, void *dst, int64_t n16, int word,
                        static_cast<double2 *>(dst), n16);
 }
 
-void launch_clear_flags(int *flags, hipStream_t s) {
-  hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, s, flags);
+void launch_clear_flags(int *flags, hipStream_t s, int n) {
+  hipLaunchKernelGGL(k_clear_flags, dim3((unsigned)((4 * n + 63) / 64)), dim3(64), 0, s,
+                     flags, n);
 }
 
 void launch_check_state(int dim, int64_t N, const double *U, int *flags,

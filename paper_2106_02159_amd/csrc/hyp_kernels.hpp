@@ -77,6 +77,14 @@ struct StageArgsT {
   // qcnt[p] counts the entries of pass p+1 (reset by k_lo).
   uint32_t *q;
   uint32_t *qcnt;
+  // A pack of several meshes stepped together: member of every 256-row
+  // workgroup (each member's rows start at a workgroup boundary; padding
+  // rows are isolated nodes), member count and workgroup offsets of the
+  // members (nmem + 1 entries).  tau, tacc and flags (4 ints) are then per
+  // member.  seg == nullptr: one mesh.
+  const int32_t *seg = nullptr;
+  const int32_t *mblk = nullptr;
+  int nmem = 1;
 };
 
 using DevGraph = DevGraphT<double>;
@@ -96,15 +104,18 @@ void launch_dt_only(int dim, const Gas &gas, const DevGraphT<LT> &g,
                     void (*before)(void *, const char *), void (*after)(void *),
                     void *prof);
 
+// Slip projection of the listed nodes; the k-th normal component of entry
+// t is nrm[k*stride + t] (stride < 0: nslip).
 void launch_slip(int dim, int64_t N, int nslip, const int32_t *idx,
-                 const double *nrm, double *U, hipStream_t s);
-void launch_set_scalar(double *p, double v, hipStream_t s);
-void launch_add_scalar(double *acc, const double *v, hipStream_t s);  // acc += *v
+                 const double *nrm, double *U, hipStream_t s, int stride = -1);
+void launch_set_scalar(double *p, double v, hipStream_t s, int n = 1);  // p[0..n) = v
+void launch_add_scalar(double *acc, const double *v, hipStream_t s,
+                       int n = 1);  // acc[k] += v[k], k < n
 // plain streaming copy of 16*n16 bytes, `word` (8 or 16) bytes per lane
 // (bandwidth and counter calibration)
 void launch_copy(const void *src, void *dst, int64_t n16, int word,
                  hipStream_t s);
-void launch_clear_flags(int *flags, hipStream_t s);
+void launch_clear_flags(int *flags, hipStream_t s, int n = 1);  // n groups of 4
 void launch_check_state(int dim, int64_t N, const double *U, int *flags,
                         hipStream_t s);
 

@@ -108,6 +108,16 @@ struct ns_solver {
   int64_t N = 0;
   int64_t Np = 0;  // N rounded up to the 64-row slices of the edge arrays
   int W = 0;
+  // a pack of several meshes (ns_pack): members, the first row of each (a
+  // multiple of kBlock; the rows up to the next member are isolated padding
+  // nodes), their node counts and slip-list ranges; seg and mblk on the
+  // device (see StageArgsT)
+  int nmem = 1;
+  bool pack = false;
+  std::vector<ns::MeshGraph> mgs;
+  std::vector<int64_t> mbase, mslip;
+  std::vector<char> mset;
+  int32_t *seg = nullptr, *mblk = nullptr;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::vector<void *> allocs;
@@ -184,6 +194,7 @@ struct ns_solver {
     b.U = a.U; b.Un = a.Un; b.out = a.out; b.aux = a.aux; b.UL = a.UL; b.bnds = a.bnds;
     b.U1 = a.U1; b.partial = a.partial; b.tau = a.tau; b.flags = a.flags;
     b.sa = a.sa; b.sb = a.sb; b.check_cfl = a.check_cfl; b.q = a.q; b.qcnt = a.qcnt;
+    b.seg = a.seg; b.mblk = a.mblk; b.nmem = a.nmem;
     b.alpha = alphaf; b.d = df; b.FH = FHf; b.lt1 = lt1f; b.lt2 = lt2f;
     return b;
   }
@@ -194,6 +205,7 @@ struct ns_solver {
     a.lt1 = lt1; a.lt2 = lt2; a.U1 = U1; a.partial = partial; a.tau = tau;
     a.flags = flags; a.sa = sa; a.sb = sb; a.check_cfl = check;
     a.q = q; a.qcnt = qcnt;
+    a.seg = seg; a.mblk = mblk; a.nmem = nmem;
     return a;
   }
   int fail(int code, const std::string &msg) { err = msg; return code; }
@@ -502,27 +514,69 @@ int ns_graph_export(const ns_graph *g, int32_t *col, double *mij, double *cij,
   return NS_OK;
 }
 
-int ns_solver_footprint(const ns_graph *g, const ns_params *p, int64_t *bytes) {
-  if (!g || !p || !bytes) return NS_EINVAL;
-  const ns::MeshGraph &m = g->mg;
-  const int64_t N = m.N, W = m.W, dim = m.dim, nc = dim + 2;
-  const int64_t Np = (N + 63) / 64 * 64;
+namespace {
+// Rows of a solver: one mesh (N nodes, edge slices padded to 64 rows) or a
+// pack (each member's rows start at a workgroup boundary).
+struct Layout {
+  std::vector<const ns::MeshGraph *> mgs;
+  std::vector<int64_t> base;
+  int64_t N = 0, Np = 0;
+  bool pack = false;
+};
+
+Layout one_mesh(const ns::MeshGraph &m) {
+  Layout L;
+  L.mgs = {&m};
+  L.base = {0};
+  L.N = m.N;
+  L.Np = (m.N + 63) / 64 * 64;
+  return L;
+}
+
+Layout packed(const ns::MeshGraph *const *m, int count) {
+  Layout L;
+  L.pack = true;
+  for (int r = 0; r < count; ++r) {
+    L.mgs.push_back(m[r]);
+    L.base.push_back(L.N);
+    L.N += (m[r]->N + ns::kBlock - 1) / ns::kBlock * ns::kBlock;
+  }
+  L.Np = L.N;
+  return L;
+}
+
+int64_t slip_count(const ns::MeshGraph &m) {
+  int64_t interior = 1;
+  for (int d = 0; d < m.dim; ++d)
+    interior *= m.periodic[d] ? m.n[d] : std::max<int64_t>(m.n[d] - 2, 0);
+  return m.N - interior;
+}
+
+int64_t footprint(const Layout &Lt, const ns_params *p) {
+  const ns::MeshGraph &m = *Lt.mgs[0];
+  const int64_t N = Lt.N, Np = Lt.Np, W = m.W, dim = m.dim, nc = dim + 2;
   const int64_t L = p->precision == NS_PREC_MIXED ? 4 : 8;
   const int64_t nblocks = (N + ns::kBlock - 1) / ns::kBlock;
-  int64_t interior = 1;
-  for (int d = 0; d < dim; ++d)
-    interior *= m.periodic[d] ? m.n[d] : std::max<int64_t>(m.n[d] - 2, 0);
-  const int64_t nslip = N - interior;
+  const int64_t nm = (int64_t)Lt.mgs.size();
+  int64_t nslip = 0;
+  for (const ns::MeshGraph *g : Lt.mgs) nslip += slip_count(*g);
   int64_t b = 0;
   b += W * Np * (4 + 1) + W * Np * L * (1 + dim);   // col, trk, m_ij, c_ij
   b += 4 * N * 8 + N;                                // m_i, 1/m_i, lfac, r_i, wall
   b += 3 * nc * N * 8 + (dim + 5) * N * 8;           // states, aux
   b += N * L + W * Np * L + nc * N * 8 + nc * N * L;  // alpha, d, U^L, F^H
   b += 3 * N * 8 + 2 * W * Np * L + nc * N * 8;      // bounds, l~ (2), U^(1)
-  b += nblocks * 8 + 8 + 4 * 4 + 8;                  // partial, tau, flags, time
+  b += nblocks * 8 + nm * (8 + 4 * 4 + 8);           // partial, tau, flags, time
   b += W * Np * 4 + 2 * 4;                           // root work list
   b += nslip * 4 + dim * nslip * 8;                  // slip list
-  *bytes = b;
+  if (Lt.pack) b += nblocks * 4 + (nm + 1) * 4;      // member of each workgroup
+  return b;
+}
+}  // namespace
+
+int ns_solver_footprint(const ns_graph *g, const ns_params *p, int64_t *bytes) {
+  if (!g || !p || !bytes) return NS_EINVAL;
+  *bytes = footprint(one_mesh(g->mg), p);
   return NS_OK;
 }
 
@@ -545,9 +599,8 @@ void keep_pool_memory() {
 }
 }  // namespace
 
-int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
-                     ns_solver **out) {
-  if (!g || !p || !out) { g_create_error = "null argument"; return NS_EINVAL; }
+namespace {
+int create_impl(const Layout &Lt, const ns_params *p, void *stream, ns_solver **out) {
   if (!(p->gamma > 1.0 && p->gamma <= 5.0 / 3.0 + 1e-12) ||
       !(p->cfl > 0.0 && p->cfl <= 1.0) || p->indicator < 0 || p->indicator > 2 ||
       p->limiter < 0 || p->limiter > 2 || (p->passes != 1 && p->passes != 2) ||
@@ -558,21 +611,27 @@ int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
                      "precision NS_PREC_FP64 or NS_PREC_MIXED)";
     return NS_EINVAL;
   }
-  if ((int64_t)g->mg.W * ((g->mg.N + 63) / 64 * 64) > (int64_t)UINT32_MAX) {
+  const ns::MeshGraph &m0 = *Lt.mgs[0];
+  if ((int64_t)m0.W * Lt.Np > (int64_t)UINT32_MAX) {
     g_create_error = "mesh too large: edge indices must fit in 32 bits";
     return NS_EINVAL;
   }
   ns_solver *s = new (std::nothrow) ns_solver;
   if (!s) { g_create_error = "host allocation"; return NS_ENOMEM; }
   keep_pool_memory();
-  s->mg = g->mg;
+  s->mg = m0;
   s->prm = *p;
   s->mixed = p->precision == NS_PREC_MIXED;
-  s->dim = g->mg.dim;
+  s->dim = m0.dim;
   s->nc = s->dim + 2;
-  s->N = g->mg.N;
-  s->Np = (g->mg.N + 63) / 64 * 64;
-  s->W = g->mg.W;
+  s->N = Lt.N;
+  s->Np = Lt.Np;
+  s->W = m0.W;
+  s->pack = Lt.pack;
+  s->nmem = (int)Lt.mgs.size();
+  for (const ns::MeshGraph *g : Lt.mgs) s->mgs.push_back(*g);
+  s->mbase = Lt.base;
+  s->mset.assign(s->nmem, 0);
   const double gm = p->gamma;
   s->gas.gamma = gm;
   s->gas.gm1 = gm - 1.0;
@@ -640,9 +699,13 @@ int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
   NS_ALLOC(s->bnds, 3 * N);
   NS_ALLOC(s->U1, nc * N);
   NS_ALLOC(s->partial, nblocks);
-  NS_ALLOC(s->tau, 1);
-  NS_ALLOC(s->flags, 4);
-  NS_ALLOC(s->tacc, 1);
+  NS_ALLOC(s->tau, s->nmem);
+  NS_ALLOC(s->flags, 4 * s->nmem);
+  NS_ALLOC(s->tacc, s->nmem);
+  if (s->pack) {
+    NS_ALLOC(s->seg, nblocks);
+    NS_ALLOC(s->mblk, s->nmem + 1);
+  }
   // limiter root work list, large enough for every edge
   NS_ALLOC(s->q, W * Np);
   NS_ALLOC(s->qcnt, 2);
@@ -654,26 +717,46 @@ int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
   // --- upload the graph: generate slot by slot, place into the sliced ELL
   // layout (entry (k, i) at ((i/64)*W + k)*64 + i%64) on the host, upload
   {
-    std::vector<int32_t> col(N), scol(W * Np, -1);
-    std::vector<uint8_t> trk(N), strk(W * Np, 0);
-    std::vector<double> tmp(N), cc((size_t)dim * N);
+    const int nm = s->nmem;
+    const int kc = (int)(W - 1) / 2;  // slot of the zero offset: the node itself
+    auto mend = [&](int r) { return r + 1 < nm ? Lt.base[r + 1] : N; };
+    std::vector<int32_t> scol(W * Np, -1);
+    std::vector<uint8_t> strk(W * Np, 0);
     std::vector<int> cnt(N, 0);
     auto sl = [W](int k, int64_t i) { return ((i >> 6) * W + k) * 64 + (i & 63); };
-    // m_ij and the components of c_ij, one array at a time
+    // m_ij and the components of c_ij, one array at a time; member r's rows
+    // and column indices are shifted by its first row
     for (int a = -1; a < dim; ++a) {
       std::vector<double> sv(W * Np, 0.0);
-      for (int k = 0; k < W; ++k) {
-        double *cp[3] = {cc.data(), cc.data() + N, dim == 3 ? cc.data() + 2 * N : nullptr};
-        s->mg.fill_slot(k, col.data(), trk.data(), a < 0 ? tmp.data() : nullptr,
-                        a < 0 ? nullptr : cp);
-        const double *src = a < 0 ? tmp.data() : cc.data() + (size_t)a * N;
-        for (int64_t i = 0; i < N; ++i) sv[sl(k, i)] = src[i];
-        if (a < 0) {
-          for (int64_t i = 0; i < N; ++i) {
-            scol[sl(k, i)] = col[i];
-            strk[sl(k, i)] = trk[i];
-            cnt[i] += col[i] >= 0;
+      for (int r = 0; r < nm; ++r) {
+        const ns::MeshGraph &m = *Lt.mgs[r];
+        const int64_t b0 = Lt.base[r], Nr = m.N;
+        std::vector<int32_t> col(Nr);
+        std::vector<uint8_t> trk(Nr);
+        std::vector<double> tmp(Nr), cc((size_t)dim * Nr);
+        for (int k = 0; k < W; ++k) {
+          double *cp[3] = {cc.data(), cc.data() + Nr, dim == 3 ? cc.data() + 2 * Nr : nullptr};
+          m.fill_slot(k, col.data(), trk.data(), a < 0 ? tmp.data() : nullptr,
+                      a < 0 ? nullptr : cp);
+          const double *src = a < 0 ? tmp.data() : cc.data() + (size_t)a * Nr;
+          for (int64_t i = 0; i < Nr; ++i) sv[sl(k, b0 + i)] = src[i];
+          if (a < 0) {
+            for (int64_t i = 0; i < Nr; ++i) {
+              scol[sl(k, b0 + i)] = col[i] >= 0 ? (int32_t)(b0 + col[i]) : -1;
+              strk[sl(k, b0 + i)] = trk[i];
+              cnt[b0 + i] += col[i] >= 0;
+            }
           }
+        }
+        // padding rows of a pack: isolated nodes (only the diagonal entry,
+        // m_ii = 1, c_ii = 0)
+        for (int64_t i = b0 + Nr; i < mend(r); ++i) {
+          if (a < 0) {
+            scol[sl(kc, i)] = (int32_t)i;
+            strk[sl(kc, i)] = (uint8_t)kc;
+            cnt[i] = 1;
+          }
+          sv[sl(kc, i)] = a < 0 ? 1.0 : 0.0;
         }
       }
       if (s->mixed) {
@@ -691,30 +774,51 @@ int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
     if (e == hipSuccess)
       e = hipMemcpy(s->trk, strk.data(), W * Np, hipMemcpyHostToDevice);
     if (e != hipSuccess) return bail(NS_EHIP, "graph upload failed");
-    std::vector<double> mi(N), bnd((size_t)dim * N), rmi(N), lfac(N), rrel(N);
-    std::vector<uint8_t> wall(N);
-    s->mg.fill_nodes(mi.data(), bnd.data(), wall.data());
-    double vol = 0.0;
-    for (int64_t i = 0; i < N; ++i) vol += mi[i];
+    // node data; padding rows: m_i = 1, |I(i)| - 1 := 1, r_i = 0, no wall
+    std::vector<double> mi(N, 1.0), rmi(N, 1.0), lfac(N, 1.0), rrel(N, 0.0);
+    std::vector<uint8_t> wall(N, 0);
     std::vector<int32_t> sidx;
-    std::vector<double> snrm;
-    for (int64_t i = 0; i < N; ++i) {
-      rmi[i] = 1.0 / mi[i];
-      lfac[i] = (double)(cnt[i] - 1);
-      rrel[i] = p->relax * std::pow(mi[i] / vol, 1.5 / dim);
-      if (wall[i]) sidx.push_back((int32_t)i);
+    std::vector<double> nrm;  // unit normals of the slip nodes, node by node
+    s->mslip.assign(1, 0);
+    for (int r = 0; r < nm; ++r) {
+      const ns::MeshGraph &m = *Lt.mgs[r];
+      const int64_t b0 = Lt.base[r], Nr = m.N;
+      std::vector<double> mr(Nr), bnd((size_t)dim * Nr);
+      std::vector<uint8_t> wr(Nr);
+      m.fill_nodes(mr.data(), bnd.data(), wr.data());
+      double vol = 0.0;
+      for (int64_t i = 0; i < Nr; ++i) vol += mr[i];
+      for (int64_t i = 0; i < Nr; ++i) {
+        mi[b0 + i] = mr[i];
+        rmi[b0 + i] = 1.0 / mr[i];
+        lfac[b0 + i] = (double)(cnt[b0 + i] - 1);
+        rrel[b0 + i] = p->relax * std::pow(mr[i] / vol, 1.5 / dim);
+        wall[b0 + i] = wr[i];
+        if (!wr[i]) continue;
+        sidx.push_back((int32_t)(b0 + i));
+        double nn = 0.0, v[3];
+        for (int q = 0; q < dim; ++q) { v[q] = bnd[(size_t)q * Nr + i]; nn += v[q] * v[q]; }
+        nn = std::sqrt(nn);
+        for (int q = 0; q < dim; ++q) nrm.push_back(v[q] / nn);
+      }
+      s->mslip.push_back((int64_t)sidx.size());
     }
     s->nslip = (int)sidx.size();
-    snrm.resize((size_t)dim * s->nslip);
-    for (int t = 0; t < s->nslip; ++t) {
-      const int64_t i = sidx[t];
-      double nn = 0.0, v[3];
-      for (int q = 0; q < dim; ++q) { v[q] = bnd[(size_t)q * N + i]; nn += v[q] * v[q]; }
-      nn = std::sqrt(nn);
-      for (int q = 0; q < dim; ++q) snrm[(size_t)q * s->nslip + t] = v[q] / nn;
-    }
+    std::vector<double> snrm((size_t)dim * s->nslip);
+    for (int t = 0; t < s->nslip; ++t)
+      for (int q = 0; q < dim; ++q) snrm[(size_t)q * s->nslip + t] = nrm[(size_t)t * dim + q];
     NS_ALLOC(s->slip_idx, s->nslip);
     NS_ALLOC(s->slip_n, dim * s->nslip);
+    // member of every workgroup, workgroup offsets of the members
+    std::vector<int32_t> hseg, hmblk;
+    if (s->pack) {
+      hseg.resize(nblocks);
+      for (int r = 0; r < nm; ++r) {
+        hmblk.push_back((int32_t)(Lt.base[r] / ns::kBlock));
+        for (int64_t b = Lt.base[r] / ns::kBlock; b < mend(r) / ns::kBlock; ++b) hseg[b] = r;
+      }
+      hmblk.push_back((int32_t)nblocks);
+    }
     struct { void *dst; const void *src; size_t n; } ups[] = {
         {s->mi, mi.data(), N * sizeof(double)},
         {s->rmi, rmi.data(), N * sizeof(double)},
@@ -722,13 +826,33 @@ int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
         {s->rrel, rrel.data(), N * sizeof(double)},
         {s->wall, wall.data(), (size_t)N},
         {s->slip_idx, sidx.data(), sidx.size() * sizeof(int32_t)},
-        {s->slip_n, snrm.data(), snrm.size() * sizeof(double)}};
+        {s->slip_n, snrm.data(), snrm.size() * sizeof(double)},
+        {s->seg, hseg.data(), hseg.size() * sizeof(int32_t)},
+        {s->mblk, hmblk.data(), hmblk.size() * sizeof(int32_t)}};
     e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return bail(NS_EHIP, "stream synchronize");
     for (auto &u : ups) {
       if (u.n == 0) continue;
       e = hipMemcpy(u.dst, u.src, u.n, hipMemcpyHostToDevice);
       if (e != hipSuccess) return bail(NS_EHIP, "graph upload failed");
+    }
+    // padding rows of a pack hold a constant admissible state in every
+    // state buffer (they have no neighbours, so the steps keep it)
+    if (s->pack) {
+      std::vector<double> pad((size_t)nc * ns::kBlock, 0.0);
+      for (int t = 0; t < ns::kBlock; ++t) {
+        pad[t] = 1.0;
+        pad[(size_t)(nc - 1) * ns::kBlock + t] = 1.0;
+      }
+      for (int r = 0; r < nm; ++r) {
+        const int64_t first = Lt.base[r] + Lt.mgs[r]->N, count = mend(r) - first;
+        if (count <= 0) continue;
+        for (int b = 0; b < 3 && e == hipSuccess; ++b)
+          e = hipMemcpy2D(s->S[b] + first, N * sizeof(double), pad.data(),
+                          ns::kBlock * sizeof(double), count * sizeof(double), nc,
+                          hipMemcpyHostToDevice);
+      }
+      if (e != hipSuccess) return bail(NS_EHIP, "padding upload failed");
     }
   }
   // zero the scratch edge arrays once: entries never written stay zero
@@ -743,6 +867,13 @@ int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
 #undef NS_ALLOC
   *out = s;
   return NS_OK;
+}
+}  // namespace
+
+int ns_solver_create(const ns_graph *g, const ns_params *p, void *stream,
+                     ns_solver **out) {
+  if (!g || !p || !out) { g_create_error = "null argument"; return NS_EINVAL; }
+  return create_impl(one_mesh(g->mg), p, stream, out);
 }
 
 void ns_solver_destroy(ns_solver *s) {
@@ -917,7 +1048,7 @@ hipGraphExec_t step_graph(ns_solver *s) {
   }
   const int last = s->last_out;
   (void)ssprk3_enqueue(s, 0.0, true);
-  ns::launch_add_scalar(s->tacc, s->tau, s->stream);
+  ns::launch_add_scalar(s->tacc, s->tau, s->stream, s->nmem);
   s->last_out = last;
   hipGraph_t gr = nullptr;
   e = hipStreamEndCapture(s->stream, &gr);
@@ -944,8 +1075,8 @@ int ns_step_cfl_async(ns_solver *s, int nsteps) {
     if (e != hipSuccess) return s->hipfail(e, "event create");
   }
   if (!s->async_open) {  // a new run: the sticky status and the time start at 0
-    ns::launch_clear_flags(s->flags, s->stream);
-    ns::launch_set_scalar(s->tacc, 0.0, s->stream);
+    ns::launch_clear_flags(s->flags, s->stream, s->nmem);
+    ns::launch_set_scalar(s->tacc, 0.0, s->stream, s->nmem);
     s->async_open = true;
   }
   hipError_t e = hipSuccess;
@@ -957,7 +1088,7 @@ int ns_step_cfl_async(ns_solver *s, int nsteps) {
       if (e != hipSuccess) break;
     } else {
       (void)ssprk3_enqueue(s, 0.0, true);
-      ns::launch_add_scalar(s->tacc, s->tau, s->stream);
+      ns::launch_add_scalar(s->tacc, s->tau, s->stream, s->nmem);
     }
     s->last_out = o1;
     s->cur = o1;
@@ -991,6 +1122,141 @@ int ns_query(ns_solver *s, int *done) {
   const int rc = ns_inflight(s, &n);
   *done = n == 0;
   return rc;
+}
+
+struct ns_pack {
+  ns_solver *s = nullptr;
+};
+
+int ns_pack_footprint(const ns_graph *const *graphs, int count, const ns_params *p,
+                      int64_t *bytes) {
+  if (!graphs || count < 1 || !p || !bytes) return NS_EINVAL;
+  std::vector<const ns::MeshGraph *> m;
+  for (int r = 0; r < count; ++r) {
+    if (!graphs[r] || graphs[r]->mg.dim != graphs[0]->mg.dim) return NS_EINVAL;
+    m.push_back(&graphs[r]->mg);
+  }
+  *bytes = footprint(packed(m.data(), count), p);
+  return NS_OK;
+}
+
+int ns_pack_create(const ns_graph *const *graphs, int count, const ns_params *p,
+                   void *hip_stream, ns_pack **out) {
+  if (!graphs || count < 1 || !p || !out) {
+    g_create_error = "null argument or empty pack";
+    return NS_EINVAL;
+  }
+  std::vector<const ns::MeshGraph *> m;
+  for (int r = 0; r < count; ++r) {
+    if (!graphs[r] || graphs[r]->mg.dim != graphs[0]->mg.dim) {
+      g_create_error = "pack members must be graphs of one dimension";
+      return NS_EINVAL;
+    }
+    m.push_back(&graphs[r]->mg);
+  }
+  ns_pack *k = new (std::nothrow) ns_pack;
+  if (!k) { g_create_error = "host allocation"; return NS_ENOMEM; }
+  const int rc = create_impl(packed(m.data(), count), p, hip_stream, &k->s);
+  if (rc != NS_OK) {
+    delete k;
+    return rc;
+  }
+  *out = k;
+  return NS_OK;
+}
+
+void ns_pack_destroy(ns_pack *k) {
+  if (!k) return;
+  ns_solver_destroy(k->s);
+  delete k;
+}
+
+int ns_pack_set_state(ns_pack *k, int r, const double *U) {
+  if (!k || !U) return NS_EINVAL;
+  ns_solver *s = k->s;
+  if (r < 0 || r >= s->nmem) return s->fail(NS_EINVAL, "no such pack member");
+  const int64_t Nr = s->mgs[r].N, b0 = s->mbase[r], nc = s->nc, dim = s->dim;
+  for (int64_t i = 0; i < Nr; ++i) {
+    const double rho = U[i], E = U[(dim + 1) * Nr + i];
+    double m2 = 0.0;
+    bool fin = std::isfinite(rho) && std::isfinite(E);
+    for (int d = 0; d < dim; ++d) {
+      const double mk = U[(1 + d) * Nr + i];
+      fin = fin && std::isfinite(mk);
+      m2 += mk * mk;
+    }
+    if (!fin || !(rho > 0.0) || !(E - 0.5 * m2 / rho > 0.0)) {
+      char buf[128];
+      snprintf(buf, sizeof buf, "state of pack member %d not admissible at node %lld", r,
+               (long long)i);
+      return s->fail(NS_ENOTADMISSIBLE, buf);
+    }
+  }
+  double *dst = s->S[s->cur] + b0;
+  hipError_t e = hipMemcpy2DAsync(dst, s->N * sizeof(double), U, Nr * sizeof(double),
+                                  Nr * sizeof(double), nc, hipMemcpyHostToDevice, s->stream);
+  if (e != hipSuccess) return s->hipfail(e, "state upload");
+  const int64_t t0 = s->mslip[r], t1 = s->mslip[r + 1];
+  ns::launch_slip(s->dim, s->N, (int)(t1 - t0), s->slip_idx + t0, s->slip_n + t0,
+                  s->S[s->cur], s->stream, s->nslip);
+  e = hipStreamSynchronize(s->stream);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return s->hipfail(e, "state upload");
+  s->mset[r] = 1;
+  s->has_state = std::all_of(s->mset.begin(), s->mset.end(), [](char c) { return c != 0; });
+  return NS_OK;
+}
+
+int ns_pack_get_state(ns_pack *k, int r, double *U) {
+  if (!k || !U) return NS_EINVAL;
+  ns_solver *s = k->s;
+  if (r < 0 || r >= s->nmem) return s->fail(NS_EINVAL, "no such pack member");
+  if (!s->mset[r]) return s->fail(NS_ESTATE, "no state set");
+  const int64_t Nr = s->mgs[r].N;
+  hipError_t e = hipMemcpy2DAsync(U, Nr * sizeof(double), s->S[s->cur] + s->mbase[r],
+                                  s->N * sizeof(double), Nr * sizeof(double), s->nc,
+                                  hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return s->hipfail(e, "state download");
+  return NS_OK;
+}
+
+int ns_pack_step_cfl_async(ns_pack *k, int nsteps) {
+  if (!k) return NS_EINVAL;
+  return ns_step_cfl_async(k->s, nsteps);
+}
+
+int ns_pack_inflight(ns_pack *k, int *calls) {
+  if (!k) return NS_EINVAL;
+  return ns_inflight(k->s, calls);
+}
+
+int ns_pack_finish(ns_pack *k, int *status, double *t) {
+  if (!k || !status || !t) return NS_EINVAL;
+  ns_solver *s = k->s;
+  if (!s->async_open) return s->fail(NS_ESTATE, "no asynchronous steps enqueued");
+  s->async_open = false;
+  const int nm = s->nmem;
+  std::vector<int> fl(4 * (size_t)nm);
+  std::vector<double> ta(nm);
+  hipError_t e = hipMemcpyAsync(fl.data(), s->flags, fl.size() * sizeof(int),
+                                hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ta.data(), s->tacc, nm * sizeof(double), hipMemcpyDeviceToHost,
+                       s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return s->hipfail(e, "asynchronous step status");
+  for (int r = 0; r < nm; ++r) {
+    status[r] = fl[4 * r] ? NS_ECFL : fl[4 * r + 1] ? NS_EBOUNDS : NS_OK;
+    t[r] = ta[r];
+  }
+  return NS_OK;
+}
+
+const char *ns_pack_error(const ns_pack *k) {
+  if (!k) return ns_create_error();
+  return k->s->err.c_str();
 }
 
 int ns_async_finish(ns_solver *s, double *t) {
