@@ -157,7 +157,8 @@ def serve_bench(args):
         time.sleep(1e-3)
     warm.close()
     sv = abi.Server(mem, max_running=args.max_running, precision=prec,
-                    chunk=args.serve_chunk, depth=2)
+                    chunk=args.serve_chunk, depth=2, pack_nodes=args.pack_nodes,
+                    pack_max=args.pack_max)
     t0 = time.perf_counter()
     pending = list(range(len(reqs)))
     ids, info = {}, {}
@@ -198,9 +199,12 @@ def serve_bench(args):
                                f"four-quadrant data, {args.serve_steps} SSPRK3 steps "
                                f"each, Poisson arrivals at {args.rate}/s, admission by "
                                f"device footprint (budget {args.serve_mem_gb} GiB, at "
-                               f"most {args.max_running} running), chunks of "
-                               f"{args.serve_chunk} steps, {args.hw_queues} hardware "
-                               f"queues",
+                               f"most {args.max_running} running units), requests "
+                               f"of at most {args.pack_nodes // 2} rows packed "
+                               f"(consecutive, same step count, up to "
+                               f"{args.pack_nodes} rows and {args.pack_max} members "
+                               f"per pack), chunks of {args.serve_chunk} steps, "
+                               f"{args.hw_queues} hardware queues",
                    "requests": args.requests},
         "latency_ms": {"p50": float(np.percentile(lat, 50)),
                        "p99": float(np.percentile(lat, 99)),
@@ -209,6 +213,9 @@ def serve_bench(args):
         "host_progress_s": t_progress,
         "peak_running": stats.peak_running,
         "peak_bytes": stats.peak_bytes,
+        "units": stats.units,
+        "host_s": {"admit": stats.host_admit_s, "top_up": stats.host_topup_s,
+                   "finish": stats.host_finish_s},
     }
 
 
@@ -242,6 +249,11 @@ def main():
     ap.add_argument("--serve-mem-gb", type=float, default=160.0)
     ap.add_argument("--serve-chunk", type=int, default=2,
                     help="steps per enqueued chunk of a running request")
+    ap.add_argument("--pack-nodes", type=int, default=1 << 21,
+                    help="serving: rows of a pack of small requests at most (0: "
+                         "every request gets its own solver)")
+    ap.add_argument("--pack-max", type=int, default=64,
+                    help="serving: members of a pack at most")
     ap.add_argument("--hw-queues", type=int, default=16,
                     help="hardware queues for the serving streams (GPU_MAX_HW_QUEUES, "
                          "at most 32)")

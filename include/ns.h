@@ -283,26 +283,33 @@ const char *ns_pack_error(const ns_pack *k);
 
 /* ---- serving: continuous batching of independent simulations ------------
  * A server holds a FIFO queue of requests (uniform-mesh Euler problems: mesh,
- * initial state, number of SSPRK(3,3) steps with the CFL time step).  A
- * request is admitted, in order, when its device footprint
- * (ns_solver_footprint) fits in mem_bytes beside the running ones and fewer
- * than max_running are running; it then gets its own solver on its own HIP
- * stream; its steps are enqueued in chunks of `chunk` steps, at most
- * `depth` chunks in flight, one new chunk per request per progress call
- * (round robin), so running requests advance together and overlap on the
- * device.  ns_server_progress never blocks on the device: it tops up the
- * running requests' chunks, collects finished requests (their states are
- * copied to host memory and their device memory freed) and admits queued
- * ones.  A
+ * initial state, number of SSPRK(3,3) steps with the CFL time step).
+ * Requests are admitted in order as units: a request whose mesh has at most
+ * pack_nodes / 2 rows (N rounded up to 256) is packed (ns_pack_*) with the
+ * consecutive queued requests of the same step count and dimension, up to
+ * pack_nodes rows and pack_max members; any other request gets its own
+ * solver.  A unit is admitted when its device footprint (ns_pack_footprint,
+ * ns_solver_footprint) fits in mem_bytes beside the running ones and fewer
+ * than max_running units are running; it runs on its own HIP stream; its
+ * steps are enqueued in chunks of `chunk` steps, at most `depth` chunks in
+ * flight, one new chunk per unit per progress call (round robin), so
+ * running units advance together and overlap on the device.
+ * ns_server_progress never blocks on the device: it tops up the running
+ * units' chunks, collects finished units (their states are copied to host
+ * memory and their device memory freed) and admits queued requests.  A
  * request's result depends only on its input (deterministic kernels, no
- * shared device data): it is bit-identical alone and in any mix. */
+ * shared device data, pack members bit-identical to their own solvers): it
+ * is bit-identical alone and in any mix. */
 typedef struct ns_server ns_server;
 typedef struct ns_server_params {
   int64_t mem_bytes;  /* device memory the running requests may use        */
-  int max_running;    /* running requests at most, >= 1                    */
+  int max_running;    /* running units (solvers or packs) at most, >= 1    */
   int chunk;          /* steps per enqueued chunk, >= 1                    */
-  int depth;          /* chunks in flight per request, >= 1                */
+  int depth;          /* chunks in flight per unit, >= 1                   */
   ns_params solver;   /* parameters of every request's solver              */
+  int64_t pack_nodes; /* rows of a pack at most (meshes rounded up to 256  */
+                      /* rows; 0: every request gets its own solver)       */
+  int pack_max;       /* members of a pack at most, >= 2 with packs        */
 } ns_server_params;
 enum { NS_REQ_QUEUED = 0, NS_REQ_RUNNING = 1, NS_REQ_FINISHED = 2 };
 typedef struct ns_request_info {
@@ -317,6 +324,9 @@ typedef struct ns_request_info {
 typedef struct ns_server_stats {
   int64_t submitted, finished, queued, running;
   int64_t peak_running, peak_bytes, bytes_in_use;
+  int64_t units;                        /* units admitted (solvers + packs)  */
+  double host_admit_s, host_topup_s, host_finish_s;  /* host time spent in */
+                                        /* admissions, top-ups, collections  */
 } ns_server_stats;
 
 /* NS_EINVAL for bad parameters. */

@@ -204,7 +204,8 @@ class ParInfo(C.Structure):
 
 class ServerParams(C.Structure):
     _fields_ = [("mem_bytes", C.c_int64), ("max_running", C.c_int), ("chunk", C.c_int),
-                ("depth", C.c_int), ("solver", Params)]
+                ("depth", C.c_int), ("solver", Params), ("pack_nodes", C.c_int64),
+                ("pack_max", C.c_int)]
 
 
 class RequestInfo(C.Structure):
@@ -215,7 +216,9 @@ class RequestInfo(C.Structure):
 
 class ServerStats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("submitted", "finished", "queued", "running",
-                                        "peak_running", "peak_bytes", "bytes_in_use")]
+                                        "peak_running", "peak_bytes", "bytes_in_use",
+                                        "units")] + \
+               [(k, C.c_double) for k in ("host_admit_s", "host_topup_s", "host_finish_s")]
 
 
 REQ_QUEUED, REQ_RUNNING, REQ_FINISHED = 0, 1, 2
@@ -308,11 +311,11 @@ class Server:
     """ns_server_*: continuous batching of independent simulations."""
 
     def __init__(self, mem_bytes, max_running=64, gamma=1.4, cfl=0.5,
-                 precision=PREC_FP64, chunk=2, depth=2):
+                 precision=PREC_FP64, chunk=2, depth=2, pack_nodes=0, pack_max=64):
         L = lib()
         self.prm = ServerParams(int(mem_bytes), int(max_running), int(chunk), int(depth),
                                 Params(gamma, cfl, IND_ENTROPY, LIM_CONVEX, 2, 1.0,
-                                       precision))
+                                       precision), int(pack_nodes), int(pack_max))
         h = C.c_void_p()
         rc = L.ns_server_create(C.byref(self.prm), C.byref(h))
         if rc != NS_OK:

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -19,6 +20,7 @@
 #include "element.hpp"
 #include "graph.hpp"
 #include "hyp_kernels.hpp"
+#include "device.hpp"
 #include "par_kernels.hpp"
 
 struct ns_graph {
@@ -514,6 +516,22 @@ int ns_graph_export(const ns_graph *g, int32_t *col, double *mij, double *cij,
   return NS_OK;
 }
 
+extern "C++" {
+namespace ns {
+int current_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return dev;
+}
+void use_device(int device) {
+  if (hipSetDevice(device) != hipSuccess) (void)hipGetLastError();
+}
+}  // namespace ns
+}  // extern "C++"
+
 namespace {
 // Rows of a solver: one mesh (N nodes, edge slices padded to 64 rows) or a
 // pack (each member's rows start at a workgroup boundary).
@@ -584,18 +602,24 @@ namespace {
 // Keep memory freed by hipFreeAsync in the device's default pool instead of
 // returning it to the driver, so that solvers created after others were
 // destroyed reuse it without new driver allocations.
+// (solvers may be created from several threads: once per device)
 void keep_pool_memory() {
-  static bool done = false;
-  if (done) return;
+  static std::mutex mu;
+  static std::vector<int> done;
   int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  if (std::find(done.begin(), done.end(), dev) != done.end()) return;
   hipMemPool_t pool;
-  if (hipGetDevice(&dev) == hipSuccess &&
-      hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
     uint64_t thr = UINT64_MAX;
     (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
   }
   (void)hipGetLastError();
-  done = true;
+  done.push_back(dev);
 }
 }  // namespace
 
@@ -762,17 +786,21 @@ int create_impl(const Layout &Lt, const ns_params *p, void *stream, ns_solver **
       if (s->mixed) {
         // FP32 storage: rounding to nearest keeps c_ij = -c_ji and m_ij = m_ji
         const std::vector<float> svf(sv.begin(), sv.end());
-        e = hipMemcpy(a < 0 ? s->mijf : s->cf[a], svf.data(), W * Np * sizeof(float),
-                      hipMemcpyHostToDevice);
+        e = hipMemcpyAsync(a < 0 ? s->mijf : s->cf[a], svf.data(), W * Np * sizeof(float),
+                           hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
       } else {
-        e = hipMemcpy(a < 0 ? s->mij : s->c[a], sv.data(), W * Np * sizeof(double),
-                      hipMemcpyHostToDevice);
+        e = hipMemcpyAsync(a < 0 ? s->mij : s->c[a], sv.data(), W * Np * sizeof(double),
+                           hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
       }
       if (e != hipSuccess) return bail(NS_EHIP, "graph upload failed");
     }
-    e = hipMemcpy(s->col, scol.data(), W * Np * sizeof(int32_t), hipMemcpyHostToDevice);
+    e = hipMemcpyAsync(s->col, scol.data(), W * Np * sizeof(int32_t), hipMemcpyHostToDevice,
+                       s->stream);
     if (e == hipSuccess)
-      e = hipMemcpy(s->trk, strk.data(), W * Np, hipMemcpyHostToDevice);
+      e = hipMemcpyAsync(s->trk, strk.data(), W * Np, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return bail(NS_EHIP, "graph upload failed");
     // node data; padding rows: m_i = 1, |I(i)| - 1 := 1, r_i = 0, no wall
     std::vector<double> mi(N, 1.0), rmi(N, 1.0), lfac(N, 1.0), rrel(N, 0.0);
@@ -833,9 +861,12 @@ int create_impl(const Layout &Lt, const ns_params *p, void *stream, ns_solver **
     if (e != hipSuccess) return bail(NS_EHIP, "stream synchronize");
     for (auto &u : ups) {
       if (u.n == 0) continue;
-      e = hipMemcpy(u.dst, u.src, u.n, hipMemcpyHostToDevice);
+      e = hipMemcpyAsync(u.dst, u.src, u.n, hipMemcpyHostToDevice, s->stream);
       if (e != hipSuccess) return bail(NS_EHIP, "graph upload failed");
     }
+    // the host arrays go out of scope below
+    e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return bail(NS_EHIP, "graph upload failed");
     // padding rows of a pack hold a constant admissible state in every
     // state buffer (they have no neighbours, so the steps keep it)
     if (s->pack) {
@@ -848,10 +879,11 @@ int create_impl(const Layout &Lt, const ns_params *p, void *stream, ns_solver **
         const int64_t first = Lt.base[r] + Lt.mgs[r]->N, count = mend(r) - first;
         if (count <= 0) continue;
         for (int b = 0; b < 3 && e == hipSuccess; ++b)
-          e = hipMemcpy2D(s->S[b] + first, N * sizeof(double), pad.data(),
-                          ns::kBlock * sizeof(double), count * sizeof(double), nc,
-                          hipMemcpyHostToDevice);
+          e = hipMemcpy2DAsync(s->S[b] + first, N * sizeof(double), pad.data(),
+                               ns::kBlock * sizeof(double), count * sizeof(double), nc,
+                               hipMemcpyHostToDevice, s->stream);
       }
+      if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
       if (e != hipSuccess) return bail(NS_EHIP, "padding upload failed");
     }
   }
@@ -859,10 +891,11 @@ int create_impl(const Layout &Lt, const ns_params *p, void *stream, ns_solver **
   for (void *z : {(void *)s->d, (void *)s->lt1, (void *)s->lt2, (void *)s->df,
                   (void *)s->lt1f, (void *)s->lt2f}) {
     if (!z) continue;
-    e = hipMemset(z, 0, (size_t)W * Np * (s->mixed ? sizeof(float) : sizeof(double)));
+    e = hipMemsetAsync(z, 0, (size_t)W * Np * (s->mixed ? sizeof(float) : sizeof(double)),
+                       s->stream);
     if (e != hipSuccess) return bail(NS_EHIP, "memset failed");
   }
-  e = hipDeviceSynchronize();
+  e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return bail(NS_EHIP, hipGetErrorString(e));
 #undef NS_ALLOC
   *out = s;

@@ -4,20 +4,26 @@
 // of SSPRK(3,3) steps with the CFL time step).  Requests wait in a FIFO queue
 // and are admitted, in order, whenever their device footprint fits in the
 // server's memory budget beside the running ones (and the number of running
-// requests is below the limit).  An admitted request gets its own solver on
-// its own HIP stream.  Its steps are enqueued in small chunks, at most
-// `depth` chunks in flight, without host synchronization: every progress
-// call tops up each running request by one chunk (round robin), so the
-// running requests advance together -- a small request is never queued
-// behind the whole run of a large one on a hardware queue -- and their
-// kernels overlap on the device.  ns_server_progress also collects finished
-// requests (copying their states to host memory and freeing their device
-// memory, which lets the next queued requests in) and admits new ones; it
-// never blocks on the device.  Each request's result depends only on its own
-// input: the kernels are deterministic and requests share no device data.
+// units is below the limit).  A unit is either one request with its own
+// solver, or -- for meshes of at most half the pack size -- a pack: the
+// consecutive queued requests with the same step count whose rows fit in
+// one pack, advanced by the same kernel launches (ns_pack_*), each with its
+// own time step.  Each unit runs on its own HIP stream.  Its steps are
+// enqueued in small chunks, at most `depth` chunks in flight, without host
+// synchronization: every progress call tops up each running unit by one
+// chunk (round robin), so the running units advance together -- a small
+// request is never queued behind the whole run of a large one on a hardware
+// queue -- and their kernels overlap on the device.  ns_server_progress also
+// collects finished units (copying their states to host memory and freeing
+// their device memory, which lets the next queued requests in) and admits
+// new ones; it never blocks on the device.  Each request's result depends
+// only on its own input: the kernels are deterministic, requests share no
+// device data, and a pack member's result is bit-identical to its own
+// solver's.
 #include <algorithm>
 #include <chrono>
 #include <deque>
+#include <future>
 #include <map>
 #include <memory>
 #include <new>
@@ -25,6 +31,7 @@
 #include <vector>
 
 #include "../../include/ns.h"
+#include "device.hpp"
 
 namespace {
 
@@ -40,11 +47,11 @@ struct Request {
   ns_mesh_desc mesh{};
   std::vector<double> u0;
   int steps = 0;
-  int enqueued = 0;  // steps enqueued so far
   int state = QUEUED;
   ns_graph *g = nullptr;
-  ns_solver *s = nullptr;
-  int64_t bytes = 0;
+  int64_t N = 0, rows = 0;  // nodes; rows in a pack (N rounded up to 256)
+  int dim = 0;
+  int64_t bytes = 0;        // footprint of its own solver
   double t_submit = 0, t_admit = 0, t_finish = 0;
   double t_sim = 0.0;
   int status = NS_OK;
@@ -52,12 +59,28 @@ struct Request {
   std::vector<double> out;
 };
 
+// One request with its own solver, or a pack of several.  The solver or
+// pack is created and given its states in a worker thread (graph set-up
+// and uploads take host time in proportion to the mesh), while the
+// progress calls keep the running units fed.
+struct Unit {
+  std::vector<Request *> mem;
+  ns_solver *s = nullptr;
+  ns_pack *k = nullptr;
+  int steps = 0, enqueued = 0;
+  int64_t bytes = 0;
+  std::future<int> ready;  // set-up in a worker thread, until collected
+  bool preparing = false;
+  std::string err;         // set-up failure
+};
+
 }  // namespace
 
 struct ns_server {
   ns_server_params prm{};
+  int device = 0;  // the creating thread's device, for the set-up threads
   std::deque<Request *> queue;
-  std::vector<Request *> running;
+  std::vector<Unit *> running;
   std::map<int64_t, std::unique_ptr<Request>> all;
   int64_t used = 0;
   int64_t next_id = 1;
@@ -67,43 +90,147 @@ struct ns_server {
 
 namespace {
 
-void release(ns_server *sv, Request *r) {
-  if (r->s) ns_solver_destroy(r->s);
+void release_graph(Request *r) {
   if (r->g) ns_graph_destroy(r->g);
-  r->s = nullptr;
   r->g = nullptr;
-  sv->used -= r->bytes;
+}
+
+void release(ns_server *sv, Unit *u) {
+  if (u->s) ns_solver_destroy(u->s);
+  if (u->k) ns_pack_destroy(u->k);
+  u->s = nullptr;
+  u->k = nullptr;
+  for (Request *r : u->mem) release_graph(r);
+  sv->used -= u->bytes;
+}
+
+const char *unit_error(const Unit *u) {
+  return u->k ? ns_pack_error(u->k) : u->s ? ns_last_error(u->s) : ns_create_error();
 }
 
 // enqueue the next chunk of steps
-int top_up(ns_server *sv, Request *r) {
-  const int k = std::min(sv->prm.chunk, r->steps - r->enqueued);
-  const int rc = ns_step_cfl_async(r->s, k);
-  if (rc == NS_OK) r->enqueued += k;
+int top_up(ns_server *sv, Unit *u) {
+  const int k = std::min(sv->prm.chunk, u->steps - u->enqueued);
+  const int rc = u->k ? ns_pack_step_cfl_async(u->k, k) : ns_step_cfl_async(u->s, k);
+  if (rc == NS_OK) u->enqueued += k;
   return rc;
 }
 
-// admit the request at the head of the queue: solver, state, first chunk
-int admit(ns_server *sv, Request *r) {
-  int rc = ns_solver_create(r->g, &sv->prm.solver, nullptr, &r->s);
-  if (rc == NS_OK) rc = ns_set_state(r->s, r->u0.data(), 0);
-  if (rc == NS_OK) rc = top_up(sv, r);
-  if (rc != NS_OK) {
-    r->error = r->s ? ns_last_error(r->s) : ns_create_error();
-    return rc;
-  }
-  r->t_admit = now_s();
-  r->state = RUNNING;
-  std::vector<double>().swap(r->u0);
-  return NS_OK;
+int inflight(Unit *u, int *n) {
+  return u->k ? ns_pack_inflight(u->k, n) : ns_inflight(u->s, n);
 }
 
-void finish(ns_server *sv, Request *r, int status) {
+// Worker thread: create the unit's solver or pack and set the states.
+int prepare(const ns_params prm, int device, Unit *u) {
+  ns::use_device(device);
+  int rc;
+  if (u->mem.size() == 1) {
+    Request *r = u->mem[0];
+    rc = ns_solver_create(r->g, &prm, nullptr, &u->s);
+    if (rc == NS_OK) rc = ns_set_state(u->s, r->u0.data(), 0);
+  } else {
+    std::vector<const ns_graph *> gs;
+    for (Request *r : u->mem) gs.push_back(r->g);
+    rc = ns_pack_create(gs.data(), (int)gs.size(), &prm, nullptr, &u->k);
+    for (size_t m = 0; rc == NS_OK && m < u->mem.size(); ++m)
+      rc = ns_pack_set_state(u->k, (int)m, u->mem[m]->u0.data());
+  }
+  if (rc != NS_OK) u->err = unit_error(u);
+  return rc;
+}
+
+// Main thread, once the set-up is done: enqueue the first chunk.
+int start(ns_server *sv, Unit *u) {
+  u->preparing = false;
+  int rc = u->ready.get();
+  if (rc == NS_OK) {
+    rc = top_up(sv, u);
+    if (rc != NS_OK) u->err = unit_error(u);
+  }
+  for (Request *r : u->mem) {
+    if (rc != NS_OK) r->error = u->err;
+    std::vector<double>().swap(r->u0);
+  }
+  return rc;
+}
+
+void finish_request(ns_server *sv, Request *r, int status) {
   r->status = status;
   r->t_finish = now_s();
   r->state = FINISHED;
-  release(sv, r);
   sv->st.finished += 1;
+}
+
+// all steps done (rc NS_OK) or the unit failed (rc): collect its requests
+void finish(ns_server *sv, Unit *u, int rc) {
+  const size_t n = u->mem.size();
+  std::vector<int> st(n, rc);
+  std::vector<double> t(n, 0.0);
+  if (rc == NS_OK) {
+    if (u->k) {
+      rc = ns_pack_finish(u->k, st.data(), t.data());
+      if (rc != NS_OK) std::fill(st.begin(), st.end(), rc);
+    } else {
+      st[0] = ns_async_finish(u->s, &t[0]);
+    }
+  }
+  for (size_t m = 0; m < n; ++m) {
+    Request *r = u->mem[m];
+    r->t_sim = t[m];
+    int s = st[m];
+    if (s == NS_OK || s == NS_ECFL || s == NS_EBOUNDS) {
+      r->out.resize((size_t)(r->dim + 2) * r->N);
+      const int rg = u->k ? ns_pack_get_state(u->k, (int)m, r->out.data())
+                          : ns_get_state(u->s, r->out.data(), 0);
+      if (s == NS_OK) s = rg;
+    }
+    if (s != NS_OK && r->error.empty()) r->error = u->err.empty() ? unit_error(u) : u->err;
+    finish_request(sv, r, s);
+  }
+  release(sv, u);
+  delete u;
+}
+
+// The unit to admit next: the queue head alone, or the head and the
+// consecutive queued requests with its step count that fit in a pack (and
+// in the memory left).  Empty if the head does not fit.
+Unit *next_unit(ns_server *sv) {
+  Request *h = sv->queue.front();
+  const int64_t free_bytes = sv->prm.mem_bytes - sv->used;
+  const int64_t cap = sv->prm.pack_nodes;
+  std::vector<Request *> mem{h};
+  if (cap > 0 && h->rows * 2 <= cap) {
+    int64_t rows = h->rows;
+    for (size_t q = 1; q < sv->queue.size() && (int)mem.size() < sv->prm.pack_max; ++q) {
+      Request *r = sv->queue[q];
+      if (r->steps != h->steps || r->dim != h->dim || r->rows * 2 > cap ||
+          rows + r->rows > cap)
+        break;
+      mem.push_back(r);
+      rows += r->rows;
+    }
+  }
+  // shrink to the memory left
+  while (!mem.empty()) {
+    int64_t b = 0;
+    if (mem.size() == 1) {
+      b = mem[0]->bytes;
+    } else {
+      std::vector<const ns_graph *> gs;
+      for (Request *r : mem) gs.push_back(r->g);
+      if (ns_pack_footprint(gs.data(), (int)gs.size(), &sv->prm.solver, &b) != NS_OK)
+        b = INT64_MAX;
+    }
+    if (b <= free_bytes) {
+      Unit *u = new Unit;
+      u->mem = mem;
+      u->steps = h->steps;
+      u->bytes = b;
+      return u;
+    }
+    mem.pop_back();
+  }
+  return nullptr;
 }
 
 }  // namespace
@@ -112,25 +239,24 @@ extern "C" {
 
 int ns_server_create(const ns_server_params *p, ns_server **out) {
   if (!p || !out || p->mem_bytes <= 0 || p->max_running < 1 || p->chunk < 1 ||
-      p->depth < 1)
+      p->depth < 1 || p->pack_nodes < 0 || (p->pack_nodes > 0 && p->pack_max < 2))
     return NS_EINVAL;
   ns_server *sv = new (std::nothrow) ns_server;
   if (!sv) return NS_ENOMEM;
   sv->prm = *p;
+  sv->device = ns::current_device();
   *out = sv;
   return NS_OK;
 }
 
 void ns_server_destroy(ns_server *sv) {
   if (!sv) return;
-  for (auto &kv : sv->all) {
-    Request *r = kv.second.get();
-    if (r->state == RUNNING) {
-      double t;
-      (void)ns_async_finish(r->s, &t);
-    }
-    release(sv, r);
+  for (Unit *u : sv->running) {
+    if (u->preparing) u->ready.wait();
+    release(sv, u);  // waits for the unit's stream
+    delete u;
   }
+  for (auto &kv : sv->all) release_graph(kv.second.get());
   delete sv;
 }
 
@@ -158,6 +284,9 @@ int ns_server_submit(ns_server *sv, const ns_mesh_desc *mesh, const double *U0,
     return NS_ENOMEM;
   }
   r->u0.assign(U0, U0 + (size_t)(dim + 2) * N);
+  r->N = N;
+  r->dim = dim;
+  r->rows = (N + 255) / 256 * 256;
   r->steps = steps;
   r->id = sv->next_id++;
   r->t_submit = now_s();
@@ -170,54 +299,68 @@ int ns_server_submit(ns_server *sv, const ns_mesh_desc *mesh, const double *U0,
 
 int ns_server_progress(ns_server *sv, int *n_finished) {
   if (!sv) return NS_EINVAL;
-  int nf = 0;
-  // top up running requests by one chunk each; collect finished ones
+  const int64_t before = sv->st.finished;
+  // top up running units by one chunk each; collect finished ones
   for (size_t k = 0; k < sv->running.size();) {
-    Request *r = sv->running[k];
-    int inflight = 0;
-    int rc = ns_inflight(r->s, &inflight);
-    if (rc == NS_OK && r->enqueued < r->steps) {
-      if (inflight < sv->prm.depth) rc = top_up(sv, r);
+    Unit *u = sv->running[k];
+    int n = 0;
+    int rc = NS_OK;
+    if (u->preparing) {
+      if (u->ready.wait_for(std::chrono::seconds(0)) != std::future_status::ready) {
+        ++k;
+        continue;
+      }
+      const double t0 = now_s();
+      rc = start(sv, u);
+      sv->st.host_admit_s += now_s() - t0;
       if (rc == NS_OK) {
         ++k;
         continue;
       }
     }
-    if (rc == NS_OK && inflight > 0) {
+    if (rc == NS_OK) rc = inflight(u, &n);
+    if (rc == NS_OK && u->enqueued < u->steps) {
+      if (n < sv->prm.depth) {
+        const double t0 = now_s();
+        rc = top_up(sv, u);
+        sv->st.host_topup_s += now_s() - t0;
+      }
+      if (rc == NS_OK) {
+        ++k;
+        continue;
+      }
+    }
+    if (rc == NS_OK && n > 0) {
       ++k;
       continue;
     }
-    if (rc == NS_OK) rc = ns_async_finish(r->s, &r->t_sim);
-    if (rc == NS_OK || rc == NS_ECFL || rc == NS_EBOUNDS) {
-      int64_t N = 0;
-      int dim = 0;
-      ns_graph_info(r->g, &N, nullptr, &dim, nullptr);
-      r->out.resize((size_t)(dim + 2) * N);
-      const int rg = ns_get_state(r->s, r->out.data(), 0);
-      if (rc == NS_OK) rc = rg;
-    }
-    if (rc != NS_OK) r->error = ns_last_error(r->s);
-    finish(sv, r, rc);
     sv->running.erase(sv->running.begin() + k);
-    ++nf;
+    const double t0 = now_s();
+    finish(sv, u, rc);
+    sv->st.host_finish_s += now_s() - t0;
   }
   // admit queued requests, in order, while they fit
   while (!sv->queue.empty() && (int)sv->running.size() < sv->prm.max_running) {
-    Request *r = sv->queue.front();
-    if (sv->used + r->bytes > sv->prm.mem_bytes) break;
-    sv->queue.pop_front();
-    sv->used += r->bytes;
-    const int rc = admit(sv, r);
-    if (rc != NS_OK) {
-      finish(sv, r, rc);
-      ++nf;
-      continue;
+    Unit *u = next_unit(sv);
+    if (!u) break;
+    for (size_t m = 0; m < u->mem.size(); ++m) sv->queue.pop_front();
+    sv->used += u->bytes;
+    sv->st.units += 1;
+    const double t0 = now_s();
+    for (Request *r : u->mem) {
+      r->t_admit = t0;
+      r->state = RUNNING;
     }
-    sv->running.push_back(r);
-    sv->st.peak_running = std::max<int64_t>(sv->st.peak_running, (int64_t)sv->running.size());
+    u->ready = std::async(std::launch::async, prepare, sv->prm.solver, sv->device, u);
+    u->preparing = true;
+    sv->st.host_admit_s += now_s() - t0;
+    sv->running.push_back(u);
+    int64_t nreq = 0;
+    for (Unit *v : sv->running) nreq += (int64_t)v->mem.size();
+    sv->st.peak_running = std::max(sv->st.peak_running, nreq);
     sv->st.peak_bytes = std::max(sv->st.peak_bytes, sv->used);
   }
-  if (n_finished) *n_finished = nf;
+  if (n_finished) *n_finished = (int)(sv->st.finished - before);
   return NS_OK;
 }
 
@@ -255,7 +398,8 @@ int ns_server_stats_get(const ns_server *sv, ns_server_stats *out) {
   if (!sv || !out) return NS_EINVAL;
   *out = sv->st;
   out->queued = (int64_t)sv->queue.size();
-  out->running = (int64_t)sv->running.size();
+  out->running = 0;
+  for (const Unit *u : sv->running) out->running += (int64_t)u->mem.size();
   out->bytes_in_use = sv->used;
   return NS_OK;
 }

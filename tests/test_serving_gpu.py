@@ -73,8 +73,10 @@ def test_graph_replays_equal_eager_steps(dim, precision):
         assert np.array_equal(a.get_state(), b.get_state())
 
 
-def run_server(reqs, mem_bytes, max_running, precision=abi.PREC_FP64, stagger=0.0):
-    sv = abi.Server(mem_bytes, max_running=max_running, precision=precision)
+def run_server(reqs, mem_bytes, max_running, precision=abi.PREC_FP64, stagger=0.0,
+               pack_nodes=0, pack_max=64):
+    sv = abi.Server(mem_bytes, max_running=max_running, precision=precision,
+                    pack_nodes=pack_nodes, pack_max=pack_max)
     ids = []
     for mesh, U, steps in reqs:
         ids.append(sv.submit(mesh, U, steps))
@@ -128,6 +130,41 @@ def test_alone_and_in_the_mix_are_identical(precision):
     for _ in range(steps):
         s.step_cfl()
     assert np.array_equal(s.get_state(), together[1][0])
+
+
+@pytest.mark.parametrize("precision", [abi.PREC_FP64, abi.PREC_MIXED])
+def test_packed_requests_equal_alone(precision):
+    """With packs (up to 65536 rows, 4 members): the six requests run as two
+    packs of consecutive requests (4 + 2 members); every result and its
+    simulated time are bit-identical to the request run alone."""
+    reqs = mix()
+    alone = [run_server([r], 1 << 34, 1, precision)[0][0] for r in reqs]
+    packed, st = run_server(reqs, 1 << 34, 6, precision, pack_nodes=65536, pack_max=4)
+    say("peak running", st.peak_running)
+    assert st.finished == len(reqs)
+    for (ua, ta), (ub, tb) in zip(alone, packed):
+        assert np.array_equal(ua, ub)
+        assert ta == tb
+    # requests with another step count are not packed with them
+    reqs2 = reqs[:3] + [(reqs[3][0], reqs[3][1], 7)] + reqs[4:]
+    packed2, _ = run_server(reqs2, 1 << 34, 6, precision, pack_nodes=65536, pack_max=4)
+    solo3, _ = run_server([reqs2[3]], 1 << 34, 1, precision)
+    assert np.array_equal(packed2[3][0], solo3[0][0])
+    for k in (0, 1, 2, 4, 5):
+        assert np.array_equal(packed2[k][0], alone[k][0])
+
+
+def test_pack_admission_by_memory():
+    """A pack shrinks to the members whose pack footprint fits the memory
+    left; every request still finishes."""
+    reqs = [(*W.four_quadrant_state(60, seed=k), 6) for k in range(6)]
+    g = [abi.Graph(m) for m, _, _ in reqs]
+    budget = abi.pack_footprint(g[:3])
+    res, st = run_server(reqs, budget, 8, pack_nodes=1 << 20, pack_max=64)
+    say("peak running", st.peak_running, "peak bytes", st.peak_bytes, "budget", budget)
+    assert st.finished == 6
+    assert st.peak_bytes <= budget
+    assert st.peak_running == 3
 
 
 def test_admission_by_memory():
