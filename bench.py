@@ -245,7 +245,8 @@ def main():
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--rate", type=float, default=20.0)
     ap.add_argument("--serve-steps", type=int, default=200)
-    ap.add_argument("--max-running", type=int, default=64)
+    ap.add_argument("--max-running", type=int, default=8,
+                    help="serving: running units (solvers or packs) at most")
     ap.add_argument("--serve-mem-gb", type=float, default=160.0)
     ap.add_argument("--serve-chunk", type=int, default=2,
                     help="steps per enqueued chunk of a running request")
