@@ -109,29 +109,38 @@ def workload(dim: int, n: int, seed: int):
     return W.shock_tube_state(n, seed=seed)
 
 
-def cpu_baseline(dim: int, n_sample: int, seed: int, ns: bool = False):
-    """The oracle, as it stands, on one SSPRK(3,3) step (one Strang step with
-    `ns`) of the same workload at n_sample nodes per direction (graph
-    assembly not timed)."""
+def cpu_baseline(dim: int, n_sample: int, seed: int, ns: bool = False,
+                 min_s: float = 10.0, max_steps: int = 16):
+    """The oracle, as it stands, stepping the same workload at n_sample
+    nodes per direction: SSPRK(3,3) steps (Strang steps with `ns`), each with
+    its CFL time step, until at least min_s seconds have passed (at most
+    max_steps steps; graph assembly not timed)."""
     from oracle import oracle as O
     O.build(force=False)
     mesh, U = workload(dim, n_sample, seed)
     og = O.Graph(dim, mesh.n, mesh.lo, mesh.hi, mesh.periodic, export=False)
     prm = O.params(cfl=0.5)
+    visc = O.visc(mu=1e-4, lam=0.0, kappa=1.4e-4, cv=2.5, cg_rtol=1e-10)
     U = og.slip_bc(U)
+    steps = 0
     t0 = time.perf_counter()
-    tau = og.compute_dt(prm, U)
-    if ns:
-        og.strang_step(prm, O.visc(mu=1e-4, lam=0.0, kappa=1.4e-4, cv=2.5,
-                                   cg_rtol=1e-10), U, tau)
-    else:
-        og.ssprk3_step(prm, U, tau)
-    dt = time.perf_counter() - t0
+    while True:
+        tau = og.compute_dt(prm, U)
+        if ns:
+            U, st, _ = og.strang_step(prm, visc, U, tau)
+        else:
+            U, st = og.ssprk3_step(prm, U, tau)
+        if st != 0:
+            raise RuntimeError(f"oracle step failed with status {st}")
+        steps += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_s or steps >= max_steps:
+            break
     stages = 6 if ns else 3
-    what = ("one Strang step (time step + 6 stages + parabolic step; the "
-            "oracle's parabolic part is serial)" if ns else
-            "one SSPRK3 step (time step + 3 stages)")
-    return {"value": og.N * stages / dt, "unit": "DoF-updates/s per SSP-RK stage",
+    what = (f"{steps} Strang steps (time step + 6 stages + parabolic step each; "
+            f"the oracle's parabolic part is serial)" if ns else
+            f"{steps} SSPRK3 steps (time step + 3 stages each)")
+    return {"value": og.N * stages * steps / dt, "unit": "DoF-updates/s per SSP-RK stage",
             "cores": O.num_threads(), "kind": "oracle",
             "sample": f"{what} of the "
                       f"{'four-quadrant' if dim == 2 else 'Mach-3 shock-tube'} "
