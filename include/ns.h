@@ -334,8 +334,11 @@ int ns_server_create(const ns_server_params *p, ns_server **out);
 /* Waits for running requests, frees everything. */
 void ns_server_destroy(ns_server *sv);
 /* Queues a request; U0 (host, nc*N doubles for the mesh's N) is copied.
- * NS_EINVAL for a bad mesh, NS_ENOMEM if the request alone exceeds
- * mem_bytes.  *id identifies the request. */
+ * NS_EINVAL for a bad mesh, NS_ENOTADMISSIBLE for a state with rho <= 0,
+ * internal energy <= 0 or a non-finite value, NS_ENOMEM if the request
+ * alone exceeds mem_bytes.  *id identifies the request.  A unit whose
+ * set-up fails (device memory, a HIP error) finishes all its requests with
+ * that status. */
 int ns_server_submit(ns_server *sv, const ns_mesh_desc *mesh, const double *U0,
                      int steps, int64_t *id);
 /* Collects finished requests and admits queued ones; *n_finished (may be

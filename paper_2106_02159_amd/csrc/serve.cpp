@@ -22,6 +22,7 @@
 // solver's.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <deque>
 #include <future>
 #include <map>
@@ -282,6 +283,22 @@ int ns_server_submit(ns_server *sv, const ns_mesh_desc *mesh, const double *U0,
     ns_graph_destroy(r->g);
     sv->err = "the request needs more device memory than the server's budget";
     return NS_ENOMEM;
+  }
+  // an inadmissible state is refused here, so that it never shares a pack
+  for (int64_t i = 0; i < N; ++i) {
+    const double rho = U0[i], E = U0[(dim + 1) * N + i];
+    double m2 = 0.0;
+    bool ok = std::isfinite(rho) && std::isfinite(E);
+    for (int d = 0; d < dim; ++d) {
+      const double mk = U0[(1 + d) * N + i];
+      ok = ok && std::isfinite(mk);
+      m2 += mk * mk;
+    }
+    if (!ok || !(rho > 0.0) || !(E - 0.5 * m2 / rho > 0.0)) {
+      ns_graph_destroy(r->g);
+      sv->err = "initial state not admissible at node " + std::to_string(i);
+      return NS_ENOTADMISSIBLE;
+    }
   }
   r->u0.assign(U0, U0 + (size_t)(dim + 2) * N);
   r->N = N;

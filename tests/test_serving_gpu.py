@@ -167,6 +167,22 @@ def test_pack_admission_by_memory():
     assert st.peak_running == 3
 
 
+def test_inadmissible_request_is_refused_at_submission():
+    (m, U), (m2, U2) = W.four_quadrant_state(30, seed=1), W.four_quadrant_state(31, seed=2)
+    sv = abi.Server(1 << 34, pack_nodes=1 << 20)
+    bad = U.copy()
+    bad[-1, 17] = 0.999 * 0.5 * (bad[1, 17] ** 2 + bad[2, 17] ** 2) / bad[0, 17]  # eps < 0
+    with pytest.raises(abi.NSError) as ex:
+        sv.submit(m, bad, 3)
+    assert ex.value.code == abi.NS_ENOTADMISSIBLE
+    rid = sv.submit(m2, U2, 3)
+    while sv.request(rid).state != abi.REQ_FINISHED:
+        sv.progress()
+    out, st = sv.result(rid)
+    assert st == abi.NS_OK
+    sv.close()
+
+
 def test_admission_by_memory():
     reqs = [(*W.four_quadrant_state(90, seed=k), 10) for k in range(5)]
     fp = abi.footprint(abi.Graph(reqs[0][0]))
