@@ -76,12 +76,14 @@ def stage_algorithmic_bytes(dim: int, mixed: bool = False) -> float:
 
 
 def source_sha() -> str:
-    """sha256 (first 16 hex) of the kernel sources: csrc/*.hip, *.hpp, *.cpp."""
+    """sha256 (first 16 hex) of the device code and its launch code:
+    csrc/*.hip and *.hpp (the host-only *.cpp files -- graph and element
+    tables, the server -- do not change what a kernel moves)."""
     import glob
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2106_02159_amd", "csrc")
-    for ext in ("hip", "hpp", "cpp"):
+    for ext in ("hip", "hpp"):
         for p in sorted(glob.glob(os.path.join(csrc, f"*.{ext}"))):
             h.update(open(p, "rb").read())
     return h.hexdigest()[:16]
