@@ -102,3 +102,35 @@ def test_strerror():
     L = abi.lib()
     for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert L.ns_strerror(code)
+
+
+def test_too_large_meshes_rejected_before_device_work():
+    """Edge indices are 32-bit: W * (N rounded up to 64) must not exceed
+    2^32 - 1.  21845^2 nodes is the largest square 2D mesh that fits;
+    21846^2 is refused, and so is a pack whose members together exceed it."""
+    fits = abi.Graph(W.Mesh(2, (21845, 21845), (0, 0), (1, 1), (False, False)))
+    assert 9 * ((fits.N + 63) // 64 * 64) <= 2 ** 32 - 1
+    big = abi.Graph(W.Mesh(2, (21846, 21846), (0, 0), (1, 1), (False, False)))
+    with pytest.raises(abi.NSError) as ei:
+        abi.Solver(big)
+    assert ei.value.code == abi.NS_EINVAL
+    half = abi.Graph(W.Mesh(2, (16000, 16000), (0, 0), (1, 1), (False, False)))
+    with pytest.raises(abi.NSError) as ei:
+        abi.Pack([half, half])
+    assert ei.value.code == abi.NS_EINVAL
+    # the footprint of the largest mesh is still reported (host arithmetic)
+    assert abi.footprint(fits) > 9 * fits.N * (4 + 1 + 3 * 8)
+
+
+def test_pack_rejected_before_device_work():
+    g2 = abi.Graph(W.four_quadrant_mesh(8))
+    g3 = abi.Graph(W.shock_tube_mesh(5))
+    for graphs in ([g2, g3], []):
+        with pytest.raises(abi.NSError) as ei:
+            abi.Pack(graphs)
+        assert ei.value.code == abi.NS_EINVAL
+    with pytest.raises(abi.NSError):
+        abi.pack_footprint([g2, g3])
+    # a pack's footprint covers its members' rows rounded up to 256
+    assert abi.pack_footprint([g2]) >= abi.footprint(g2)
+    assert abi.pack_footprint([g2, g2]) > abi.pack_footprint([g2])

@@ -183,6 +183,17 @@ def test_inadmissible_request_is_refused_at_submission():
     sv.close()
 
 
+@pytest.mark.parametrize("pack_nodes", [0, 1 << 20])
+def test_zero_steps_returns_the_projected_state(pack_nodes):
+    reqs = [(*W.four_quadrant_state(40, seed=3), 0), (*W.four_quadrant_state(41, seed=4), 0)]
+    res, st = run_server(reqs, 1 << 34, 4, pack_nodes=pack_nodes)
+    for (mesh, U, _), (out, t) in zip(reqs, res):
+        s = abi.Solver(abi.Graph(mesh))
+        s.set_state(U)
+        assert t == 0.0
+        assert np.array_equal(out, s.get_state())
+
+
 def test_admission_by_memory():
     reqs = [(*W.four_quadrant_state(90, seed=k), 10) for k in range(5)]
     fp = abi.footprint(abi.Graph(reqs[0][0]))
