@@ -135,6 +135,7 @@ int orc_graph_build(int dim, const long *n, const double *lo, const double *hi,
   g->bpair = (double *)calloc((size_t)dim * nnz, sizeof(double));
   g->mi = (double *)calloc(N, sizeof(double));
   g->bnd = (double *)calloc((size_t)dim * N, sizeof(double));
+  g->bface = (double *)calloc((size_t)6 * N, sizeof(double));
   g->on_wall = (int *)calloc(N, sizeof(int));
 
   /* --- cell integrals by tensor Gauss quadrature (2 points / direction) --- */
@@ -201,6 +202,7 @@ int orc_graph_build(int dim, const long *n, const double *lo, const double *hi,
               }
               for (int a = 0; a < nloc; ++a) {
                 g->bnd[(size_t)fdir * N + gl[a]] += wf * phi[a] * nrm;
+                g->bface[(size_t)(2 * fdir + side) * N + gl[a]] += wf * phi[a];
                 for (int b = 0; b < nloc; ++b) {
                   long e = find_entry(g, gl[a], gl[b]);
                   g->bpair[(size_t)fdir * nnz + e] += wf * (phi[a] * phi[b]) * nrm;
@@ -227,7 +229,7 @@ int orc_graph_build(int dim, const long *n, const double *lo, const double *hi,
 void orc_graph_free(orc_graph *g) {
   if (!g) return;
   free(g->row_ptr); free(g->col); free(g->tr); free(g->mij); free(g->cij);
-  free(g->bpair); free(g->mi); free(g->bnd); free(g->on_wall); free(g);
+  free(g->bpair); free(g->mi); free(g->bnd); free(g->bface); free(g->on_wall); free(g);
 }
 
 long orc_graph_N(const orc_graph *g) { return g->N; }

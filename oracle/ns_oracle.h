@@ -35,6 +35,9 @@ typedef struct orc_graph {
   double *bpair;        /* dim*nnz: int_{dOmega} phi_i phi_j n_k */
   double *mi;           /* N: lumped mass int phi_i */
   double *bnd;          /* dim*N: int_{dOmega} phi_i n_k */
+  double *bface;        /* 6*N: int_{face f} phi_i over face f = 2*dir + side
+                           (side 0: low end, outward normal -e_dir; side 1:
+                           high end, +e_dir); 0 for periodic directions */
   int *on_wall;         /* N: 1 if the node lies on a non-periodic wall */
 } orc_graph;
 
@@ -99,6 +102,48 @@ void orc_slip_bc(const orc_graph *g, double *U);
  * Returns 0, or 1 if any stage violated its CFL limit. */
 int orc_ssprk3_step(const orc_graph *g, const orc_params *p, const double *U,
                     double tau, double *Uout);
+/* ---- boundary post-processing with non-reflecting faces (ns_oracle_bc.c)
+ * Faces f = 2*dir + side of non-periodic directions are slip or
+ * non-reflecting (Sec. 4.3.2).  A node lies in the slip set if some slip face
+ * touches it, in the non-reflecting set if some non-reflecting face does;
+ * its normal in each set is int phi_i n over that set's faces, normalised
+ * (eq. def_ns_nio).  After a stage the non-reflecting post-processing runs
+ * first, then the slip projection (a node in both sets keeps no normal
+ * momentum through its slip faces).  A node on several non-reflecting faces
+ * takes the far-field state of the lowest-numbered one. */
+enum { ORC_BC_SLIP = 0, ORC_BC_NONREFLECTING = 1 };
+enum { ORC_NR_CHARACTERISTIC = 0, ORC_NR_GODUNOV = 1 };
+typedef struct orc_boundary {
+  int kind[6];          /* per face: ORC_BC_*                              */
+  int method;           /* ORC_NR_*                                        */
+  double state[6][5];   /* far-field state of each non-reflecting face:    */
+                        /* rho, m (dim components), E                      */
+} orc_boundary;
+/* Exact Riemann problem of the gamma-law gas in 1D (Sec. 4.3.2 Godunov
+ * variant): star pressure by bisection on the monotone pressure function,
+ * star velocity, and the solution at x/t = xi.  side_out is -1 if xi lies
+ * left of the contact, +1 if right.  Returns 0, or 1 if the data generate
+ * vacuum (no positive star pressure). */
+int orc_riemann_star(double gamma, double rl, double ul, double pl, double rr,
+                     double ur, double pr, double *pstar, double *ustar);
+int orc_riemann_sample(double gamma, double rl, double ul, double pl, double rr,
+                       double ur, double pr, double xi, double *rho, double *u,
+                       double *p, int *side_out);
+/* Post-processed state of one non-reflecting node: U, the far-field state UD
+ * and the unit outward normal n (eq. Godunov_bc, or eqs. Supersonic_inflow,
+ * Subsonic_inflow, Subsonic_outflow, Supersonic_outflow).  Returns 0, or 1
+ * if the result is not admissible (Godunov with vacuum). */
+int orc_nr_state(double gamma, int dim, int method, const double *U, const double *UD,
+                 const double *n, double *UP);
+/* Post-processing of a stage result in place; returns 0 or 1 (as above). */
+int orc_boundary_bc(const orc_graph *g, const orc_params *p, const orc_boundary *b,
+                    double *U);
+/* One SSPRK(3,3) step with this post-processing after every stage; returns
+ * bit 0 as orc_ssprk3_step, bit 1 if a post-processed state was not
+ * admissible. */
+int orc_ssprk3_step_bc(const orc_graph *g, const orc_params *p, const orc_boundary *b,
+                       const double *U, double tau, double *Uout);
+
 /* Unlimited high-order update computed directly from M_L (U^H - U) =
  * tau (I + B) F^H, used to check the limiter's l = 1 special case. */
 int orc_high_order_direct(const orc_graph *g, const orc_params *p,

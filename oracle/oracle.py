@@ -17,7 +17,8 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(HERE, "ns_oracle.c"), os.path.join(HERE, "ns_oracle_parabolic.c")]
+SRCS = [os.path.join(HERE, "ns_oracle.c"), os.path.join(HERE, "ns_oracle_parabolic.c"),
+        os.path.join(HERE, "ns_oracle_bc.c")]
 LIB = os.path.join(HERE, "libns_oracle.so")
 
 IND_ENTROPY, IND_ONE, IND_ZERO = 0, 1, 2
@@ -49,6 +50,28 @@ class _Visc(C.Structure):
 class ParInfo(C.Structure):
     _fields_ = [("it_v", C.c_int), ("it_e", C.c_int), ("it_l", C.c_int),
                 ("fct", C.c_int), ("min_eH", C.c_double), ("min_e", C.c_double)]
+
+
+class _Boundary(C.Structure):
+    _fields_ = [("kind", C.c_int * 6), ("method", C.c_int),
+                ("state", (C.c_double * 5) * 6)]
+
+
+BC_SLIP, BC_NONREFLECTING = 0, 1
+NR_CHARACTERISTIC, NR_GODUNOV = 0, 1
+
+
+def boundary(kind, method=NR_CHARACTERISTIC, state=None) -> _Boundary:
+    """Faces f = 2*dir + side (low, high end): kind[f] in BC_*; state[f] the
+    far-field conserved state (rho, m, E) of a non-reflecting face."""
+    b = _Boundary()
+    for f in range(6):
+        b.kind[f] = int(kind[f]) if f < len(kind) else BC_SLIP
+        if state is not None and f < len(state) and state[f] is not None:
+            for c, v in enumerate(state[f]):
+                b.state[f][c] = float(v)
+    b.method = int(method)
+    return b
 
 
 class _Debug(C.Structure):
@@ -100,6 +123,14 @@ def lib():
                                          C.POINTER(ParInfo)]
         L.orc_strang_step.argtypes = [C.c_void_p, C.POINTER(_Params), vpp, dp,
                                       C.c_double, dp, C.POINTER(ParInfo)]
+        L.orc_riemann_star.argtypes = [C.c_double] * 7 + [dp, dp]
+        L.orc_riemann_sample.argtypes = [C.c_double] * 8 + [dp, dp, dp,
+                                                            C.POINTER(C.c_int)]
+        L.orc_nr_state.argtypes = [C.c_double, C.c_int, C.c_int, dp, dp, dp, dp]
+        L.orc_boundary_bc.argtypes = [C.c_void_p, C.POINTER(_Params),
+                                      C.POINTER(_Boundary), dp]
+        L.orc_ssprk3_step_bc.argtypes = [C.c_void_p, C.POINTER(_Params),
+                                         C.POINTER(_Boundary), dp, C.c_double, dp]
         _lib = L
     return _lib
 
@@ -141,6 +172,34 @@ def line_search(gamma, u, P, rho_min, rho_max, phi_min) -> float:
     P = np.ascontiguousarray(P, np.float64)
     return lib().orc_line_search(gamma, len(u) - 2, _dp(u), _dp(P), rho_min,
                                  rho_max, phi_min)
+
+
+def riemann_star(gamma, left, right):
+    """(p*, u*) of the 1D Riemann problem with primitive data (rho, u, p)
+    left and right, or None for vacuum."""
+    ps, us = C.c_double(), C.c_double()
+    rc = lib().orc_riemann_star(gamma, *map(float, left), *map(float, right),
+                                C.byref(ps), C.byref(us))
+    return None if rc else (ps.value, us.value)
+
+
+def riemann_sample(gamma, left, right, xi=0.0):
+    """(rho, u, p, side) of the Riemann solution at x/t = xi (side -1 / +1:
+    left / right of the contact), or None for vacuum."""
+    r, u, p, sd = C.c_double(), C.c_double(), C.c_double(), C.c_int()
+    rc = lib().orc_riemann_sample(gamma, *map(float, left), *map(float, right), float(xi),
+                                  C.byref(r), C.byref(u), C.byref(p), C.byref(sd))
+    return None if rc else (r.value, u.value, p.value, sd.value)
+
+
+def nr_state(gamma, method, U, UD, n):
+    """(post-processed state, admissible) of one non-reflecting node."""
+    U = np.ascontiguousarray(U, np.float64)
+    UD = np.ascontiguousarray(UD, np.float64)
+    n = np.ascontiguousarray(n, np.float64)
+    out = np.empty_like(U)
+    rc = lib().orc_nr_state(gamma, len(n), int(method), _dp(U), _dp(UD), _dp(n), _dp(out))
+    return out, rc == 0
 
 
 def pressure(gamma, u) -> float:
@@ -224,11 +283,24 @@ class Graph:
         lib().orc_slip_bc(self.h, _dp(U))
         return U
 
-    def ssprk3_step(self, prm, U, tau):
+    def ssprk3_step(self, prm, U, tau, bnd=None):
+        """One SSPRK(3,3) step; with `bnd` (oracle.boundary) the
+        slip / non-reflecting post-processing after every stage, and the
+        status has bit 1 set if a post-processed state was inadmissible."""
         U = np.ascontiguousarray(U, np.float64)
         out = np.empty_like(U)
-        st = lib().orc_ssprk3_step(self.h, C.byref(prm), _dp(U), tau, _dp(out))
+        if bnd is None:
+            st = lib().orc_ssprk3_step(self.h, C.byref(prm), _dp(U), tau, _dp(out))
+        else:
+            st = lib().orc_ssprk3_step_bc(self.h, C.byref(prm), C.byref(bnd), _dp(U), tau,
+                                          _dp(out))
         return out, st
+
+    def boundary_bc(self, prm, bnd, U):
+        """(post-processed copy of U, status) with oracle.boundary `bnd`."""
+        U = np.array(U, np.float64, order="C", copy=True)
+        st = lib().orc_boundary_bc(self.h, C.byref(prm), C.byref(bnd), _dp(U))
+        return U, st
 
     def high_order_direct(self, prm, U, tau):
         U = np.ascontiguousarray(U, np.float64)

@@ -1,0 +1,256 @@
+"""Pins of the oracle's boundary post-processing with non-reflecting faces
+(Sec. 4.3.2): the exact Riemann solver against published exact solutions
+and the jump relations it must satisfy; the characteristic-variable cases
+against the invariants that define them (eqs. Supersonic_inflow,
+Subsonic_inflow, Subsonic_outflow, Supersonic_outflow); admissibility of
+the post-processed states (Lemma on non-reflecting conditions); and at
+step level, uniform far-field flow kept to round-off and the all-slip case
+equal to the slip post-processing."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2106_02159_amd import workloads as W
+
+pytestmark = pytest.mark.filterwarnings("ignore")
+G = 1.4
+
+# Exact star states of the five one-dimensional test problems of
+# E. F. Toro, Riemann Solvers and Numerical Methods for Fluid Dynamics
+# (Springer, 3rd ed. 2009), Sec. 4.3.3 (gamma = 1.4): left (rho, u, p),
+# right (rho, u, p), p*, u*, rho*_L, rho*_R, as printed to 5-6 digits.
+TORO = [
+    ((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 0.30313, 0.92745, 0.42632, 0.26557),
+    ((1.0, -2.0, 0.4), (1.0, 2.0, 0.4), 0.00189, 0.00000, 0.02185, 0.02185),
+    ((1.0, 0.0, 1000.0), (1.0, 0.0, 0.01), 460.894, 19.5975, 0.57506, 5.99924),
+    ((1.0, 0.0, 0.01), (1.0, 0.0, 100.0), 46.0950, -6.19633, 5.99242, 0.57511),
+    ((5.99924, 19.5975, 460.894), (5.99242, -6.19633, 46.0950), 1691.64, 8.68975,
+     14.2823, 31.0426),
+]
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_riemann_matches_published_exact_solutions(case):
+    left, right, ps, us, rl, rr = TORO[case]
+    p, u = O.riemann_star(G, left, right)
+    assert p == pytest.approx(ps, rel=5e-5, abs=1e-5)
+    assert u == pytest.approx(us, rel=5e-5, abs=1e-5)
+    # star densities: just left and just right of the contact
+    rho_l = O.riemann_sample(G, left, right, u - 1e-9 * max(1.0, abs(u)))[0]
+    rho_r = O.riemann_sample(G, left, right, u + 1e-9 * max(1.0, abs(u)))[0]
+    assert rho_l == pytest.approx(rl, rel=5e-5, abs=1e-5)
+    assert rho_r == pytest.approx(rr, rel=5e-5, abs=1e-5)
+
+
+def random_side(rng):
+    return (np.exp(rng.uniform(-2, 2)), rng.uniform(-2, 2), np.exp(rng.uniform(-3, 3)))
+
+
+def jump_ok(state_k, rho_s, us, ps, sign):
+    """Shock: Rankine-Hugoniot for mass, momentum, energy with the speed from
+    the mass relation; rarefaction: equal entropy and equal Riemann
+    invariant u -/+ 2a/(gamma-1) of the family (sign -1 left, +1 right)."""
+    rk, uk, pk = state_k
+    if ps > pk:
+        S = (rho_s * us - rk * uk) / (rho_s - rk)
+        Ek = pk / (G - 1) + 0.5 * rk * uk ** 2
+        Es = ps / (G - 1) + 0.5 * rho_s * us ** 2
+        sc = max(rk * abs(uk) + pk, rho_s * abs(us) + ps, 1.0)
+        assert rk * (uk - S) == pytest.approx(rho_s * (us - S), abs=1e-10 * sc)
+        assert rk * uk * (uk - S) + pk == pytest.approx(rho_s * us * (us - S) + ps, abs=1e-10 * sc * (1 + abs(S)))
+        assert (Ek + pk) * uk - S * Ek == pytest.approx((Es + ps) * us - S * Es,
+                                                         abs=1e-9 * sc * (1 + abs(S) + abs(uk) + abs(us)) ** 2)
+    else:
+        assert pk / rk ** G == pytest.approx(ps / rho_s ** G, rel=1e-12)
+        ak, a_s = np.sqrt(G * pk / rk), np.sqrt(G * ps / rho_s)
+        assert uk - sign * 2 * ak / (G - 1) == pytest.approx(us - sign * 2 * a_s / (G - 1),
+                                                             abs=1e-11 * (1 + abs(uk) + ak))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_riemann_jump_relations_and_symmetries(seed):
+    rng = np.random.default_rng(seed)
+    left, right = random_side(rng), random_side(rng)
+    res = O.riemann_star(G, left, right)
+    if res is None:  # vacuum: the data must satisfy the vacuum condition
+        al, ar = (np.sqrt(G * s[2] / s[0]) for s in (left, right))
+        assert right[1] - left[1] >= 2 * (al + ar) / (G - 1)
+        return
+    ps, us = res
+    eps = 1e-9 * (1 + abs(us))
+    rho_l = O.riemann_sample(G, left, right, us - eps)[0]
+    rho_r = O.riemann_sample(G, left, right, us + eps)[0]
+    jump_ok(left, rho_l, us, ps, -1)
+    jump_ok(right, rho_r, us, ps, +1)
+    # Galilean shift: p* unchanged, u* shifted
+    w = rng.uniform(-3, 3)
+    p2, u2 = O.riemann_star(G, (left[0], left[1] + w, left[2]), (right[0], right[1] + w, right[2]))
+    assert p2 == pytest.approx(ps, rel=1e-12)
+    assert u2 == pytest.approx(us + w, abs=1e-12 * (1 + abs(us) + abs(w)))
+    # mirror: swap sides and reverse velocities
+    p3, u3 = O.riemann_star(G, (right[0], -right[1], right[2]), (left[0], -left[1], left[2]))
+    assert p3 == pytest.approx(ps, rel=1e-12)
+    assert u3 == pytest.approx(-us, abs=1e-12 * (1 + abs(us)))
+
+
+def test_riemann_trivial_cases():
+    s = (0.7, 0.3, 1.9)
+    ps, us = O.riemann_star(G, s, s)
+    assert ps == pytest.approx(s[2], rel=1e-14) and us == pytest.approx(s[1], abs=1e-14)
+    for xi in (-5.0, 0.0, 0.3, 5.0):
+        r, u, p, _ = O.riemann_sample(G, s, s, xi)
+        assert (r, u, p) == pytest.approx(s, rel=1e-13)
+    # symmetric collision: the contact stays at rest
+    assert O.riemann_star(G, (1.0, 1.0, 1.0), (1.0, -1.0, 1.0))[1] == pytest.approx(0.0, abs=1e-14)
+    # vacuum generation is reported
+    assert O.riemann_star(G, (1.0, -10.0, 0.1), (1.0, 10.0, 0.1)) is None
+
+
+def cons(rho, v, p):
+    v = np.asarray(v, float)
+    return np.array([rho, *(rho * v), p / (G - 1) + 0.5 * rho * v @ v])
+
+
+def prim(U, n):
+    rho = U[0]
+    v = U[1:-1] / rho
+    p = (G - 1) * (U[-1] - 0.5 * rho * v @ v)
+    a = np.sqrt(G * p / rho)
+    vn = v @ n
+    return rho, v, vn, v - vn * n, p, a
+
+
+def invariants(U, n):
+    rho, v, vn, vt, p, a = prim(U, n)
+    return vn - 2 * a / (G - 1), vn + 2 * a / (G - 1), p * rho ** -G, vt
+
+
+def random_case(rng, dim, mach_n):
+    """A node state with normal Mach number mach_n (negative: inflow) and an
+    admissible far-field state ((gamma-1)/2 vn^D <= a^D)."""
+    n = rng.normal(size=dim)
+    n /= np.linalg.norm(n)
+    rho, p = np.exp(rng.uniform(-1, 1)), np.exp(rng.uniform(-1, 1))
+    a = np.sqrt(G * p / rho)
+    t = rng.normal(size=dim)
+    t -= (t @ n) * n
+    U = cons(rho, mach_n * a * n + 0.3 * a * t, p)
+    rD, pD = rho * np.exp(rng.uniform(-0.2, 0.2)), p * np.exp(rng.uniform(-0.2, 0.2))
+    aD = np.sqrt(G * pD / rD)
+    tD = rng.normal(size=dim)
+    tD -= (tD @ n) * n
+    UD = cons(rD, rng.uniform(-0.8, 0.8) * aD * n + 0.2 * aD * tD, pD)
+    return U, UD, n
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("seed", range(6))
+def test_characteristic_cases_keep_their_invariants(dim, seed):
+    rng = np.random.default_rng(100 * dim + seed)
+    m = O.NR_CHARACTERISTIC
+    # supersonic inflow: the far-field state
+    U, UD, n = random_case(rng, dim, -1.7)
+    UP, ok = O.nr_state(G, m, U, UD, n)
+    assert ok and np.array_equal(UP, UD)
+    # supersonic outflow: unchanged
+    U, UD, n = random_case(rng, dim, 1.4)
+    UP, ok = O.nr_state(G, m, U, UD, n)
+    assert ok and np.array_equal(UP, U)
+    # subsonic inflow: C1, S, V_perp from the far field, C3 from the node
+    U, UD, n = random_case(rng, dim, -0.4)
+    UP, ok = O.nr_state(G, m, U, UD, n)
+    c1, c3, S, vt = invariants(UP, n)
+    c1D, _, SD, vtD = invariants(UD, n)
+    _, c3U, _, _ = invariants(U, n)
+    assert ok
+    assert c1 == pytest.approx(c1D, abs=1e-12 * (1 + abs(c1D)))
+    assert c3 == pytest.approx(c3U, abs=1e-12 * (1 + abs(c3U)))
+    assert S == pytest.approx(SD, rel=1e-12)
+    assert np.allclose(vt, vtD, rtol=0, atol=1e-12 * (1 + np.abs(vtD).max()))
+    # subsonic outflow: C1 from the far field, C3, S, V_perp from the node
+    U, UD, n = random_case(rng, dim, 0.5)
+    UP, ok = O.nr_state(G, m, U, UD, n)
+    c1, c3, S, vt = invariants(UP, n)
+    c1D = invariants(UD, n)[0]
+    _, c3U, SU, vtU = invariants(U, n)
+    assert ok
+    assert c1 == pytest.approx(c1D, abs=1e-12 * (1 + abs(c1D)))
+    assert c3 == pytest.approx(c3U, abs=1e-12 * (1 + abs(c3U)))
+    assert S == pytest.approx(SU, rel=1e-12)
+    assert np.allclose(vt, vtU, rtol=0, atol=1e-12 * (1 + np.abs(vtU).max()))
+
+
+@pytest.mark.parametrize("method", [O.NR_CHARACTERISTIC, O.NR_GODUNOV])
+def test_far_field_equal_to_the_node_is_kept(method):
+    rng = np.random.default_rng(7)
+    for mach in (-1.5, -0.6, -0.1, 0.0, 0.2, 0.7, 1.3):
+        U, _, n = random_case(rng, 2, mach)
+        UP, ok = O.nr_state(G, method, U, U, n)
+        assert ok
+        assert np.allclose(UP, U, rtol=1e-13, atol=1e-13 * np.abs(U).max())
+
+
+@pytest.mark.parametrize("method", [O.NR_CHARACTERISTIC, O.NR_GODUNOV])
+def test_post_processed_states_are_admissible(method):
+    rng = np.random.default_rng(11)
+    for k in range(400):
+        dim = 2 + k % 2
+        U, UD, n = random_case(rng, dim, rng.uniform(-2.5, 2.5))
+        UP, ok = O.nr_state(G, method, U, UD, n)
+        rho, v, vn, vt, p, a = prim(UP, n)
+        assert ok and rho > 0 and p > 0
+
+
+def test_godunov_solution_at_the_boundary():
+    """Eq. Godunov_bc: density, normal velocity and pressure are the exact
+    Riemann solution at x = 0 (node state inside, far field outside); the
+    tangential velocity is carried from the side of the contact."""
+    rng = np.random.default_rng(3)
+    for mach in (-1.8, -0.5, 0.0, 0.4, 1.6):
+        U, UD, n = random_case(rng, 3, mach)
+        UP, ok = O.nr_state(G, O.NR_GODUNOV, U, UD, n)
+        _, _, vn, vt, p, _ = prim(U, n)
+        _, _, vnD, vtD, pD, _ = prim(UD, n)
+        r, u, pp, side = O.riemann_sample(G, (U[0], vn, p), (UD[0], vnD, pD), 0.0)
+        rho, _, vnP, vtP, pP, _ = prim(UP, n)
+        assert ok
+        assert rho == pytest.approx(r, rel=1e-14)
+        assert vnP == pytest.approx(u, abs=1e-13 * (1 + abs(u)))
+        assert pP == pytest.approx(pp, rel=1e-12)
+        assert np.allclose(vtP, vt if side < 0 else vtD, atol=1e-13 * (1 + np.abs(vt).max()))
+
+
+def vortex_box(n=20):
+    mesh = W.Mesh(2, (n, n), (-1.0, -1.0), (1.0, 1.0), (False, False))
+    og = O.Graph(2, mesh.n, mesh.lo, mesh.hi, mesh.periodic)
+    return mesh, og
+
+
+@pytest.mark.parametrize("method", [O.NR_CHARACTERISTIC, O.NR_GODUNOV])
+@pytest.mark.parametrize("mach", [0.5, 2.0])
+def test_uniform_far_field_flow_is_steady(method, mach):
+    """Uniform flow equal to the far field on every non-reflecting face is
+    a steady solution: a step keeps it to round-off (subsonic and
+    supersonic)."""
+    mesh, og = vortex_box(17)
+    a = 1.0 / mach
+    UD = cons(1.0, (1.0, 0.3), a * a / G)
+    U = np.repeat(UD[:, None], mesh.N, axis=1)
+    bnd = O.boundary([O.BC_NONREFLECTING] * 4, method, [UD] * 4)
+    prm = O.params(cfl=0.5)
+    tau = og.compute_dt(prm, U)
+    out, st = og.ssprk3_step(prm, U, tau, bnd)
+    assert st == 0
+    assert np.allclose(out, U, rtol=0, atol=1e-13)
+
+
+def test_all_slip_faces_equal_the_slip_post_processing():
+    mesh, U = W.four_quadrant_state(23, seed=3)
+    og = O.Graph(2, mesh.n, mesh.lo, mesh.hi, mesh.periodic)
+    U = og.slip_bc(U)
+    prm = O.params()
+    tau = og.compute_dt(prm, U)
+    a, st_a = og.ssprk3_step(prm, U, tau)
+    b, st_b = og.ssprk3_step(prm, U, tau, O.boundary([O.BC_SLIP] * 4))
+    assert st_a == st_b == 0
+    assert np.allclose(a, b, rtol=0, atol=1e-14 * np.abs(a).max())
