@@ -231,6 +231,36 @@ typedef struct ns_par_info {
 /* Diagnostics of the last parabolic step. */
 int ns_parabolic_info(ns_solver *s, ns_par_info *out);
 
+/* ---- boundary kinds: slip and non-reflecting faces ----------------------
+ * Every face of a non-periodic direction (f = 2*dir + side: side 0 the low
+ * end with outward normal -e_dir, side 1 the high end) is slip (the
+ * default: eq. slip_bc) or non-reflecting (Sec. 4.3.2) with a far-field
+ * (Dirichlet) state: post-processing by the characteristic variables (eqs.
+ * Supersonic_inflow, Subsonic_inflow, Subsonic_outflow, Supersonic_outflow)
+ * or by Godunov's method (eq. Godunov_bc, the exact Riemann solution at the
+ * boundary).  A node belongs to the slip set if a slip face touches it and
+ * to the non-reflecting set if a non-reflecting face does; its normal in
+ * each set is the normalised integral of phi_i n over that set's faces (eq.
+ * def_ns_nio).  After every stage the non-reflecting nodes are post-processed
+ * first, then the slip nodes (a node in both keeps no normal momentum
+ * through its slip faces); a node on several non-reflecting faces takes the
+ * far-field state of the lowest-numbered one.  An inadmissible result
+ * (Godunov with vacuum) keeps the node's state and the step returns
+ * NS_EBOUNDS.  Non-reflecting faces are for the Euler step: with any,
+ * ns_step_parabolic and the Strang steps return NS_ESTATE.  NS_EINVAL for
+ * unknown kinds or methods, a non-admissible far-field state, or one that
+ * violates (gamma-1)/2 v_n^D <= a^D on its face (the Lemma's condition). */
+enum { NS_BC_SLIP = 0, NS_BC_NONREFLECTING = 1 };
+enum { NS_NR_CHARACTERISTIC = 0, NS_NR_GODUNOV = 1 };
+typedef struct ns_boundary {
+  int kind[6];         /* per face: NS_BC_*; faces of periodic directions   */
+                       /* and beyond dim are ignored                        */
+  int method;          /* NS_NR_*                                           */
+  double state[6][5];  /* far-field state per non-reflecting face: rho,     */
+                       /* m (dim components), E                             */
+} ns_boundary;
+int ns_set_boundary(ns_solver *s, const ns_boundary *b);
+
 /* ---- asynchronous stepping (serving) ------------------------------------
  * ns_step_cfl_async enqueues nsteps SSPRK(3,3) steps, each with its own CFL
  * time step computed on the device as in ns_step_cfl, and returns without

@@ -132,7 +132,7 @@ int orc_riemann_sample(double gamma, double rl, double ul, double pl, double rr,
 /* Post-processed state of one non-reflecting node: U, the far-field state UD
  * and the unit outward normal n (eq. Godunov_bc, or eqs. Supersonic_inflow,
  * Subsonic_inflow, Subsonic_outflow, Supersonic_outflow).  Returns 0, or 1
- * if the result is not admissible (Godunov with vacuum). */
+ * if the result is not admissible (Godunov with vacuum: then UP = U). */
 int orc_nr_state(double gamma, int dim, int method, const double *U, const double *UD,
                  const double *n, double *UP);
 /* Post-processing of a stage result in place; returns 0 or 1 (as above). */

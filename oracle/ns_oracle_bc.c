@@ -139,8 +139,10 @@ int orc_nr_state(double g, int dim, int method, const double *U, const double *U
     double rho, un, p;
     int side;
     if (orc_riemann_sample(g, q.rho, q.vn, q.p, d.rho, d.vn, d.p, 0.0, &rho, &un, &p,
-                           &side))
+                           &side)) {
+      memcpy(UP, U, sizeof(double) * nc);  /* vacuum: the state is kept, flagged */
       return 1;
+    }
     conserved(g, dim, rho, un, side < 0 ? q.vt : d.vt, p, n, UP);
   } else {
     if (q.vn < 0.0 && q.a < fabs(q.vn)) {           /* supersonic inflow */

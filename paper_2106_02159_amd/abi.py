@@ -40,7 +40,7 @@ EXPORTED = [
     "ns_server_submit", "ns_server_progress", "ns_server_request", "ns_server_result",
     "ns_server_stats_get", "ns_server_error", "ns_pack_footprint", "ns_pack_create",
     "ns_pack_destroy", "ns_pack_set_state", "ns_pack_get_state", "ns_pack_step_cfl_async",
-    "ns_pack_inflight", "ns_pack_finish", "ns_pack_error",
+    "ns_pack_inflight", "ns_pack_finish", "ns_pack_error", "ns_set_boundary",
 ]
 
 
@@ -126,6 +126,7 @@ def lib() -> C.CDLL:
             "ns_pack_inflight": (C.c_int, [vp, C.POINTER(C.c_int)]),
             "ns_pack_finish": (C.c_int, [vp, C.POINTER(C.c_int), dp]),
             "ns_pack_error": (C.c_char_p, [vp]),
+            "ns_set_boundary": (C.c_int, [vp, C.POINTER(Boundary)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -200,6 +201,14 @@ class Viscous(C.Structure):
 class ParInfo(C.Structure):
     _fields_ = [("it_v", C.c_int), ("it_e", C.c_int), ("it_l", C.c_int),
                 ("fct", C.c_int), ("min_eH", C.c_double)]
+
+
+class Boundary(C.Structure):
+    _fields_ = [("kind", C.c_int * 6), ("method", C.c_int), ("state", (C.c_double * 5) * 6)]
+
+
+BC_SLIP, BC_NONREFLECTING = 0, 1
+NR_CHARACTERISTIC, NR_GODUNOV = 0, 1
 
 
 class ServerParams(C.Structure):
@@ -452,6 +461,18 @@ class Solver:
     # -- asynchronous stepping ---------------------------------------------
     def step_cfl_async(self, nsteps: int):
         return self._check(lib().ns_step_cfl_async(self.h, int(nsteps)))
+
+    def set_boundary(self, kind, method=NR_CHARACTERISTIC, state=None):
+        """Faces f = 2*dir + side: kind[f] in BC_*; state[f] the far-field
+        conserved state (rho, m, E) of a non-reflecting face."""
+        b = Boundary()
+        for f in range(6):
+            b.kind[f] = int(kind[f]) if f < len(kind) else BC_SLIP
+            if state is not None and f < len(state) and state[f] is not None:
+                for c, v in enumerate(state[f]):
+                    b.state[f][c] = float(v)
+        b.method = int(method)
+        self._check(lib().ns_set_boundary(self.h, C.byref(b)))
 
     def query(self) -> bool:
         done = C.c_int()

@@ -108,6 +108,13 @@ void launch_dt_only(int dim, const Gas &gas, const DevGraphT<LT> &g,
 // t is nrm[k*stride + t] (stride < 0: nslip).
 void launch_slip(int dim, int64_t N, int nslip, const int32_t *idx,
                  const double *nrm, double *U, hipStream_t s, int stride = -1);
+// Non-reflecting post-processing (bc_kernels.hip) of n listed nodes: method
+// 0 characteristic variables, 1 Godunov; normal component k of entry t at
+// nrm[k*n + t], far-field state component c at ud[c*n + t]; flags[1] is set
+// for an inadmissible result.
+void launch_nonreflecting(int dim, const Gas &gas, int method, int n, const int32_t *idx,
+                          const double *nrm, const double *ud, int64_t N, double *U,
+                          int *flags, hipStream_t s);
 void launch_set_scalar(double *p, double v, hipStream_t s, int n = 1);  // p[0..n) = v
 void launch_add_scalar(double *acc, const double *v, hipStream_t s,
                        int n = 1);  // acc[k] += v[k], k < n

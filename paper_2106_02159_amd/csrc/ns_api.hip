@@ -139,6 +139,11 @@ struct ns_solver {
   int nslip = 0;
   int32_t *slip_idx = nullptr;
   double *slip_n = nullptr;
+  // non-reflecting nodes (ns_set_boundary): index, unit normal (dim x nnr),
+  // far-field state (nc x nnr), method
+  int nnr = 0, nr_method = 0;
+  int32_t *nr_idx = nullptr;
+  double *nr_n = nullptr, *nr_ud = nullptr;
   // state and scratch
   double *S[3] = {nullptr, nullptr, nullptr};
   int cur = 0;
@@ -228,6 +233,17 @@ struct ns_solver {
     *p = static_cast<T *>(q);
     return hipSuccess;
   }
+  // frees one allocation made by alloc (stream-ordered)
+  template <typename T> void free_one(T *&p, size_t count) {
+    if (!p) return;
+    auto it = std::find(allocs.begin(), allocs.end(), (void *)p);
+    if (it != allocs.end()) {
+      allocs.erase(it);
+      bytes -= (int64_t)(count * sizeof(T));
+      (void)hipFreeAsync(p, stream);
+    }
+    p = nullptr;
+  }
 };
 
 namespace {
@@ -285,7 +301,16 @@ void run_stage(ns_solver *s, int in, int out, double sa, double sb, int check,
                      &s->prof);
 }
 
+// Boundary post-processing of a stage result (Sec. 4.3): the non-reflecting
+// nodes first, then the slip projection (a node in both sets keeps no normal
+// momentum through its slip faces).
 void run_slip(ns_solver *s, int buf) {
+  if (s->nnr > 0) {
+    Profiler::before(&s->prof, "nonreflecting");
+    ns::launch_nonreflecting(s->dim, s->gas, s->nr_method, s->nnr, s->nr_idx, s->nr_n,
+                             s->nr_ud, s->N, s->S[buf], s->flags, s->stream);
+    Profiler::after(&s->prof);
+  }
   Profiler::before(&s->prof, "slip");
   ns::launch_slip(s->dim, s->N, s->nslip, s->slip_idx, s->slip_n, s->S[buf],
                   s->stream);
@@ -1041,6 +1066,8 @@ int ns_step_parabolic(ns_solver *s, double dt) {
   if (!(dt > 0.0) || !std::isfinite(dt)) return s->fail(NS_EINVAL, "dt must be positive");
   if (!s->has_state) return s->fail(NS_ESTATE, "no state set");
   if (!s->viscous) return s->fail(NS_ESTATE, "ns_set_viscous has not been called");
+  if (s->nnr > 0)
+    return s->fail(NS_ESTATE, "non-reflecting boundaries are for the Euler step only");
   const int o = others(s->cur, 0);
   const int rc = par_step(s, dt, s->cur, o);
   if (rc == NS_OK) s->cur = o;
@@ -1050,12 +1077,135 @@ int ns_step_parabolic(ns_solver *s, double dt) {
 int ns_step_strang(ns_solver *s, double tau) {
   if (!s) return NS_EINVAL;
   if (!(tau > 0.0) || !std::isfinite(tau)) return s->fail(NS_EINVAL, "tau must be positive");
+  if (s->nnr > 0)
+    return s->fail(NS_ESTATE, "non-reflecting boundaries are for the Euler step only");
   return strang(s, tau, false, nullptr);
 }
 
 int ns_step_strang_cfl(ns_solver *s, double *tau) {
   if (!s) return NS_EINVAL;
+  if (s->nnr > 0)
+    return s->fail(NS_ESTATE, "non-reflecting boundaries are for the Euler step only");
   return strang(s, 0.0, true, tau);
+}
+
+int ns_set_boundary(ns_solver *s, const ns_boundary *b) {
+  if (!s || !b) return NS_EINVAL;
+  if (s->pack) return s->fail(NS_EINVAL, "boundary kinds are set per solver, not per pack");
+  const int dim = s->dim, nc = s->nc;
+  const ns::MeshGraph &m = s->mg;
+  if (b->method != NS_NR_CHARACTERISTIC && b->method != NS_NR_GODUNOV)
+    return s->fail(NS_EINVAL, "unknown non-reflecting method");
+  bool any_nr = false;
+  for (int f = 0; f < 2 * dim; ++f) {
+    if (b->kind[f] != NS_BC_SLIP && b->kind[f] != NS_BC_NONREFLECTING)
+      return s->fail(NS_EINVAL, "unknown boundary kind");
+    if (b->kind[f] != NS_BC_NONREFLECTING || m.periodic[f / 2]) continue;
+    any_nr = true;
+    // admissible far-field state with (gamma-1)/2 v_n^D <= a^D on this face
+    const double *u = b->state[f];
+    double m2 = 0.0;
+    bool fin = std::isfinite(u[0]) && std::isfinite(u[dim + 1]);
+    for (int k = 0; k < dim; ++k) { fin = fin && std::isfinite(u[1 + k]); m2 += u[1 + k] * u[1 + k]; }
+    const double p = s->gas.gm1 * (u[dim + 1] - 0.5 * m2 / u[0]);
+    if (!fin || !(u[0] > 0.0) || !(p > 0.0))
+      return s->fail(NS_EINVAL, "far-field state of a non-reflecting face not admissible");
+    const double vn = (f % 2 ? 1.0 : -1.0) * u[1 + f / 2] / u[0];
+    if (0.5 * s->gas.gm1 * vn > std::sqrt(s->gas.gamma * p / u[0]))
+      return s->fail(NS_EINVAL, "far-field state violates (gamma-1)/2 v_n <= a on its face");
+  }
+  (void)any_nr;
+  // node sets and normals (eq. def_ns_nio) from the faces' integrals of phi_i
+  const int64_t N = s->N;
+  std::vector<int32_t> sidx, nidx;
+  std::vector<double> sn, nn, nud;
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t a[3];
+    m.coords(i, a);
+    double ns_[3] = {0, 0, 0}, nr_[3] = {0, 0, 0};
+    int first_nr = -1;
+    bool on_s = false, on_nr = false;
+    for (int f = 0; f < 2 * dim; ++f) {
+      const int d = f / 2;
+      if (m.periodic[d] || a[d] != (f % 2 ? m.n[d] - 1 : 0)) continue;
+      double w = 1.0;  // int over face f of phi_i
+      for (int e = 0; e < dim; ++e)
+        if (e != d) w *= m.ml(e, a[e]);
+      const double sg = f % 2 ? 1.0 : -1.0;
+      if (b->kind[f] == NS_BC_NONREFLECTING) {
+        nr_[d] += sg * w;
+        on_nr = true;
+        if (first_nr < 0) first_nr = f;
+      } else {
+        ns_[d] += sg * w;
+        on_s = true;
+      }
+    }
+    auto unit = [dim](double *v) {
+      double l = 0.0;
+      for (int k = 0; k < dim; ++k) l += v[k] * v[k];
+      l = std::sqrt(l);
+      for (int k = 0; k < dim; ++k) v[k] /= l;
+      return l > 0.0;
+    };
+    if (on_s && unit(ns_)) {
+      sidx.push_back((int32_t)i);
+      for (int k = 0; k < dim; ++k) sn.push_back(ns_[k]);
+    }
+    if (on_nr && unit(nr_)) {
+      nidx.push_back((int32_t)i);
+      for (int k = 0; k < dim; ++k) nn.push_back(nr_[k]);
+      for (int c = 0; c < nc; ++c) nud.push_back(b->state[first_nr][c]);
+    }
+  }
+  // structure of arrays on the device
+  const int nsl = (int)sidx.size(), nnr = (int)nidx.size();
+  std::vector<double> snT((size_t)dim * nsl), nnT((size_t)dim * nnr), udT((size_t)nc * nnr);
+  for (int t = 0; t < nsl; ++t)
+    for (int k = 0; k < dim; ++k) snT[(size_t)k * nsl + t] = sn[(size_t)t * dim + k];
+  for (int t = 0; t < nnr; ++t) {
+    for (int k = 0; k < dim; ++k) nnT[(size_t)k * nnr + t] = nn[(size_t)t * dim + k];
+    for (int c = 0; c < nc; ++c) udT[(size_t)c * nnr + t] = nud[(size_t)t * nc + c];
+  }
+  // a captured step holds the old lists: drop it
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return s->hipfail(e, "stream synchronize");
+  for (hipGraphExec_t &gx : s->step_graph) {
+    if (gx) (void)hipGraphExecDestroy(gx);
+    gx = nullptr;
+  }
+  s->free_one(s->slip_idx, s->nslip);
+  s->free_one(s->slip_n, (size_t)dim * s->nslip);
+  s->free_one(s->nr_idx, s->nnr);
+  s->free_one(s->nr_n, (size_t)dim * s->nnr);
+  s->free_one(s->nr_ud, (size_t)nc * s->nnr);
+  s->nslip = 0;
+  s->nnr = 0;
+  if ((e = s->alloc(&s->slip_idx, nsl)) != hipSuccess ||
+      (e = s->alloc(&s->slip_n, (size_t)dim * nsl)) != hipSuccess ||
+      (e = s->alloc(&s->nr_idx, nnr)) != hipSuccess ||
+      (e = s->alloc(&s->nr_n, (size_t)dim * nnr)) != hipSuccess ||
+      (e = s->alloc(&s->nr_ud, (size_t)nc * nnr)) != hipSuccess) {
+    (void)hipGetLastError();
+    return s->fail(NS_ENOMEM, "boundary lists");
+  }
+  struct { void *dst; const void *src; size_t n; } ups[] = {
+      {s->slip_idx, sidx.data(), sidx.size() * sizeof(int32_t)},
+      {s->slip_n, snT.data(), snT.size() * sizeof(double)},
+      {s->nr_idx, nidx.data(), nidx.size() * sizeof(int32_t)},
+      {s->nr_n, nnT.data(), nnT.size() * sizeof(double)},
+      {s->nr_ud, udT.data(), udT.size() * sizeof(double)}};
+  for (auto &u : ups) {
+    if (u.n == 0) continue;
+    e = hipMemcpyAsync(u.dst, u.src, u.n, hipMemcpyHostToDevice, s->stream);
+    if (e != hipSuccess) return s->hipfail(e, "boundary upload");
+  }
+  e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return s->hipfail(e, "boundary upload");
+  s->nslip = nsl;
+  s->nnr = nnr;
+  s->nr_method = b->method;
+  return NS_OK;
 }
 
 int ns_parabolic_info(ns_solver *s, ns_par_info *out) {

@@ -225,3 +225,24 @@ def serving_requests(count: int = 256, seed: int = 0, nmin: int = 64,
     n = np.rint(np.exp(rng.uniform(np.log(nmin), np.log(nmax), size=count))).astype(int)
     seeds = rng.integers(0, 2 ** 31 - 1, size=count)
     return [(float(t[k]), int(n[k]), int(seeds[k])) for k in range(count)]
+
+
+def nr_vortex_state(n: int = 80, mach: float = 0.5, vbar: float = 0.75, r0: float = 0.25,
+                    gamma: float = 1.4):
+    """Vortex convected through [-1,1]^2 by a uniform stream (the
+    non-reflecting boundary tests of the paper's Sec. 5): rho = 1,
+    v = v_inf + vbar/r0 psi(|x|) (-y, x), p = p_inf - rho vbar^2 psi^2 / 2,
+    psi(r) = exp((1 - r^2/r0^2)/2), v_inf = (1, 0), a_inf = 1/mach,
+    p_inf = a_inf^2/gamma; centre 0 and r0 = 0.25 (not given in the paper).
+    Returns (mesh, U, far-field state U_inf)."""
+    mesh = Mesh(2, (n, n), (-1.0, -1.0), (1.0, 1.0), (False, False))
+    x, y = mesh.coords()
+    psi = np.exp(0.5 * (1.0 - (x * x + y * y) / r0 ** 2))
+    p_inf = (1.0 / mach) ** 2 / gamma
+    u = 1.0 - vbar / r0 * psi * y
+    v = vbar / r0 * psi * x
+    p = p_inf - 0.5 * vbar ** 2 * psi ** 2
+    rho = np.ones_like(x)
+    U = np.vstack([rho, rho * u, rho * v, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
+    U_inf = np.array([1.0, 1.0, 0.0, p_inf / (gamma - 1.0) + 0.5])
+    return mesh, U, U_inf
