@@ -144,6 +144,19 @@ int orc_boundary_bc(const orc_graph *g, const orc_params *p, const orc_boundary 
 int orc_ssprk3_step_bc(const orc_graph *g, const orc_params *p, const orc_boundary *b,
                        const double *U, double tau, double *Uout);
 
+/* One SSPRK(3,3) step with the adaptive CFL number of the Remark on high
+ * aspect-ratio meshes (Sec. 3.1): tau = c min_i(-m_i/(2 d_ii)) with c
+ * starting at c_start (may exceed 1); the stage CFL limit is not imposed,
+ * instead every stage's low-order update U^L and every stage result (after
+ * the SSP combination, before the boundary post-processing) must be
+ * admissible, and so must the post-processed states; if any is not, the
+ * step restarts from U with c halved.  b may be NULL (slip everywhere).
+ * Returns 0 with tau_out, c_out and Uout, or 1 if no c in the sequence
+ * c_start 2^-k, k < 24, works. */
+int orc_ssprk3_step_adaptive(const orc_graph *g, const orc_params *p,
+                             const orc_boundary *b, const double *U, double c_start,
+                             double *tau_out, double *c_out, double *Uout);
+
 /* Unlimited high-order update computed directly from M_L (U^H - U) =
  * tau (I + B) F^H, used to check the limiter's l = 1 special case. */
 int orc_high_order_direct(const orc_graph *g, const orc_params *p,

@@ -231,3 +231,68 @@ int orc_ssprk3_step_bc(const orc_graph *g, const orc_params *p, const orc_bounda
   free(w1); free(w2); free(t);
   return st | (bad << 1);
 }
+
+/* admissible: rho > 0 and internal energy > 0 at every node */
+static int all_admissible(int dim, long N, const double *U) {
+  for (long i = 0; i < N; ++i) {
+    double m2 = 0.0;
+    for (int k = 0; k < dim; ++k) m2 += U[(size_t)(1 + k) * N + i] * U[(size_t)(1 + k) * N + i];
+    const double rho = U[i], e = U[(size_t)(dim + 1) * N + i] - 0.5 * m2 / rho;
+    if (!(rho > 0.0) || !(e > 0.0)) return 0;
+  }
+  return 1;
+}
+
+static int post(const orc_graph *g, const orc_params *p, const orc_boundary *b, double *U) {
+  if (b) return orc_boundary_bc(g, p, b, U);
+  orc_slip_bc(g, U);
+  return 0;
+}
+
+int orc_ssprk3_step_adaptive(const orc_graph *g, const orc_params *p,
+                             const orc_boundary *b, const double *U, double c_start,
+                             double *tau_out, double *c_out, double *Uout) {
+  const int dim = g->dim, nc = dim + 2;
+  const long N = g->N;
+  const size_t len = (size_t)nc * N;
+  double *w1 = (double *)malloc(sizeof(double) * len);
+  double *w2 = (double *)malloc(sizeof(double) * len);
+  double *t = (double *)malloc(sizeof(double) * len);
+  double *UL = (double *)malloc(sizeof(double) * len);
+  orc_debug dbg;
+  memset(&dbg, 0, sizeof(dbg));
+  dbg.UL = UL;
+  int done = 0;
+  double c = c_start;
+  for (int k = 0; k < 24 && !done; ++k, c *= 0.5) {
+    orc_params q = *p;
+    q.cfl = c;
+    double tau;
+    orc_compute_dt(g, &q, U, &tau);
+    int ok = 1;
+    /* stage 1 */
+    orc_fe_stage(g, &q, U, tau, w1, &dbg);
+    ok = ok && all_admissible(dim, N, UL) && all_admissible(dim, N, w1);
+    ok = ok && !post(g, &q, b, w1);
+    /* stage 2 */
+    if (ok) {
+      orc_fe_stage(g, &q, w1, tau, t, &dbg);
+      for (size_t e = 0; e < len; ++e) w2[e] = 0.75 * U[e] + 0.25 * t[e];
+      ok = all_admissible(dim, N, UL) && all_admissible(dim, N, w2) && !post(g, &q, b, w2);
+    }
+    /* stage 3 */
+    if (ok) {
+      orc_fe_stage(g, &q, w2, tau, t, &dbg);
+      for (size_t e = 0; e < len; ++e) Uout[e] = U[e] / 3.0 + 2.0 / 3.0 * t[e];
+      ok = all_admissible(dim, N, UL) && all_admissible(dim, N, Uout) &&
+           !post(g, &q, b, Uout);
+    }
+    if (ok) {
+      *tau_out = tau;
+      *c_out = c;
+      done = 1;
+    }
+  }
+  free(w1); free(w2); free(t); free(UL);
+  return done ? 0 : 1;
+}

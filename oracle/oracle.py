@@ -131,6 +131,9 @@ def lib():
                                       C.POINTER(_Boundary), dp]
         L.orc_ssprk3_step_bc.argtypes = [C.c_void_p, C.POINTER(_Params),
                                          C.POINTER(_Boundary), dp, C.c_double, dp]
+        L.orc_ssprk3_step_adaptive.argtypes = [C.c_void_p, C.POINTER(_Params),
+                                               C.POINTER(_Boundary), dp, C.c_double,
+                                               dp, dp, dp]
         _lib = L
     return _lib
 
@@ -295,6 +298,19 @@ class Graph:
             st = lib().orc_ssprk3_step_bc(self.h, C.byref(prm), C.byref(bnd), _dp(U), tau,
                                           _dp(out))
         return out, st
+
+    def ssprk3_step_adaptive(self, prm, U, c_start, bnd=None):
+        """(U^{n+1}, tau, c) of a step with the adaptive CFL number (restart
+        with c halved while a low-order state or a stage result is not
+        admissible), or None if no c works."""
+        U = np.ascontiguousarray(U, np.float64)
+        out = np.empty_like(U)
+        tau, c = C.c_double(), C.c_double()
+        rc = lib().orc_ssprk3_step_adaptive(self.h, C.byref(prm),
+                                            C.byref(bnd) if bnd is not None else None,
+                                            _dp(U), float(c_start), C.byref(tau),
+                                            C.byref(c), _dp(out))
+        return None if rc else (out, tau.value, c.value)
 
     def boundary_bc(self, prm, bnd, U):
         """(post-processed copy of U, status) with oracle.boundary `bnd`."""

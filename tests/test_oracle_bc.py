@@ -254,3 +254,60 @@ def test_all_slip_faces_equal_the_slip_post_processing():
     b, st_b = og.ssprk3_step(prm, U, tau, O.boundary([O.BC_SLIP] * 4))
     assert st_a == st_b == 0
     assert np.allclose(a, b, rtol=0, atol=1e-14 * np.abs(a).max())
+
+
+def channel_tube(nx=80, ny=9, height=0.02):
+    """Sod data in a thin channel: cells of aspect ratio ~5."""
+    mesh = W.Mesh(2, (nx, ny), (0, 0), (1.0, height), (False, False))
+    x, _ = mesh.coords()
+    rho = np.where(x < 0.5, 1.0, 0.125)
+    p = np.where(x < 0.5, 1.0, 0.1)
+    U = np.vstack([rho, 0 * rho, 0 * rho, p / (G - 1)])
+    return mesh, U
+
+
+def test_adaptive_cfl_at_most_one_is_the_plain_step():
+    mesh, U = channel_tube()
+    og = O.Graph(2, mesh.n, mesh.lo, mesh.hi, mesh.periodic)
+    U = og.slip_bc(U)
+    for c in (0.3, 1.0):
+        prm = O.params(cfl=c)
+        out, tau, cu = og.ssprk3_step_adaptive(prm, U, c)
+        ref, st = og.ssprk3_step(prm, U, og.compute_dt(prm, U))
+        assert st == 0 and cu == c
+        assert tau == og.compute_dt(prm, U)
+        assert np.array_equal(out, ref)
+
+
+def test_adaptive_cfl_restarts_with_halved_c():
+    """From c = 16 the step restarts until every low-order state and stage
+    result is admissible; the accepted step equals the one started at the
+    accepted c, and the rejected c = 2 c_used really breaks admissibility."""
+    mesh, U = channel_tube()
+    og = O.Graph(2, mesh.n, mesh.lo, mesh.hi, mesh.periodic)
+    U = og.slip_bc(U)
+    prm = O.params()
+    out, tau, c = og.ssprk3_step_adaptive(prm, U, 16.0)
+    assert 1.0 < c < 16.0 and c in (8.0, 4.0, 2.0)
+    out2, tau2, c2 = og.ssprk3_step_adaptive(prm, U, c)
+    assert c2 == c and tau2 == tau and np.array_equal(out, out2)
+    assert tau == og.compute_dt(O.params(cfl=c), U)
+
+    def admissible(V):
+        e = V[3] - 0.5 * (V[1] ** 2 + V[2] ** 2) / V[0]
+        return bool(np.all(V[0] > 0) and np.all(e > 0))
+
+    q = O.params(cfl=2 * c)
+    t2 = og.compute_dt(q, U)
+    w1, _, dbg = og.fe_stage(q, U, t2, debug=True)
+    bad = not (admissible(dbg["UL"]) and admissible(w1))
+    if not bad:
+        w1 = og.slip_bc(w1)
+        t, _, dbg = og.fe_stage(q, w1, t2, debug=True)
+        w2 = 0.75 * U + 0.25 * t
+        bad = not (admissible(dbg["UL"]) and admissible(w2))
+        if not bad:
+            w2 = og.slip_bc(w2)
+            t, _, dbg = og.fe_stage(q, w2, t2, debug=True)
+            bad = not (admissible(dbg["UL"]) and admissible(U / 3.0 + 2.0 / 3.0 * t))
+    assert bad
