@@ -167,6 +167,15 @@ int ns_step(ns_solver *s, double dt);
  * first stage from that stage's own d_ij and reused by stages 2 and 3
  * (Sec. 3.1).  The dt used is returned in *dt (may be NULL). */
 int ns_step_cfl(ns_solver *s, double *dt);
+/* One SSPRK(3,3) step with the adaptive CFL number of the Remark on high
+ * aspect-ratio meshes (Sec. 3.1): dt = c min_i(-m_i/(2 d_ii)) with c
+ * starting at c_start (0 < c_start <= 64; above 1 is the point), the stage
+ * CFL limit not imposed; instead every stage's low-order update U^L and
+ * every stage result must be admissible (and the boundary post-processing
+ * must succeed), else the step restarts from the same state with c halved.
+ * Transactional; *dt and *c_used (either may be NULL) report the accepted
+ * step.  NS_EBOUNDS if no c_start / 2^k, k < 24, works. */
+int ns_step_adaptive(ns_solver *s, double c_start, double *dt, double *c_used);
 
 /* ---- parabolic sub-step and Strang composition (Sec. 5) ----------------
  * Viscous and thermal data of the Navier-Stokes system: the viscous stress

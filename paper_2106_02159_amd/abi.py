@@ -41,6 +41,7 @@ EXPORTED = [
     "ns_server_stats_get", "ns_server_error", "ns_pack_footprint", "ns_pack_create",
     "ns_pack_destroy", "ns_pack_set_state", "ns_pack_get_state", "ns_pack_step_cfl_async",
     "ns_pack_inflight", "ns_pack_finish", "ns_pack_error", "ns_set_boundary",
+    "ns_step_adaptive",
 ]
 
 
@@ -127,6 +128,7 @@ def lib() -> C.CDLL:
             "ns_pack_finish": (C.c_int, [vp, C.POINTER(C.c_int), dp]),
             "ns_pack_error": (C.c_char_p, [vp]),
             "ns_set_boundary": (C.c_int, [vp, C.POINTER(Boundary)]),
+            "ns_step_adaptive": (C.c_int, [vp, C.c_double, dp, dp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -461,6 +463,12 @@ class Solver:
     # -- asynchronous stepping ---------------------------------------------
     def step_cfl_async(self, nsteps: int):
         return self._check(lib().ns_step_cfl_async(self.h, int(nsteps)))
+
+    def step_adaptive(self, c_start: float):
+        """(dt, c) of one step with the adaptive CFL number."""
+        dt, c = C.c_double(), C.c_double()
+        self._check(lib().ns_step_adaptive(self.h, float(c_start), C.byref(dt), C.byref(c)))
+        return dt.value, c.value
 
     def set_boundary(self, kind, method=NR_CHARACTERISTIC, state=None):
         """Faces f = 2*dir + side: kind[f] in BC_*; state[f] the far-field

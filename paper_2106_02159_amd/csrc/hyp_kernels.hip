@@ -472,6 +472,14 @@ __global__ __launch_bounds__(kBlock) void k_lo(DevGraphT<LT> G, StageArgsT<LT> A
     A.FH[q * N + i] = to_lt<LT>(fh[q] * rmi);
   }
   if (A.check_cfl && tau > G.mi[i] / (2.0 * dsum)) A.flags[4 * mem] = 1;
+  if (A.check_low) {
+    double ul[NC], m2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) ul[q] = ui[q] + tm * acc[q];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) m2 += ul[1 + k] * ul[1 + k];
+    if (!(ul[0] > 0.0) || !(ul[NC - 1] - 0.5 * m2 / ul[0] > 0.0)) A.flags[4 * mem + 3] = 1;
+  }
   const double r = G.rrel[i];
   A.bnds[i] = (1.0 - r) * rmin;
   A.bnds[N + i] = (1.0 + r) * rmax;

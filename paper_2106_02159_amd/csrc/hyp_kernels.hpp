@@ -71,6 +71,9 @@ struct StageArgsT {
   int *flags;        // [0] CFL violated, [1] inadmissible state
   double sa, sb;     // SSP combination out = sa*Un + sb*E(U)
   int check_cfl;
+  // adaptive CFL steps: flags[3] (of the member) is set where the low-order
+  // update U^L is not admissible
+  int check_low = 0;
   // Work list of the edges (sliced ELL index) whose line search needs the
   // root of the entropy bound; W*Np entries, so that it holds every edge.
   // Pass 1 fills it and k_root<1> drains it before pass 2 fills it again;

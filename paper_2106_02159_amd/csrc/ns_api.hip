@@ -142,6 +142,9 @@ struct ns_solver {
   // non-reflecting nodes (ns_set_boundary): index, unit normal (dim x nnr),
   // far-field state (nc x nnr), method
   int nnr = 0, nr_method = 0;
+  // adaptive CFL step in progress: CFL number of its time step, U^L checks
+  bool adaptive = false;
+  double cfl_now = 0.0;
   int32_t *nr_idx = nullptr;
   double *nr_n = nullptr, *nr_ud = nullptr;
   // state and scratch
@@ -201,7 +204,7 @@ struct ns_solver {
     b.U = a.U; b.Un = a.Un; b.out = a.out; b.aux = a.aux; b.UL = a.UL; b.bnds = a.bnds;
     b.U1 = a.U1; b.partial = a.partial; b.tau = a.tau; b.flags = a.flags;
     b.sa = a.sa; b.sb = a.sb; b.check_cfl = a.check_cfl; b.q = a.q; b.qcnt = a.qcnt;
-    b.seg = a.seg; b.mblk = a.mblk; b.nmem = a.nmem;
+    b.seg = a.seg; b.mblk = a.mblk; b.nmem = a.nmem; b.check_low = a.check_low;
     b.alpha = alphaf; b.d = df; b.FH = FHf; b.lt1 = lt1f; b.lt2 = lt2f;
     return b;
   }
@@ -210,7 +213,8 @@ struct ns_solver {
     a.U = S[in]; a.Un = S[cur]; a.out = S[out];
     a.aux = aux; a.alpha = alpha; a.d = d; a.UL = UL; a.FH = FH; a.bnds = bnds;
     a.lt1 = lt1; a.lt2 = lt2; a.U1 = U1; a.partial = partial; a.tau = tau;
-    a.flags = flags; a.sa = sa; a.sb = sb; a.check_cfl = check;
+    a.flags = flags; a.sa = sa; a.sb = sb; a.check_cfl = adaptive ? 0 : check;
+    a.check_low = adaptive ? 1 : 0;
     a.q = q; a.qcnt = qcnt;
     a.seg = seg; a.mblk = mblk; a.nmem = nmem;
     return a;
@@ -292,12 +296,14 @@ void run_stage(ns_solver *s, int in, int out, double sa, double sb, int check,
   if (s->mixed)
     ns::launch_stage(s->dim, s->gas, s->devgraph32(), s->args32(in, out, sa, sb, check),
                      s->prm.indicator, s->prm.limiter, s->prm.passes, auto_dt,
-                     s->prm.cfl, s->stream, &Profiler::before, &Profiler::after,
+                     s->adaptive ? s->cfl_now : s->prm.cfl, s->stream, &Profiler::before,
+                     &Profiler::after,
                      &s->prof);
   else
     ns::launch_stage(s->dim, s->gas, s->devgraph(), s->args(in, out, sa, sb, check),
                      s->prm.indicator, s->prm.limiter, s->prm.passes, auto_dt,
-                     s->prm.cfl, s->stream, &Profiler::before, &Profiler::after,
+                     s->adaptive ? s->cfl_now : s->prm.cfl, s->stream, &Profiler::before,
+                     &Profiler::after,
                      &s->prof);
 }
 
@@ -1011,6 +1017,29 @@ int ns_step(ns_solver *s, double dt) {
 int ns_step_cfl(ns_solver *s, double *dt) {
   if (!s) return NS_EINVAL;
   return ssprk3(s, 0.0, true, dt);
+}
+
+int ns_step_adaptive(ns_solver *s, double c_start, double *dt, double *c_used) {
+  if (!s) return NS_EINVAL;
+  if (!(c_start > 0.0 && c_start <= 64.0))
+    return s->fail(NS_EINVAL, "c_start must be in (0, 64]");
+  if (!s->has_state) return s->fail(NS_ESTATE, "no state set");
+  double c = c_start;
+  for (int k = 0; k < 24; ++k, c *= 0.5) {
+    s->adaptive = true;
+    s->cfl_now = c;
+    ns::launch_clear_flags(s->flags, s->stream);
+    const int o1 = ssprk3_enqueue(s, 0.0, true);
+    s->adaptive = false;
+    const int rc = read_flags(s);
+    if (rc != NS_OK) return rc;
+    if (s->hflags[1] || s->hflags[3]) continue;  // restart with c / 2
+    s->cur = o1;
+    if (dt) *dt = *s->htau;
+    if (c_used) *c_used = c;
+    return NS_OK;
+  }
+  return s->fail(NS_EBOUNDS, "no CFL number c_start / 2^k, k < 24, kept the states admissible");
 }
 
 int ns_set_viscous(ns_solver *s, const ns_viscous *v) {

@@ -189,3 +189,53 @@ def test_vortex_leaves_through_nonreflecting_faces(vbar):
     assert out["charac"] < 0.25 and out["godunov"] < 0.25
     assert out["godunov"] <= out["charac"] * 1.05
     assert out["slip"] > 1.0
+
+
+def channel_tube(nx=80, ny=9, height=0.02):
+    mesh = W.Mesh(2, (nx, ny), (0, 0), (1.0, height), (False, False))
+    x, _ = mesh.coords()
+    rho = np.where(x < 0.5, 1.0, 0.125)
+    p = np.where(x < 0.5, 1.0, 0.1)
+    return mesh, np.vstack([rho, 0 * rho, 0 * rho, p / (G - 1)])
+
+
+@pytest.mark.parametrize("c_start", [0.5, 3.0, 16.0])
+def test_adaptive_cfl_matches_oracle(c_start):
+    """Adaptive CFL (Remark on high aspect-ratio meshes) on a channel of
+    aspect-ratio-5 cells: the same accepted c, dt and state as the oracle,
+    two steps; transactional when nothing is admissible is not reachable
+    here (c <= 1 always works)."""
+    mesh, U = channel_tube()
+    og = O.Graph(2, mesh.n, mesh.lo, mesh.hi, mesh.periodic)
+    U = og.slip_bc(U)
+    prm = O.params(cfl=0.5)
+    s = abi.Solver(abi.Graph(mesh), cfl=0.5)
+    cur = U
+    for k in range(2):
+        ref, tau, c = og.ssprk3_step_adaptive(prm, cur, c_start)
+        s.set_state(cur, project=False)
+        dt, cg = s.step_adaptive(c_start)
+        say("adaptive", c_start, "step", k, "c", cg, c, "dt", dt, tau)
+        assert cg == c
+        assert dt == pytest.approx(tau, rel=1e-14, abs=0)
+        err = state_rel_err(s.get_state(), ref)
+        assert np.all(err <= TOL), err
+        cur = s.get_state()
+
+
+def test_adaptive_cfl_with_nonreflecting_faces_and_bad_arguments():
+    mesh, U, Uinf = W.nr_vortex_state(24)
+    og = O.Graph(2, mesh.n, mesh.lo, mesh.hi, mesh.periodic)
+    kind = [abi.BC_NONREFLECTING] * 4
+    bnd = O.boundary(kind, O.NR_GODUNOV, [Uinf] * 4)
+    s = abi.Solver(abi.Graph(mesh), cfl=0.5)
+    s.set_boundary(kind, abi.NR_GODUNOV, [Uinf] * 4)
+    s.set_state(U, project=False)
+    ref, tau, c = og.ssprk3_step_adaptive(O.params(cfl=0.5), U, 2.0, bnd)
+    dt, cg = s.step_adaptive(2.0)
+    assert cg == c and dt == pytest.approx(tau, rel=1e-14, abs=0)
+    assert np.all(state_rel_err(s.get_state(), ref) <= TOL)
+    for bad in (0.0, -1.0, 100.0, float("nan")):
+        with pytest.raises(abi.NSError) as ei:
+            s.step_adaptive(bad)
+        assert ei.value.code == abi.NS_EINVAL
