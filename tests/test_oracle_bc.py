@@ -311,3 +311,22 @@ def test_adaptive_cfl_restarts_with_halved_c():
             t, _, dbg = og.fe_stage(q, w2, t2, debug=True)
             bad = not (admissible(dbg["UL"]) and admissible(U / 3.0 + 2.0 / 3.0 * t))
     assert bad
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_two_independent_exact_riemann_solvers_agree(seed):
+    """The C solver (bisection) against the Python one (safeguarded Newton,
+    oracle/riemann_exact.py): star state and samples across the fan."""
+    from oracle import riemann_exact as R
+    rng = np.random.default_rng(50 + seed)
+    left, right = random_side(rng), random_side(rng)
+    c = O.riemann_star(G, left, right)
+    if c is None:
+        return
+    ps, us = R.star_state(*left, *right, g=G)[:2]
+    assert c[0] == pytest.approx(ps, rel=1e-12)
+    assert c[1] == pytest.approx(us, abs=1e-12 * (1 + abs(us)))
+    for xi in np.linspace(-4, 4, 17):
+        a = O.riemann_sample(G, left, right, xi)[:3]
+        b = [float(np.ravel(v)[0]) for v in R.sample(*left, *right, xi, g=G)[:3]]
+        assert np.allclose(a, b, rtol=1e-11, atol=1e-13), (xi, a, b)
