@@ -198,7 +198,14 @@ typedef struct ns_viscous {
   int fct;         /* NS_FCT_AUTO: limit the internal energy only when the
                       Crank-Nicolson value is not positive somewhere;
                       NS_FCT_ALWAYS: always (tests)                         */
+  int precond;     /* NS_PC_JACOBI: diagonal preconditioner;
+                      NS_PC_GMG: geometric multigrid V-cycle in FP32 with a
+                      Chebyshev(3)-Jacobi smoother (the viscous-dominated
+                      regime); coarse levels halve the cells of every
+                      direction (rounded up; non-nested interpolation) down
+                      to about 512 nodes                                    */
 } ns_viscous;
+enum { NS_PC_JACOBI = 0, NS_PC_GMG = 1 };
 
 /* Enables the parabolic step: validates the data, builds the Q1 element
  * matrices of the stress and heat operators and allocates the CG vectors

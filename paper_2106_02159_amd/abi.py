@@ -197,7 +197,10 @@ class Graph:
 class Viscous(C.Structure):
     _fields_ = [("mu", C.c_double), ("lam", C.c_double), ("kappa", C.c_double),
                 ("cv", C.c_double), ("cg_rtol", C.c_double), ("cg_maxit", C.c_int),
-                ("fct", C.c_int)]
+                ("fct", C.c_int), ("precond", C.c_int)]
+
+
+PC_JACOBI, PC_GMG = 0, 1
 
 
 class ParInfo(C.Structure):
@@ -437,8 +440,8 @@ class Solver:
 
     # -- parabolic sub-step and Strang composition --------------------------
     def set_viscous(self, mu=1e-4, lam=0.0, kappa=1.4e-4, cv=2.5, cg_rtol=1e-10,
-                    cg_maxit=500, fct=FCT_AUTO):
-        self.vprm = Viscous(mu, lam, kappa, cv, cg_rtol, cg_maxit, fct)
+                    cg_maxit=500, fct=FCT_AUTO, precond=PC_JACOBI):
+        self.vprm = Viscous(mu, lam, kappa, cv, cg_rtol, cg_maxit, fct, precond)
         self._check(lib().ns_set_viscous(self.h, C.byref(self.vprm)))
 
     def step_parabolic(self, dt: float):

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libns.so")
 
 SOURCES = ["graph.cpp", "element.cpp", "serve.cpp", "hyp_kernels.hip", "bc_kernels.hip",
-           "par_kernels.hip", "ns_api.hip"]
+           "par_kernels.hip", "mg_kernels.hip", "ns_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are switched off for all device code.

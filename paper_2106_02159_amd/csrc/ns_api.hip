@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -142,6 +143,10 @@ struct ns_solver {
   // non-reflecting nodes (ns_set_boundary): index, unit normal (dim x nnr),
   // far-field state (nc x nnr), method
   int nnr = 0, nr_method = 0;
+  // multigrid preconditioner of the parabolic CG (NS_PC_GMG): levels on the
+  // device (their buffers), z vector of the CG
+  std::vector<ns::MGLevel> mgl;
+  double *mg_z = nullptr;
   // adaptive CFL step in progress: CFL number of its time step, U^L checks
   bool adaptive = false;
   double cfl_now = 0.0;
@@ -373,14 +378,26 @@ ns::ParGrid par_grid(const ns_solver *s) {
 // with one status readback per batch.
 int run_cg(ns_solver *s, int ncomp, double cdt, const char *label, int *iters) {
   const ns::ParGrid g = par_grid(s);
+  const bool mg = s->vprm.precond == NS_PC_GMG && !s->mgl.empty();
+  const int nlev = (int)s->mgl.size(), deg = 3, cdeg = 12;
   Profiler::before(&s->prof, label);
-  ns::par_cg_start(s->dim, ncomp, g, s->pb, cdt, s->vprm.cg_rtol, s->vprm.cg_maxit,
-                   s->stream);
+  if (mg) {
+    ns::mg_setup(s->dim, ncomp, s->mgl.data(), nlev, s->pb.rm, cdt, s->stream);
+    ns::par_cg_start_mg(s->dim, ncomp, g, s->pb, s->mg_z, cdt, s->vprm.cg_rtol,
+                        s->vprm.cg_maxit, s->mgl.data(), nlev, deg, cdeg, s->stream);
+  } else {
+    ns::par_cg_start(s->dim, ncomp, g, s->pb, cdt, s->vprm.cg_rtol, s->vprm.cg_maxit,
+                     s->stream);
+  }
   Profiler::after(&s->prof);
   int launched = 0, batch = 2;
   for (;;) {
     Profiler::before(&s->prof, label);
-    ns::par_cg_iterate(s->dim, ncomp, g, s->pb, cdt, batch, s->stream);
+    if (mg)
+      ns::par_cg_iterate_mg(s->dim, ncomp, g, s->pb, s->mg_z, cdt, batch, s->mgl.data(), nlev,
+                            deg, cdeg, s->stream);
+    else
+      ns::par_cg_iterate(s->dim, ncomp, g, s->pb, cdt, batch, s->stream);
     Profiler::after(&s->prof);
     launched += batch;
     hipError_t e = hipMemcpyAsync(s->hcg, s->pb.cg, sizeof(ns::CGState),
@@ -1042,6 +1059,74 @@ int ns_step_adaptive(ns_solver *s, double c_start, double *dt, double *c_used) {
   return s->fail(NS_EBOUNDS, "no CFL number c_start / 2^k, k < 24, kept the states admissible");
 }
 
+namespace {
+// Multigrid levels (NS_PC_GMG): level 0 is the solver's mesh; a direction is
+// coarsened while it has at least 4 cells (8 nodes if periodic), to
+// ceil(cells/2) cells; stop at about 512 nodes or when nothing coarsens.
+// The level structure is built (and its buffers allocated) once; the element
+// tables, which depend on the viscous data, on every call.
+int mg_build(ns_solver *s, const ns_viscous *v) {
+  const int dim = s->dim;
+  std::vector<ns::ParGrid> grids{par_grid(s)};
+  std::vector<std::array<double, 3>> hs{{s->mg.h[0], s->mg.h[1], s->mg.h[2]}};
+  while (grids.size() < 16 && grids.back().N > 512) {
+    ns::ParGrid g = grids.back();
+    std::array<double, 3> h = hs.back();
+    bool any = false;
+    for (int d = 0; d < dim; ++d) {
+      const int64_t n = g.n[d], cells = g.per[d] ? n : n - 1;
+      if (g.per[d] ? n < 8 : cells < 4) continue;
+      const int64_t cc = (cells + 1) / 2;
+      h[d] *= (double)cells / (double)cc;
+      g.n[d] = g.per[d] ? cc : cc + 1;
+      any = true;
+    }
+    if (!any) break;
+    g.N = g.n[0] * g.n[1] * g.n[2];
+    grids.push_back(g);
+    hs.push_back(h);
+  }
+  const int nlev = (int)grids.size();
+  hipError_t e = hipSuccess;
+  if (s->mgl.empty()) {
+    s->mgl.resize(nlev);
+    for (int l = 0; l < nlev && e == hipSuccess; ++l) {
+      ns::MGLevel &L = s->mgl[l];
+      L.G = grids[l];
+      const int64_t N = L.G.N, dN = (int64_t)dim * N;
+      const int64_t nb = (N + ns::kParBlock - 1) / ns::kParBlock;
+      float *tab = nullptr;
+      ns::Q1Tables t;
+      ns::build_q1_tables(dim, hs[l].data(), 1.0, 0.0, 1.0, &t);
+      if (e == hipSuccess) e = s->alloc(&tab, t.packed().size());
+      L.tab = tab;
+      if (e == hipSuccess) e = s->alloc(&L.rm, N);
+      for (float **pv : {&L.diag, &L.x, &L.y, &L.b, &L.d})
+        if (e == hipSuccess) e = s->alloc(pv, dN);
+      if (e == hipSuccess) e = s->alloc(&L.lmax, 1);
+      if (e == hipSuccess) e = s->alloc(&L.gpart, nb);
+    }
+    if (e == hipSuccess) e = s->alloc(&s->mg_z, (size_t)dim * s->N);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      s->mgl.clear();
+      return s->fail(NS_ENOMEM, "multigrid levels");
+    }
+  }
+  e = hipStreamSynchronize(s->stream);
+  for (int l = 0; l < (int)s->mgl.size() && e == hipSuccess; ++l) {
+    ns::Q1Tables t;
+    ns::build_q1_tables(dim, hs[l].data(), v->mu, v->lambda, v->kappa / v->cv, &t);
+    const std::vector<double> td = t.packed();
+    const std::vector<float> tf(td.begin(), td.end());
+    e = hipMemcpy(const_cast<float *>(s->mgl[l].tab), tf.data(), tf.size() * sizeof(float),
+                  hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return s->hipfail(e, "multigrid tables");
+  return NS_OK;
+}
+}  // namespace
+
 int ns_set_viscous(ns_solver *s, const ns_viscous *v) {
   if (!s || !v) return NS_EINVAL;
   const double vals[] = {v->mu, v->lambda, v->kappa, v->cv, v->cg_rtol};
@@ -1049,9 +1134,11 @@ int ns_set_viscous(ns_solver *s, const ns_viscous *v) {
     if (!std::isfinite(x)) return s->fail(NS_EINVAL, "viscous data must be finite");
   if (!(v->mu >= 0.0) || !(v->lambda >= 0.0) || !(v->kappa >= 0.0) || !(v->cv > 0.0) ||
       !(v->cg_rtol > 0.0 && v->cg_rtol < 1.0) || v->cg_maxit < 1 ||
-      (v->fct != NS_FCT_AUTO && v->fct != NS_FCT_ALWAYS))
+      (v->fct != NS_FCT_AUTO && v->fct != NS_FCT_ALWAYS) ||
+      (v->precond != NS_PC_JACOBI && v->precond != NS_PC_GMG))
     return s->fail(NS_EINVAL, "viscous data out of range (need mu, lambda, kappa >= 0, "
-                              "cv > 0, 0 < cg_rtol < 1, cg_maxit >= 1, fct 0 or 1)");
+                              "cv > 0, 0 < cg_rtol < 1, cg_maxit >= 1, fct 0 or 1, "
+                              "precond 0 or 1)");
   ns::Q1Tables t;
   ns::build_q1_tables(s->dim, s->mg.h, v->mu, v->lambda, v->kappa / v->cv, &t);
   const std::vector<double> tab = t.packed();
@@ -1085,6 +1172,10 @@ int ns_set_viscous(ns_solver *s, const ns_viscous *v) {
   if (e == hipSuccess)
     e = hipMemcpy(s->ptab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice);
   if (e != hipSuccess) return s->hipfail(e, "element table upload");
+  if (v->precond == NS_PC_GMG) {
+    const int rc = mg_build(s, v);
+    if (rc != NS_OK) return rc;
+  }
   s->vprm = *v;
   s->viscous = true;
   return NS_OK;

@@ -3,147 +3,12 @@
 
 #include <cmath>
 
+#include "par_ops.hpp"
+
 namespace ns {
 
 namespace {
-
-template <int DIM> struct P {
-  static constexpr int S = DIM == 2 ? 9 : 27;  // neighbourhood slots
-  static constexpr int L = 1 << DIM;           // nodes per cell
-  static constexpr int C = S / 2;              // slot of the node itself
-};
-
-__device__ __forceinline__ void decode(const ParGrid &G, int64_t i, int64_t c[3]) {
-  c[0] = i % G.n[0];
-  const int64_t t = i / G.n[0];
-  c[1] = t % G.n[1];
-  c[2] = t / G.n[1];
-}
-
-// node at offset (slot s: o_d = (s / 3^d) % 3 - 1) from c, or -1 outside a
-// wall-bounded direction
-template <int DIM>
-__device__ __forceinline__ int64_t nb_index(const ParGrid &G, const int64_t c[3],
-                                            int s) {
-  int64_t idx = 0, stride = 1;
-  int m = 1;
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    int64_t a = c[d] + (s / m) % 3 - 1;
-    m *= 3;
-    if (G.per[d]) {
-      a = a < 0 ? a + G.n[d] : (a >= G.n[d] ? a - G.n[d] : a);
-    } else if (a < 0 || a >= G.n[d]) {
-      return -1;
-    }
-    idx += a * stride;
-    stride *= G.n[d];
-  }
-  return idx;
-}
-
-// does the cell in which node c is local node a exist?
-template <int DIM>
-__device__ __forceinline__ bool cell_exists(const ParGrid &G, const int64_t c[3],
-                                            int a) {
-  bool ok = true;
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    const int64_t lo = c[d] - ((a >> d) & 1);
-    if (!G.per[d] && (lo < 0 || lo > G.n[d] - 2)) ok = false;
-  }
-  return ok;
-}
-
-// neighbourhood slot of local node b of the cell in which the centre is a
-template <int DIM>
-__host__ __device__ constexpr int slot_of(int a, int b) {
-  int s = 0, m = 1;
-  for (int d = 0; d < DIM; ++d) {
-    s += (((b >> d) & 1) - ((a >> d) & 1) + 1) * m;
-    m *= 3;
-  }
-  return s;
-}
-
-// offsets into the element table (element.hpp, Q1Tables::packed)
-template <int DIM> struct TabOff {
-  static constexpr int L = 1 << DIM, S = DIM == 2 ? 9 : 27;
-  static constexpr int heat = DIM * DIM * L * L;
-  static constexpr int phi = heat + L * L;
-  static constexpr int dphi = phi + L * L;
-  static constexpr int w = dphi + L * L * DIM;
-  static constexpr int sst = w + 1;
-  static constexpr int sht = sst + S * DIM * DIM;
-};
-
-// all 2^dim cells of the node exist (no wall face through it)
-template <int DIM>
-__device__ __forceinline__ bool interior(const ParGrid &G, const int64_t c[3]) {
-  bool in = true;
-#pragma unroll
-  for (int d = 0; d < DIM; ++d)
-    if (!G.per[d] && (c[d] == 0 || c[d] == G.n[d] - 1)) in = false;
-  return in;
-}
-
-// acc_k = (operator row of the node applied to x), without the mass term:
-// at interior nodes by the pre-summed 3^dim-point stencil, at wall nodes
-// cell by cell with the element matrix (NC = dim: stress, NC = 1: heat)
-template <int DIM, int NC>
-__device__ __forceinline__ void op_apply(const ParGrid &G, const double *__restrict__ tab,
-                                         const double *__restrict__ x,
-                                         const int64_t c[3], double (&acc)[NC]) {
-  using T = TabOff<DIM>;
-  constexpr int L = T::L, S = T::S;
-  const int64_t N = G.N;
-#pragma unroll
-  for (int k = 0; k < NC; ++k) acc[k] = 0.0;
-  if (interior<DIM>(G, c)) {
-    const double *__restrict__ st = tab + (NC > 1 ? T::sst : T::sht);
-    // a plane of 3^(dim-1) neighbours at a time (all 27 gathers of the 3D
-    // stencil in flight at once would cut the occupancy to 2 waves)
-#pragma unroll 9
-    for (int s = 0; s < S; ++s) {
-      const int64_t j = nb_index<DIM>(G, c, s);
-      double xj[NC];
-#pragma unroll
-      for (int l = 0; l < NC; ++l) xj[l] = x[l * N + j];
-#pragma unroll
-      for (int k = 0; k < NC; ++k)
-#pragma unroll
-        for (int l = 0; l < NC; ++l) acc[k] += st[(s * NC + k) * NC + l] * xj[l];
-    }
-  } else {
-    const double *__restrict__ E = tab + (NC > 1 ? 0 : T::heat);
-    for (int a = 0; a < L; ++a) {
-      if (!cell_exists<DIM>(G, c, a)) continue;
-      for (int b = 0; b < L; ++b) {
-        const int64_t j = nb_index<DIM>(G, c, slot_of<DIM>(a, b));
-        double xj[NC];
-#pragma unroll
-        for (int l = 0; l < NC; ++l) xj[l] = x[l * N + j];
-#pragma unroll
-        for (int k = 0; k < NC; ++k)
-#pragma unroll
-          for (int l = 0; l < NC; ++l)
-            acc[k] += E[((k * NC + l) * L + a) * L + b] * xj[l];
-      }
-    }
-  }
-}
-
-// diagonal entry E^kk_aa summed over the node's cells
-template <int DIM, int NC>
-__device__ __forceinline__ double op_diag(const ParGrid &G, const double *__restrict__ E,
-                                          const int64_t c[3], int k) {
-  constexpr int L = P<DIM>::L;
-  double d = 0.0;
-#pragma unroll
-  for (int a = 0; a < L; ++a)
-    if (cell_exists<DIM>(G, c, a)) d += E[((k * NC + k) * L + a) * L + a];
-  return d;
-}
+using namespace pops;
 
 // deterministic block sum of K values into partial[k * gridDim.x + block]
 template <int K>
@@ -293,6 +158,101 @@ __global__ __launch_bounds__(kParBlock) void k_cg_direction(ParGrid G, ParBufs B
   for (int k = 0; k < NC; ++k) {
     const int64_t t = k * N + i;
     B.p[t] = B.r[t] / B.diag[t] + beta * B.p[t];
+  }
+}
+
+// ---- CG with an external preconditioner (z = M^-1 r in a separate vector)
+// r = b - A x
+template <int DIM, int NC>
+__global__ __launch_bounds__(kParBlock) void k_cg_residual(ParGrid G, ParBufs B, double cdt) {
+  constexpr bool VEL = NC > 1;
+  const int64_t i = gid();
+  const int64_t N = G.N;
+  if (i >= N) return;
+  int64_t c[3];
+  decode(G, i, c);
+  double acc[NC];
+  op_apply<DIM, NC>(G, B.tab, B.x, c, acc);
+  const bool fx = VEL && B.fixed[i] != 0;
+  const double rm = B.rm[i];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const double xi = B.x[k * N + i];
+    const double y = fx ? xi : rm * xi + cdt * acc[k];
+    B.r[k * N + i] = B.b[k * N + i] - y;
+  }
+}
+
+// p = z; partial r.z, r.r, b.b
+template <int NC>
+__global__ __launch_bounds__(kParBlock) void k_cg_first(ParGrid G, ParBufs B,
+                                                        const double *__restrict__ z) {
+  const int64_t i = gid();
+  const int64_t N = G.N;
+  double sums[3] = {0.0, 0.0, 0.0};
+  if (i < N) {
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const int64_t t = k * N + i;
+      const double r = B.r[t], bi = B.b[t];
+      B.p[t] = z[t];
+      sums[0] += r * z[t];
+      sums[1] += r * r;
+      sums[2] += bi * bi;
+    }
+  }
+  block_sum<3>(sums, B.partial);
+}
+
+// x += alpha p, r -= alpha q
+template <int NC>
+__global__ __launch_bounds__(kParBlock) void k_cg_update_xr(ParGrid G, ParBufs B) {
+  if (B.cg->done) return;
+  const int64_t i = gid();
+  const int64_t N = G.N;
+  if (i >= N) return;
+  const double alpha = B.cg->alpha;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const int64_t t = k * N + i;
+    B.x[t] += alpha * B.p[t];
+    B.r[t] -= alpha * B.q[t];
+  }
+}
+
+// partial r.r, r.z
+template <int NC>
+__global__ __launch_bounds__(kParBlock) void k_cg_sums_rz(ParGrid G, ParBufs B,
+                                                          const double *__restrict__ z) {
+  if (B.cg->done) return;
+  const int64_t i = gid();
+  const int64_t N = G.N;
+  double sums[2] = {0.0, 0.0};
+  if (i < N) {
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const int64_t t = k * N + i;
+      const double r = B.r[t];
+      sums[0] += r * r;
+      sums[1] += r * z[t];
+    }
+  }
+  block_sum<2>(sums, B.partial);
+}
+
+// p = z + beta p
+template <int NC>
+__global__ __launch_bounds__(kParBlock) void k_cg_direction_z(ParGrid G, ParBufs B,
+                                                              const double *__restrict__ z) {
+  if (B.cg->done) return;
+  const int64_t i = gid();
+  const int64_t N = G.N;
+  if (i >= N) return;
+  const double beta = B.cg->beta;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const int64_t t = k * N + i;
+    B.p[t] = z[t] + beta * B.p[t];
   }
 }
 
@@ -636,7 +596,58 @@ void cg_iterate(const ParGrid &g, const ParBufs &B, double cdt, int iters,
     hipLaunchKernelGGL(k_cg_direction<NC>, grid, blk, 0, s, g, B);
   }
 }
+template <int DIM, int NC>
+void cg_start_mg(const ParGrid &g, const ParBufs &B, double *z, double cdt, double rtol,
+                 int maxit, const MGLevel *lv, int nlev, int deg, int cdeg, hipStream_t s) {
+  const dim3 grid = grid_of(g.N), blk(kParBlock);
+  hipLaunchKernelGGL((k_cg_residual<DIM, NC>), grid, blk, 0, s, g, B, cdt);
+  mg_vcycle(DIM, NC, lv, nlev, B.r, z, cdt, nullptr, deg, cdeg, s);
+  hipLaunchKernelGGL(k_cg_first<NC>, grid, blk, 0, s, g, B, (const double *)z);
+  hipLaunchKernelGGL(k_cg_scalars<0>, dim3(1), blk, 0, s, B.partial, (int)grid.x,
+                     B.cg, rtol * rtol, maxit);
+}
+
+template <int DIM, int NC>
+void cg_iterate_mg(const ParGrid &g, const ParBufs &B, double *z, double cdt, int iters,
+                   const MGLevel *lv, int nlev, int deg, int cdeg, hipStream_t s) {
+  const dim3 grid = grid_of(g.N), blk(kParBlock);
+  for (int it = 0; it < iters; ++it) {
+    hipLaunchKernelGGL((k_cg_apply<DIM, NC>), grid, blk, 0, s, g, B, cdt);
+    hipLaunchKernelGGL(k_cg_scalars<1>, dim3(1), blk, 0, s, B.partial, (int)grid.x,
+                       B.cg, 0.0, 0);
+    hipLaunchKernelGGL(k_cg_update_xr<NC>, grid, blk, 0, s, g, B);
+    mg_vcycle(DIM, NC, lv, nlev, B.r, z, cdt, B.cg, deg, cdeg, s);
+    hipLaunchKernelGGL(k_cg_sums_rz<NC>, grid, blk, 0, s, g, B, (const double *)z);
+    hipLaunchKernelGGL(k_cg_scalars<2>, dim3(1), blk, 0, s, B.partial, (int)grid.x,
+                       B.cg, 0.0, 0);
+    hipLaunchKernelGGL(k_cg_direction_z<NC>, grid, blk, 0, s, g, B, (const double *)z);
+  }
+}
 }  // namespace
+
+void par_cg_start_mg(int dim, int ncomp, const ParGrid &g, const ParBufs &B, double *zb,
+                     double cdt, double rtol, int maxit, const MGLevel *lv, int nlev,
+                     int deg, int coarse_deg, hipStream_t s) {
+  if (dim == 2) {
+    if (ncomp == 2) cg_start_mg<2, 2>(g, B, zb, cdt, rtol, maxit, lv, nlev, deg, coarse_deg, s);
+    else cg_start_mg<2, 1>(g, B, zb, cdt, rtol, maxit, lv, nlev, deg, coarse_deg, s);
+  } else {
+    if (ncomp == 3) cg_start_mg<3, 3>(g, B, zb, cdt, rtol, maxit, lv, nlev, deg, coarse_deg, s);
+    else cg_start_mg<3, 1>(g, B, zb, cdt, rtol, maxit, lv, nlev, deg, coarse_deg, s);
+  }
+}
+
+void par_cg_iterate_mg(int dim, int ncomp, const ParGrid &g, const ParBufs &B, double *zb,
+                       double cdt, int iters, const MGLevel *lv, int nlev, int deg,
+                       int coarse_deg, hipStream_t s) {
+  if (dim == 2) {
+    if (ncomp == 2) cg_iterate_mg<2, 2>(g, B, zb, cdt, iters, lv, nlev, deg, coarse_deg, s);
+    else cg_iterate_mg<2, 1>(g, B, zb, cdt, iters, lv, nlev, deg, coarse_deg, s);
+  } else {
+    if (ncomp == 3) cg_iterate_mg<3, 3>(g, B, zb, cdt, iters, lv, nlev, deg, coarse_deg, s);
+    else cg_iterate_mg<3, 1>(g, B, zb, cdt, iters, lv, nlev, deg, coarse_deg, s);
+  }
+}
 
 void par_cg_start(int dim, int ncomp, const ParGrid &g, const ParBufs &B,
                   double cdt, double rtol, int maxit, hipStream_t s) {

@@ -36,6 +36,35 @@ struct CGState {
   int done, it, maxit, pad;
 };
 
+// One level of the geometric multigrid preconditioner (FP32 V-cycle,
+// mg_kernels.hip).  Level 0 is the mesh of the solver; level l+1 halves the
+// cells of every direction (rounded up), so coarse grids need not nest: the
+// prolongation interpolates the coarse Q1 function at the fine nodes (two
+// weights per direction), the restriction is its exact transpose.  The
+// operator of a level is rediscretised on its own mesh size; its mass-term
+// coefficient rho m is restricted from the finer level (the restriction of
+// the lumped masses of Q1 is the coarse lumped mass).
+struct MGLevel {
+  ParGrid G;
+  const float *tab;  // element tables at this level's mesh size
+  float *rm;         // N: rho m
+  float *diag;       // NC*N: diagonal of the level operator
+  float *x, *y;      // NC*N: iterate (two buffers, the smoother alternates)
+  float *b, *d;      // NC*N: right-hand side, Chebyshev direction
+  float *lmax;       // 1: Gershgorin bound of the spectrum of D^-1 A
+  float *gpart;      // block maxima for lmax
+};
+
+// Coefficients and spectral bounds of all levels for one system: rho m from
+// the fine rm (FP64), diagonals, lmax; ncomp = dim (velocity, no-slip rows
+// fixed) or 1 (energy).
+void mg_setup(int dim, int ncomp, MGLevel *lv, int nlev, const double *rm, double cdt,
+              hipStream_t s);
+// z = V-cycle(r) (Chebyshev(deg)-Jacobi pre- and post-smoothing, coarsest
+// level smoothed `coarse_deg` times from zero); no-op once st->done.
+void mg_vcycle(int dim, int ncomp, const MGLevel *lv, int nlev, const double *r, double *z,
+               double cdt, const CGState *st, int deg, int coarse_deg, hipStream_t s);
+
 struct ParBufs {
   const double *tab;    // element tables (Q1Tables::packed)
   const double *mi;     // N lumped masses
@@ -64,6 +93,13 @@ void par_cg_start(int dim, int ncomp, const ParGrid &g, const ParBufs &B,
                   double cdt, double rtol, int maxit, hipStream_t s);
 void par_cg_iterate(int dim, int ncomp, const ParGrid &g, const ParBufs &B,
                     double cdt, int iters, hipStream_t s);
+// The same with the multigrid preconditioner (z in B.q's sibling buffer zb).
+void par_cg_start_mg(int dim, int ncomp, const ParGrid &g, const ParBufs &B, double *zb,
+                     double cdt, double rtol, int maxit, const MGLevel *lv, int nlev,
+                     int deg, int coarse_deg, hipStream_t s);
+void par_cg_iterate_mg(int dim, int ncomp, const ParGrid &g, const ParBufs &B, double *zb,
+                       double cdt, int iters, const MGLevel *lv, int nlev, int deg,
+                       int coarse_deg, hipStream_t s);
 // V^{n+1} = 2 V^{1/2} - V^n (0 at no-slip nodes) into Vn and out (momentum
 // rows), K_i from V^{1/2} (x); then the energy system: RHS rho m e^n +
 // ksrc m K, start e^n, diagonal rho m + cdt b_ii

@@ -48,11 +48,11 @@ def case(request):
     return request.param, mesh, og, abi.Graph(mesh), U
 
 
-def gpu_solver(g, U, fct=abi.FCT_AUTO, rtol=1e-13, maxit=2000, **kw):
+def gpu_solver(g, U, fct=abi.FCT_AUTO, rtol=1e-13, maxit=2000, precond=abi.PC_JACOBI, **kw):
     s = abi.Solver(g)
     s.set_state(U, project=False)
     v = dict(VISC, **kw)
-    s.set_viscous(cg_rtol=rtol, cg_maxit=maxit, fct=fct, **v)
+    s.set_viscous(cg_rtol=rtol, cg_maxit=maxit, fct=fct, precond=precond, **v)
     return s
 
 
@@ -217,3 +217,64 @@ def test_strang_equals_its_parts():
     b.step_parabolic(2.0 * tau)
     b.step(tau)
     assert np.array_equal(a.get_state(), b.get_state())
+
+
+@pytest.mark.parametrize("fct", [0, 1])
+def test_parabolic_step_multigrid(case, fct):
+    """The multigrid-preconditioned CG (FP32 V-cycle) reaches the same
+    solution: parity with the oracle's Jacobi CG at rtol 1e-13 on both sides."""
+    name, mesh, og, g, U = case
+    say("parabolic gmg", name, "fct", fct)
+    dt = 20.0 * og.compute_dt(O.params(), U)
+    ref, st, oi = og.parabolic_step(oracle_visc(fct=fct), U, dt)
+    assert st == 0
+    s = gpu_solver(g, U, fct=fct, precond=abi.PC_GMG)
+    s.step_parabolic(dt)
+    gi = s.parabolic_info()
+    assert gi.fct == oi.fct
+    err = state_rel_err(s.get_state(), ref, scale=state_scale(ref))
+    say("  err", err.max(), "iters gmg", gi.it_v, gi.it_e, "jacobi (oracle)", oi.it_v, oi.it_e)
+    assert err.max() <= TOL, err
+
+
+def test_strang_step_multigrid():
+    mesh, U = W.shock_tube_state(17, seed=4)
+    og = O.Graph(3, mesh.n, mesh.lo, mesh.hi, mesh.periodic)
+    U = og.slip_bc(U)
+    prm = O.params()
+    tau = og.compute_dt(prm, U)
+    ref, st, oi = og.strang_step(prm, oracle_visc(), U, tau)
+    assert st == 0
+    s = gpu_solver(abi.Graph(mesh), U, precond=abi.PC_GMG)
+    s.step_strang(tau)
+    assert state_rel_err(s.get_state(), ref, scale=state_scale(ref)).max() <= TOL
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_multigrid_in_the_viscous_dominated_regime(dim):
+    """mu = kappa = 1 and a step 50 times the hyperbolic one: the diagonal
+    preconditioner needs many iterations, growing with refinement; the
+    V-cycle needs few, nearly independent of the mesh; both reach the same
+    solution to the solver tolerance."""
+    sizes = (33, 65, 129) if dim == 2 else (17, 33)
+    its = {}
+    for n in sizes:
+        mesh, U = W.four_quadrant_state(n, seed=5) if dim == 2 else W.shock_tube_state(n, seed=5)
+        og = O.Graph(dim, mesh.n, mesh.lo, mesh.hi, mesh.periodic)
+        U = og.slip_bc(U)
+        dt = 50.0 * og.compute_dt(O.params(), U)
+        g = abi.Graph(mesh)
+        out = {}
+        for pc in (abi.PC_JACOBI, abi.PC_GMG):
+            s = gpu_solver(g, U, rtol=1e-10, maxit=20000, precond=pc, mu=1.0, lam=0.5,
+                           kappa=1.0)
+            s.step_parabolic(dt)
+            out[pc] = (s.get_state(), s.parabolic_info())
+        ij, ig = out[abi.PC_JACOBI][1], out[abi.PC_GMG][1]
+        its[n] = (ij.it_v, ij.it_e, ig.it_v, ig.it_e)
+        say("viscous-dominated", dim, n, "jacobi v/e", ij.it_v, ij.it_e, "gmg v/e", ig.it_v, ig.it_e)
+        a, b = out[abi.PC_JACOBI][0], out[abi.PC_GMG][0]
+        assert state_rel_err(b, a, scale=state_scale(a)).max() <= 1e-8
+        assert ig.it_v * 3 <= ij.it_v and ig.it_e * 3 <= ij.it_e
+    first, last = its[sizes[0]], its[sizes[-1]]
+    assert last[2] <= 1.6 * first[2] + 2 and last[3] <= 1.6 * first[3] + 2
