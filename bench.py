@@ -112,7 +112,7 @@ def workload(dim: int, n: int, seed: int):
 
 
 def cpu_baseline(dim: int, n_sample: int, seed: int, ns: bool = False,
-                 min_s: float = 10.0, max_steps: int = 16):
+                 min_s: float = 10.0, max_steps: int = 16, mu: float = 1e-4):
     """The oracle, as it stands, stepping the same workload at n_sample
     nodes per direction: SSPRK(3,3) steps (Strang steps with `ns`), each with
     its CFL time step, until at least min_s seconds have passed (at most
@@ -122,7 +122,7 @@ def cpu_baseline(dim: int, n_sample: int, seed: int, ns: bool = False,
     mesh, U = workload(dim, n_sample, seed)
     og = O.Graph(dim, mesh.n, mesh.lo, mesh.hi, mesh.periodic, export=False)
     prm = O.params(cfl=0.5)
-    visc = O.visc(mu=1e-4, lam=0.0, kappa=1.4e-4, cv=2.5, cg_rtol=1e-10)
+    visc = O.visc(mu=mu, lam=0.0, kappa=1.4 * mu, cv=2.5, cg_rtol=1e-10, cg_maxit=20000)
     U = og.slip_bc(U)
     steps = 0
     t0 = time.perf_counter()
@@ -244,6 +244,11 @@ def main():
                     help="Navier-Stokes: Strang steps (hyperbolic tau, parabolic "
                          "2 tau, hyperbolic tau) with mu = 1e-4, lambda = 0, "
                          "kappa = 1.4e-4, cv = 1/(gamma-1), CG rtol 1e-10")
+    ap.add_argument("--mu", type=float, default=1e-4,
+                    help="Navier-Stokes: shear viscosity (kappa = 1.4 mu)")
+    ap.add_argument("--precond", choices=("jacobi", "gmg"), default="jacobi",
+                    help="Navier-Stokes: preconditioner of the parabolic CG (gmg: "
+                         "FP32 multigrid V-cycle, for the viscous-dominated regime)")
     ap.add_argument("--mixed", action="store_true",
                     help="mixed precision: FP32 storage of the graph coefficients "
                          "and of alpha, d_ij, F^H and the limiter coefficients, "
@@ -296,7 +301,9 @@ def main():
     solver.set_state(U)
     del U
     if args.ns:
-        solver.set_viscous(mu=1e-4, lam=0.0, kappa=1.4e-4, cv=1.0 / 0.4, cg_rtol=1e-10)
+        solver.set_viscous(mu=args.mu, lam=0.0, kappa=1.4 * args.mu, cv=1.0 / 0.4,
+                           cg_rtol=1e-10, cg_maxit=20000,
+                           precond=abi.PC_GMG if args.precond == "gmg" else abi.PC_JACOBI)
         advance = solver.step_strang_cfl
     else:
         advance = solver.step_cfl
@@ -361,10 +368,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": (
                        f"3D Navier-Stokes gamma=1.4, Q1 {n}^3 nodes on [0,1]^3, "
-                       f"mu=1e-4, lambda=0, kappa=1.4e-4, cv=2.5, Mach-3 shock tube "
-                       f"with seeded 1% density noise (seed {args.seed}); Strang step "
-                       f"= SSPRK3(tau) + parabolic CN/CG(2 tau, Jacobi, rtol 1e-10; "
-                       f"no-slip, insulated walls) + SSPRK3(tau), CFL 0.5"
+                       f"mu={args.mu:g}, lambda=0, kappa={1.4 * args.mu:g}, cv=2.5, "
+                       f"Mach-3 shock tube with seeded 1% density noise (seed "
+                       f"{args.seed}); Strang step = SSPRK3(tau) + parabolic CN/CG(2 tau, "
+                       f"{'multigrid V-cycle (FP32, Chebyshev(3)-Jacobi)' if args.precond == 'gmg' else 'Jacobi'}, "
+                       f"rtol 1e-10; no-slip, insulated walls) + SSPRK3(tau), CFL 0.5"
                        if args.ns else
                        f"2D Euler gamma=1.4, Q1 {n}x{n} nodes on [0,1]^2, "
                        f"reflecting walls, seeded four-quadrant Riemann data "
@@ -417,7 +425,7 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(
             dim, args.cpu_sample or (1024 if dim == 2 else (64 if args.ns else 96)),
-            args.seed, ns=args.ns)
+            args.seed, ns=args.ns, mu=args.mu)
     print(json.dumps(out), flush=True)
 
 
