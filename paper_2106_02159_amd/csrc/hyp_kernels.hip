@@ -34,6 +34,10 @@ template <int DIM> struct Aux {
 #ifndef NS_CH_FIN
 #define NS_CH_FIN 1
 #endif
+// 2D pass-2 search: off-diagonal P_ij kept in LDS instead of registers
+#ifndef NS_LIM2_LDS
+#define NS_LIM2_LDS 5
+#endif
 template <int DIM, int CHUNK = 9> struct Cfg {
   static constexpr int NC = DIM + 2;
   static constexpr int W = DIM == 2 ? 9 : 27;
@@ -675,8 +679,13 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraphT<LT> G, StageArgsT<LT>
   const double lam = 1.0 / G.lfac[i];
   double u1[NC];
   load_state<NC>(A.UL, N, i, u1);
-  // 2D: the row's P_ij and l_ij stay in registers for the pass-2 search
+  // 2D: the row's P_ij and l_ij stay for the pass-2 search: the P of the
+  // first NS_LIM2_LDS off-diagonal slots in the lane's own LDS words (no
+  // sharing between lanes, so no barrier), the rest in registers
   constexpr bool CACHE = DIM == 2 && MODE == 0;
+  constexpr int NLDS = CACHE ? NS_LIM2_LDS : 0;
+  __shared__ double Ps[NLDS > 0 ? NLDS : 1][NC][kBlock];
+  const int lane = threadIdx.x;
   double Pc[CACHE ? C::W : 1][NC];
   double lc[CACHE ? C::W : 1];
 #pragma unroll
@@ -706,8 +715,14 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraphT<LT> G, StageArgsT<LT>
 #pragma unroll
       for (int q = 0; q < NC; ++q) u1[q] += lam * l * P[q];
       if constexpr (CACHE) {
+        const int o = k < C::W / 2 ? k : k - 1;  // off-diagonal ordinal
+        if (o < NLDS) {
 #pragma unroll
-        for (int q = 0; q < NC; ++q) Pc[k][q] = P[q];
+          for (int q = 0; q < NC; ++q) Ps[o < NLDS ? o : 0][q][lane] = P[q];
+        } else {
+#pragma unroll
+          for (int q = 0; q < NC; ++q) Pc[k][q] = P[q];
+        }
         lc[k] = l;
       }
     }
@@ -735,8 +750,14 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraphT<LT> G, StageArgsT<LT>
 #pragma unroll
         for (int kk = 0; kk < C::CH; ++kk) {
           const int k = ch * C::CH + kk;
+          const int o = k < C::W / 2 ? k : k - 1;
+          if (k != C::W / 2 && o < NLDS) {
 #pragma unroll
-          for (int q = 0; q < NC; ++q) P[kk][q] = Pc[k][q];
+            for (int q = 0; q < NC; ++q) P[kk][q] = Ps[o < NLDS ? o : 0][q][lane];
+          } else {
+#pragma unroll
+            for (int q = 0; q < NC; ++q) P[kk][q] = Pc[k][q];
+          }
           l[kk] = lc[k];
           jc[kk] = colk[k];
         }
