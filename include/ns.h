@@ -8,9 +8,14 @@
  * 3D hexahedra), ideal-gas Euler flux, graph viscosity from a guaranteed
  * maximum wave speed, low-order update, local bounds, high-order flux with
  * the approximate inverse mass matrix, convex limiting (Sec. 3, Algorithm 1),
- * SSPRK(3,3) with slip post-processing after every stage (Sec. 4.1-4.2);
- * the parabolic (viscous) sub-step with matrix-free conjugate gradients and
- * the Strang composition of the Navier-Stokes step (Sec. 2, Sec. 5).
+ * SSPRK(3,3) with slip post-processing after every stage (Sec. 4.1-4.2) or
+ * non-reflecting post-processing on chosen faces (Sec. 4.3.2), the adaptive
+ * CFL number of the Remark on high aspect-ratio meshes; the parabolic
+ * (viscous) sub-step with matrix-free conjugate gradients (diagonal or
+ * single-precision multigrid preconditioner) and the Strang composition of
+ * the Navier-Stokes step (Sec. 2, Sec. 5); FP32 storage of the
+ * bandwidth-bound arrays; asynchronous stepping, packs of meshes advanced by
+ * shared launches and a server for many independent simulations.
  *
  * Conventions shared by every call:
  *   - Status codes: NS_OK (0) or a negative NS_E* value.  No call throws.
@@ -64,7 +69,8 @@ enum { NS_LIM_CONVEX = 0, NS_LIM_LOW = 1, NS_LIM_HIGH = 2 };
 /* Uniform box mesh.  n[d] counts nodes in direction d.  A periodic direction
  * has mesh size (hi-lo)/n and needs n >= 3; a direction bounded by walls has
  * mesh size (hi-lo)/(n-1) and needs n >= 2.  Every non-periodic face is a
- * slip (reflecting) wall for the hyperbolic step (Sec. 4.2, eq. slip_bc). */
+ * slip (reflecting) wall for the hyperbolic step (Sec. 4.2, eq. slip_bc)
+ * unless ns_set_boundary makes it non-reflecting. */
 typedef struct ns_mesh_desc {
   int dim;          /* 2 or 3 */
   int64_t n[3];     /* nodes per direction (n[2] ignored when dim == 2) */
@@ -185,8 +191,8 @@ int ns_step_adaptive(ns_solver *s, double c_start, double *dt, double *c_used);
  * velocity is prescribed to 0 at both time levels) and the internal energy
  * satisfies homogeneous Neumann conditions (thermally insulated walls).
  * The two linear systems are solved by conjugate gradients preconditioned
- * with the diagonal of the operator, started from the values at t^n and
- * stopped when ||r||_2 <= cg_rtol ||b||_2 (unpreconditioned residual). */
+ * as `precond` selects, started from the values at t^n and stopped when
+ * ||r||_2 <= cg_rtol ||b||_2 (unpreconditioned residual). */
 enum { NS_FCT_AUTO = 0, NS_FCT_ALWAYS = 1 };
 typedef struct ns_viscous {
   double mu;       /* shear viscosity, >= 0                                 */
@@ -209,8 +215,10 @@ enum { NS_PC_JACOBI = 0, NS_PC_GMG = 1 };
 
 /* Enables the parabolic step: validates the data, builds the Q1 element
  * matrices of the stress and heat operators and allocates the CG vectors
- * (about 7 dim N + 8 N doubles) and a fourth state buffer that keeps
- * Strang steps transactional.  May be called again to change the data.
+ * (about 7 dim N + 8 N doubles; with NS_PC_GMG about 4 dim N doubles
+ * more for the FP32 levels) and a fourth state buffer that keeps Strang
+ * steps transactional.  May be called again to change the data; the
+ * multigrid levels are built once and their element tables redone.
  * NS_EINVAL for a NULL pointer or data out of range; NS_ENOMEM. */
 int ns_set_viscous(ns_solver *s, const ns_viscous *v);
 

@@ -1,16 +1,17 @@
 // par_kernels.hpp -- HIP kernels of the parabolic sub-step (Sec. 5 of
 // arXiv:2106.02159; the parabolic-step algorithm of the appendix), gfx950.
 //
-// Operators are applied matrix-free, one lane per node: the lane gathers
-// the 3^dim values of its neighbourhood into registers once and then, for
-// each of its (up to) 2^dim cells, multiplies by the constant Q1 element
-// matrix of the uniform mesh (element.hpp; its entries are wave-uniform
-// and read through the scalar cache).  No atomics: results are
-// deterministic and independent of the launch shape.
+// Operators are applied matrix-free, one lane per node (par_ops.hpp): at a
+// node all of whose 2^dim cells exist by the pre-summed 3^dim-point stencil
+// of the uniform mesh, at wall nodes cell by cell with the constant Q1
+// element matrix (element.hpp; the tables are wave-uniform and read through
+// the scalar cache).  No atomics: results are deterministic and independent
+// of the launch shape.
 //
 // The linear systems (velocity with no-slip rows eliminated, internal
 // energy with homogeneous Neumann conditions) are solved by conjugate
-// gradients with the diagonal preconditioner, kept entirely on the device:
+// gradients with the diagonal preconditioner or a multigrid V-cycle
+// (mg_kernels.hip), kept entirely on the device:
 // block partial sums are reduced in a fixed order by a one-block kernel
 // that also updates the CG scalars; every kernel of an iteration returns
 // at once when the solve has converged, so the host launches iterations in
