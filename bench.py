@@ -57,7 +57,7 @@ def kernel_bytes(name: str, dim: int, mixed: bool = False) -> float:
                  if dim == 2 else  # 3D: pass-1 update only
                  col + trk + 3 * eL + rows + nL + 2 * n8 + nc * n8),
         "lim2b": col + trk + 3 * eL + rows + nL + 2 * n8 + 3 * n8 + eL,
-        "fin": col + trk + 4 * eL + nc * (3 * n8 + nL) + nL + 2 * n8 + nc * n8,
+        "fin": col + trk + 3 * eL + nc * (3 * n8 + nL) + nL + 2 * n8 + nc * n8,
         "combine": 2 * nc * n8 + nc * n8,
         "slip": 0.0,
         "dt_final": 0.0,

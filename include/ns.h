@@ -425,7 +425,9 @@ enum {
   NS_DBG_FH = 4,        /* nc*N   high-order flux F^H_i divided by m_i    */
   NS_DBG_BOUNDS = 5,    /* 3*N    relaxed rho_min, rho_max, Phi_min       */
   NS_DBG_LT1 = 6,       /* W*N    pass-1 limiter before symmetrisation    */
-  NS_DBG_LT2 = 7,       /* W*N    pass-2 limiter before symmetrisation    */
+  NS_DBG_LT2 = 7,       /* W*N    pass-2 limiter before symmetrisation,
+                                  times (1 - l_ij), l_ij the symmetric pass-1
+                                  limiter                                 */
   NS_DBG_U1 = 8,        /* nc*N   state after limiter pass 1              */
   NS_DBG_ROOTS = 9      /* 2      edges whose line search needed the root  */
                         /*        finder, limiter passes 1 and 2          */

@@ -787,9 +787,11 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraphT<LT> G, StageArgsT<LT>
         const int k = ch * C::CH + kk;
         if (jc[kk] < 0 || jc[kk] == i) continue;
         double l2;
+        const double s1 = 1.0 - l[kk];
 #pragma unroll
-        for (int q = 0; q < NC; ++q) P[kk][q] *= (1.0 - l[kk]);
+        for (int q = 0; q < NC; ++q) P[kk][q] *= s1;
         if (limit_fast<DIM, SEV>(g, u1, P[kk], b, &l2)) slow |= 1u << k;
+        else l2 *= s1;
         st_once(&lt2[eidx<DIM>(k, i)], to_lt_down<LT>(l2));
       }
     }
@@ -843,10 +845,11 @@ __global__ __launch_bounds__(kBlock) void k_lim2b(DevGraphT<LT> G, StageArgsT<LT
       if (jc[kk] < 0 || jc[kk] == i) continue;
       double P[NC], l2;
       make_P<DIM>(R, x[kk], P);
-      const double l = fmin(la[kk], lb[kk]);
+      const double s1 = 1.0 - fmin(la[kk], lb[kk]);
 #pragma unroll
-      for (int q = 0; q < NC; ++q) P[q] *= (1.0 - l);
+      for (int q = 0; q < NC; ++q) P[q] *= s1;
       if (limit_fast<DIM, SEV>(g, u1, P, b, &l2)) slow |= 1u << k;
+      else l2 *= s1;
       st_once(&lt2[eidx<DIM>(k, i)], to_lt_down<LT>(l2));
     }
   }
@@ -889,12 +892,14 @@ __global__ __launch_bounds__(kBlock) void k_root(DevGraphT<LT> G, StageArgsT<LT>
     load_state<NC>(PASS == 1 ? A.UL : A.U1, N, i, u);
     const Bounds b = load_bounds(A, N, i);
     compute_P<DIM>(G, A, R, e, j, P);
+    double s1 = 1.0;
     if constexpr (PASS == 2) {
-      const double l = fmin(A.lt1[e], A.lt1[eidx<DIM>(G.trk[e], j)]);
+      s1 = 1.0 - fmin(A.lt1[e], A.lt1[eidx<DIM>(G.trk[e], j)]);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) P[c] *= (1.0 - l);
+      for (int c = 0; c < NC; ++c) P[c] *= s1;
     }
-    lt[e] = to_lt_down<LT>(entropy_root_fast<DIM, SEV>(g, u, P, lt[e], b.pmin, b.pmin5));
+    const double l = entropy_root_fast<DIM, SEV>(g, u, P, lt[e], b.pmin, b.pmin5);
+    lt[e] = to_lt_down<LT>(PASS == 2 ? l * s1 : l);
   }
 }
 
@@ -907,7 +912,6 @@ __global__ __launch_bounds__(kBlock) void k_fin(DevGraphT<LT> G, StageArgsT<LT> 
   if (i >= N) return;
   const int32_t *__restrict__ colp = G.col;
   const uint8_t *__restrict__ trkp = G.trk;
-  const LT *__restrict__ lt1 = A.lt1;
   const LT *__restrict__ lt2 = A.lt2;
   const RowIdx<DIM, int32_t> jv(colp, i);
   const RowIdx<DIM, uint8_t> tv(trkp, i);
@@ -919,7 +923,7 @@ __global__ __launch_bounds__(kBlock) void k_fin(DevGraphT<LT> G, StageArgsT<LT> 
 #pragma unroll
   for (int ch = 0; ch < C::NCH; ++ch) {
     PIn<DIM> x[C::CH];
-    double l1a[C::CH], l1b[C::CH], l2a[C::CH], l2b[C::CH];
+    double l2a[C::CH], l2b[C::CH];
     int32_t jc[C::CH];
 #pragma unroll
     for (int kk = 0; kk < C::CH; ++kk) {
@@ -929,20 +933,20 @@ __global__ __launch_bounds__(kBlock) void k_fin(DevGraphT<LT> G, StageArgsT<LT> 
       const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
       const int64_t et = eidx<DIM>(tv[k], js);
       gather_P<DIM>(G, A, e, js, x[kk]);
-      l1a[kk] = lt1[e];
-      l1b[kk] = lt1[et];
       l2a[kk] = lt2[e];
       l2b[kk] = lt2[et];
     }
 #pragma unroll
     for (int kk = 0; kk < C::CH; ++kk) {
       if (jc[kk] < 0 || jc[kk] == i) continue;
-      const double l1 = fmin(l1a[kk], l1b[kk]);
-      const double l2 = fmin(l2a[kk], l2b[kk]);
+      // lt2 holds l~'_ij (1 - l_ij) with l_ij the symmetric pass-1 limiter;
+      // (1 - l_ij) >= 0 and equal at ij and ji, and rounding is monotone, so
+      // the smaller stored product is min(l~'_ij, l~'_ji) (1 - l_ij) itself
+      const double w = lam * fmin(l2a[kk], l2b[kk]);
       double P[NC];
       make_P<DIM>(R, x[kk], P);
 #pragma unroll
-      for (int q = 0; q < NC; ++q) u2[q] += lam * l2 * ((1.0 - l1) * P[q]);
+      for (int q = 0; q < NC; ++q) u2[q] += w * P[q];
     }
   }
   finish<DIM>(G, A, i, u2);

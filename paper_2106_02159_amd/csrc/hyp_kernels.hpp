@@ -18,8 +18,9 @@
 //   k_root   roots of the entropy bound for the listed entries, one lane
 //            per entry (the rare slow path, kept out of the row sweeps)
 //   k_lim2   l_ij = min(l~_ij, l~_ji), U^(1) = U^L + lambda_i sum l P;
-//            pass-2 line search on (1 - l) P (or the final state for one pass)
-//   k_fin    l' symmetrised, U = U^(1) + lambda_i sum l' (1-l) P, SSP
+//            pass-2 line search on (1 - l) P, stored as l~'_ij (1 - l_ij)
+//            (or the final state for one pass)
+//   k_fin    l' (1-l) symmetrised, U = U^(1) + lambda_i sum l' (1-l) P, SSP
 //            combination a U^n + b U and admissibility flag
 //   k_slip   slip post-processing at wall nodes (eq. slip_bc)
 #pragma once
@@ -64,7 +65,7 @@ struct StageArgsT {
   LT *FH;            // nc*N
   double *bnds;      // 3*N
   LT *lt1;           // W*Np (FP32: rounded down, still feasible)
-  LT *lt2;           // W*Np
+  LT *lt2;           // W*Np: l~'_ij (1 - l_ij) (FP32: rounded down)
   double *U1;        // nc*N
   double *partial;   // per-block minima for the time step
   double *tau;       // device scalar

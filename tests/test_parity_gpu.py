@@ -110,8 +110,10 @@ def test_stage(case, mode):
         assert np.all(roots == np.round(roots)) and np.all(roots >= 0)
         assert roots.max() <= off.sum()
         if kw.get("passes", 2) == 2:
+            # stored as the pass-2 limiter times (1 - symmetric pass-1 limiter)
             lt2 = s.debug("lt2")[mask]
-            assert np.abs(lt2[off] - dbg["lt2"][idx][off]).max() <= 1e-10
+            v = dbg["lt2"][idx] * (1.0 - dbg["l1"][idx])
+            assert np.abs(lt2[off] - v[off]).max() <= 1e-10
             assert np.all(state_rel_err(s.debug("U1"), dbg["U1"]) <= TOL_STATE)
 
 
