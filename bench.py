@@ -40,24 +40,24 @@ def kernel_bytes(name: str, dim: int, mixed: bool = False) -> float:
     nc = dim + 2
     na = dim + 5
     L = 4 if mixed else 8          # storage of the FP32-capable arrays
-    col, trk = 4 * Wd, 1 * Wd
+    # column indices are derived from the box mesh, not loaded
     eL = L * Wd                    # one per-edge array (d, m_ij, l)
     cL = L * dim * Wd              # c_ij
     n8, nL = 8, L
     rows = nc * (2 * n8 + nL)      # U, U^L (or U^(1)) and F^H of the row
     table = {
         "prim": nc * n8 + na * n8,
-        "visc": col + cL + trk / 2 + nc * n8 + (na - 1) * n8 + 1 + eL + nL,
-        "visc_dt": col + cL + trk / 2 + (dim + 3) * n8 + 1 + eL,
-        "dt_partial": col + eL + n8,
-        "lo": col + cL + eL + nc * n8 + (dim + 2) * n8 + nL + 3 * n8
+        "visc": cL + nc * n8 + (na - 1) * n8 + 1 + eL + nL,
+        "visc_dt": cL + (dim + 3) * n8 + 1 + eL,
+        "dt_partial": eL + n8,
+        "lo": cL + eL + nc * n8 + (dim + 2) * n8 + nL + 3 * n8
               + nc * n8 + nc * nL + 3 * n8,
-        "lim1": col + 2 * eL + rows + nL + 2 * n8 + 3 * n8 + eL,
-        "lim2": (col + trk + 3 * eL + rows + nL + 2 * n8 + 3 * n8 + nc * n8 + eL
+        "lim1": 2 * eL + rows + nL + 2 * n8 + 3 * n8 + eL,
+        "lim2": (3 * eL + rows + nL + 2 * n8 + 3 * n8 + nc * n8 + eL
                  if dim == 2 else  # 3D: pass-1 update only
-                 col + trk + 3 * eL + rows + nL + 2 * n8 + nc * n8),
-        "lim2b": col + trk + 3 * eL + rows + nL + 2 * n8 + 3 * n8 + eL,
-        "fin": col + trk + 3 * eL + nc * (3 * n8 + nL) + nL + 2 * n8 + nc * n8,
+                 3 * eL + rows + nL + 2 * n8 + nc * n8),
+        "lim2b": 3 * eL + rows + nL + 2 * n8 + 3 * n8 + eL,
+        "fin": 3 * eL + nc * (3 * n8 + nL) + nL + 2 * n8 + nc * n8,
         "combine": 2 * nc * n8 + nc * n8,
         "slip": 0.0,
         "dt_final": 0.0,
@@ -66,13 +66,14 @@ def kernel_bytes(name: str, dim: int, mixed: bool = False) -> float:
 
 
 def stage_algorithmic_bytes(dim: int, mixed: bool = False) -> float:
-    """Bytes per node per forward-Euler stage if the graph (col, c_ij, m_ij,
-    m_i) and the state were each moved once: 345 B in 2D, 1087 B in 3D
-    (237 B and 655 B with c_ij and m_ij in FP32)."""
+    """Bytes per node per forward-Euler stage if the graph (c_ij, m_ij, m_i;
+    the column indices follow from the box mesh) and the state were each
+    moved once: 309 B in 2D, 979 B in 3D (201 B and 547 B with c_ij and m_ij
+    in FP32)."""
     Wd = 3 ** dim
     nc = dim + 2
     L = 4 if mixed else 8
-    return 4 * Wd + L * dim * Wd + L * Wd + 8 + 2 * 8 * nc + 8 * nc * 2 / 3
+    return L * dim * Wd + L * Wd + 8 + 2 * 8 * nc + 8 * nc * 2 / 3
 
 
 def source_sha() -> str:

@@ -415,6 +415,17 @@ const char *ns_server_error(const ns_server *sv, int64_t id);
  * limit, like the step. */
 int ns_fe_stage(ns_solver *s, double dt);
 
+/* Test access: the column indices as the kernels derive them from the box
+ * mesh (they are not stored on the device), for the mesh placed at row
+ * `base` of a solver and followed by padding rows up to base + rows - 1
+ * (rows >= N; padding rows are isolated nodes: only their diagonal entry).
+ * col: W*rows int32 in slot-major layout, entry (slot k, row base + r) at
+ * k*rows + r, -1 where the entry is absent; slot k holds the neighbour at
+ * offset (dx,dy,dz), k = (dx+1) + 3(dy+1) + 9(dz+1), and the transposed
+ * entry of (i, k) is (col, W-1-k).  Host-only.  NS_EINVAL for rows < N, a
+ * negative base or base + rows > 2^31 - 1. */
+int ns_graph_stencil_columns(const ns_graph *g, int64_t base, int64_t rows, int32_t *col);
+
 /* Intermediates of the last stage run (ns_fe_stage, or the last stage of
  * the last step).  Edge arrays use the ELL layout of ns_graph_export. */
 enum {

@@ -57,7 +57,7 @@ __device__ __forceinline__ int64_t eidx(int k, int64_t i) {
 }
 
 // Loads of arrays that a sweep reads once per entry (graph coefficients,
-// indices, d_ij of the row): with NS_NT they carry the non-temporal hint so
+// d_ij of the row): with NS_NT they carry the non-temporal hint so
 // that they do not push the neighbour rows' node data out of L2.
 #ifndef NS_NT
 #define NS_NT 2
@@ -73,28 +73,17 @@ __device__ __forceinline__ void st_once(T *p, T v) {
   else *p = v;
 }
 
-// Column (or transpose-slot) indices of a row: in 2D all W are loaded at
-// the start so that a chunk's gathers can be issued at once; in 3D each is
-// loaded where its chunk starts (27 of them would hold 27 registers through
-// the whole kernel and lower the occupancy).
-template <int DIM, typename T>
-struct RowIdx {
-  static constexpr bool PRE = DIM == 2;
-  static constexpr int W = DIM == 2 ? 9 : 27;
-  const T *p;
-  int64_t i;
-  T v[PRE ? W : 1];
-  __device__ __forceinline__ RowIdx(const T *ptr, int64_t row) : p(ptr), i(row) {
-    if constexpr (PRE) {
-#pragma unroll
-      for (int k = 0; k < W; ++k) v[k] = ld_once(&p[eidx<DIM>(k, i)]);
-    }
-  }
-  __device__ __forceinline__ int operator[](int k) const {
-    if constexpr (PRE) return v[k];
-    else return ld_once(&p[eidx<DIM>(k, i)]);
-  }
-};
+// Neighbours of row i (in its box mesh); the rows of a workgroup belong to
+// one mesh, so the mesh's geometry is a uniform (scalar) load.
+template <int DIM, typename LT>
+__device__ __forceinline__ BoxNbr<DIM> block_nbr(const DevGraphT<LT> &G, int64_t i) {
+  return BoxNbr<DIM>(G.geo[G.seg ? G.seg[blockIdx.x] : 0], i);
+}
+// Same for a row that is not the lane's own (work-list entries).
+template <int DIM, typename LT>
+__device__ __forceinline__ BoxNbr<DIM> row_nbr(const DevGraphT<LT> &G, int64_t i) {
+  return BoxNbr<DIM>(G.geo[G.seg ? G.seg[i / kBlock] : 0], i);
+}
 
 __device__ __forceinline__ int64_t row_id() {
   return (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -196,9 +185,9 @@ __global__ __launch_bounds__(kBlock) void k_prim(int64_t N,
 
 // ---------------------------------------------------------------------------
 // Graph viscosity d^L_ij (j > i, stored at (i,j) and (j,i)) and alpha_i.
-// All column indices of the row are loaded first; each chunk of slots then
-// gathers its neighbour data unconditionally (absent entries read row i
-// itself) so that the loads of a chunk are in flight together, and the
+// The column indices of the row follow from its place in the box mesh; each
+// chunk of slots gathers its neighbour data unconditionally (absent entries
+// read row i itself) so that the loads of a chunk are in flight together, and the
 // arithmetic is predicated on the entry being present.
 template <int DIM, int IND, int SEV, typename LT>
 __global__ __launch_bounds__(kBlock) void k_visc(DevGraphT<LT> G,
@@ -213,9 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_visc(DevGraphT<LT> G,
   const int64_t N = G.N;
   const int64_t i = row_id();
   if (i >= N) return;
-  const int32_t *__restrict__ colp = G.col;
-  const uint8_t *__restrict__ trkp = G.trk;
-  const RowIdx<DIM, int32_t> jv(colp, i);
+  const BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
   double vi[DIM];
 #pragma unroll
   for (int k = 0; k < DIM; ++k) vi[k] = aux[k * N + i];
@@ -294,7 +281,7 @@ __global__ __launch_bounds__(kBlock) void k_visc(DevGraphT<LT> G,
           uR += vj[kk][q] * c[kk][q] * icn;
         }
         double dij = lambda_max<SEV>(g, uL, pi, ai, bi, uR, pj[kk], aj[kk], bj[kk]) * cn;
-        const int kt = trkp[e];
+        const int kt = tslot<DIM>(k);
         const int64_t et = eidx<DIM>(kt, j);
         if (wall_i) {
           // both ends may be on the wall: c_ji != -c_ij, take both directions
@@ -338,10 +325,11 @@ __global__ __launch_bounds__(kBlock) void k_dt_partial(DevGraphT<LT> G,
   double r = INFINITY;
   if (i < N) {
     double dsum = 0.0;
+    const BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
 #pragma unroll
     for (int k = 0; k < C::W; ++k) {
       const int64_t e = eidx<DIM>(k, i);
-      const int32_t j = G.col[e];
+      const int32_t j = jv[k];
       const double v = d[e];  // absent entries hold 0
       if (j >= 0 && j != i) dsum += v;
     }
@@ -405,8 +393,7 @@ __global__ __launch_bounds__(kBlock) void k_lo(DevGraphT<LT> G, StageArgsT<LT> A
   const double *__restrict__ aux = A.aux;
   const LT *__restrict__ alpha = A.alpha;
   const LT *__restrict__ dd = A.d;
-  const int32_t *__restrict__ colp = G.col;
-  const RowIdx<DIM, int32_t> jv(colp, i);
+  const BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
   double ui[NC], vi[DIM];
   load_state<NC>(U, N, i, ui);
 #pragma unroll
@@ -619,8 +606,7 @@ __global__ __launch_bounds__(kBlock) void k_lim1(DevGraphT<LT> G, StageArgsT<LT>
   const int64_t N = G.N;
   const int64_t i = row_id();
   if (i >= N) return;
-  const int32_t *__restrict__ colp = G.col;
-  const RowIdx<DIM, int32_t> jv(colp, i);
+  const BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
   RowCtx<DIM> R;
   load_row<DIM>(G, A, i, A.tau[member(A, i)], R);
   double ul[NC];
@@ -669,11 +655,8 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraphT<LT> G, StageArgsT<LT>
   const int64_t N = G.N;
   const int64_t i = row_id();
   if (i >= N) return;
-  const int32_t *__restrict__ colp = G.col;
-  const uint8_t *__restrict__ trkp = G.trk;
   const LT *__restrict__ lt1 = A.lt1;
-  const RowIdx<DIM, int32_t> colk(colp, i);
-  const RowIdx<DIM, uint8_t> trkk(trkp, i);
+  const BoxNbr<DIM> colk = block_nbr<DIM>(G, i);
   RowCtx<DIM> R;
   load_row<DIM>(G, A, i, A.tau[member(A, i)], R);
   const double lam = 1.0 / G.lfac[i];
@@ -702,7 +685,7 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraphT<LT> G, StageArgsT<LT>
       gather_P<DIM>(G, A, e, js, x[kk]);
       if constexpr (MODE != 2) {
         la[kk] = lt1[e];
-        lb[kk] = lt1[eidx<DIM>(trkk[k], js)];
+        lb[kk] = lt1[eidx<DIM>(tslot<DIM>(k), js)];
       }
     }
 #pragma unroll
@@ -774,7 +757,7 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraphT<LT> G, StageArgsT<LT>
           const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
           gather_P<DIM>(G, A, e, js, x[kk]);
           la[kk] = lt1[e];
-          lb[kk] = lt1[eidx<DIM>(trkk[k], js)];
+          lb[kk] = lt1[eidx<DIM>(tslot<DIM>(k), js)];
         }
 #pragma unroll
         for (int kk = 0; kk < C::CH; ++kk) {
@@ -814,10 +797,9 @@ __global__ __launch_bounds__(kBlock) void k_lim2b(DevGraphT<LT> G, StageArgsT<LT
   const int64_t N = G.N;
   const int64_t i = row_id();
   if (i >= N) return;
-  const int32_t *__restrict__ colp = G.col;
-  const uint8_t *__restrict__ trkp = G.trk;
   const LT *__restrict__ lt1 = A.lt1;
   LT *__restrict__ lt2 = A.lt2;
+  const BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
   RowCtx<DIM> R;
   load_row<DIM>(G, A, i, A.tau[member(A, i)], R);
   double u1[NC];
@@ -833,11 +815,11 @@ __global__ __launch_bounds__(kBlock) void k_lim2b(DevGraphT<LT> G, StageArgsT<LT
     for (int kk = 0; kk < C::CH; ++kk) {
       const int k = ch * C::CH + kk;
       const int64_t e = eidx<DIM>(k, i);
-      jc[kk] = ld_once(&colp[e]);
+      jc[kk] = jv[k];
       const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
       gather_P<DIM>(G, A, e, js, x[kk]);
       la[kk] = lt1[e];
-      lb[kk] = lt1[eidx<DIM>(ld_once(&trkp[e]), js)];
+      lb[kk] = lt1[eidx<DIM>(tslot<DIM>(k), js)];
     }
 #pragma unroll
     for (int kk = 0; kk < C::CH; ++kk) {
@@ -885,7 +867,8 @@ __global__ __launch_bounds__(kBlock) void k_root(DevGraphT<LT> G, StageArgsT<LT>
        t += gridDim.x * kBlock) {
     const int64_t e = q[t];
     const int64_t i = edge_row<DIM>(e);
-    const int32_t j = G.col[e];
+    const int k = (int)((e >> 6) % (DIM == 2 ? 9 : 27));
+    const int32_t j = row_nbr<DIM>(G, i)[k];
     RowCtx<DIM> R;
     load_row<DIM>(G, A, i, A.tau[member(A, i)], R);
     double u[NC], P[NC];
@@ -894,7 +877,7 @@ __global__ __launch_bounds__(kBlock) void k_root(DevGraphT<LT> G, StageArgsT<LT>
     compute_P<DIM>(G, A, R, e, j, P);
     double s1 = 1.0;
     if constexpr (PASS == 2) {
-      s1 = 1.0 - fmin(A.lt1[e], A.lt1[eidx<DIM>(G.trk[e], j)]);
+      s1 = 1.0 - fmin(A.lt1[e], A.lt1[eidx<DIM>(tslot<DIM>(k), j)]);
 #pragma unroll
       for (int c = 0; c < NC; ++c) P[c] *= s1;
     }
@@ -910,11 +893,8 @@ __global__ __launch_bounds__(kBlock) void k_fin(DevGraphT<LT> G, StageArgsT<LT> 
   const int64_t N = G.N;
   const int64_t i = row_id();
   if (i >= N) return;
-  const int32_t *__restrict__ colp = G.col;
-  const uint8_t *__restrict__ trkp = G.trk;
   const LT *__restrict__ lt2 = A.lt2;
-  const RowIdx<DIM, int32_t> jv(colp, i);
-  const RowIdx<DIM, uint8_t> tv(trkp, i);
+  const BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
   RowCtx<DIM> R;
   load_row<DIM>(G, A, i, A.tau[member(A, i)], R);
   const double lam = 1.0 / G.lfac[i];
@@ -931,7 +911,7 @@ __global__ __launch_bounds__(kBlock) void k_fin(DevGraphT<LT> G, StageArgsT<LT> 
       const int64_t e = eidx<DIM>(k, i);
       jc[kk] = jv[k];
       const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
-      const int64_t et = eidx<DIM>(tv[k], js);
+      const int64_t et = eidx<DIM>(tslot<DIM>(k), js);
       gather_P<DIM>(G, A, e, js, x[kk]);
       l2a[kk] = lt2[e];
       l2b[kk] = lt2[et];

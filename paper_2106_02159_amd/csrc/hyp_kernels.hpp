@@ -29,6 +29,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "box_nbr.hpp"
 #include "euler.hpp"
 
 namespace ns {
@@ -42,8 +43,11 @@ template <typename LT>
 struct DevGraphT {
   int64_t N;
   int W;
-  const int32_t *col;   // W*Np
-  const uint8_t *trk;   // W*Np: slot of the transposed entry in row col
+  // column indices: derived from the box mesh of the row (box_nbr.hpp);
+  // geo has one entry per mesh, seg maps each 256-row block to its mesh
+  // (null for a single mesh)
+  const BoxGeom *geo;
+  const int32_t *seg;
   const LT *mij;        // W*Np
   const LT *c0, *c1, *c2;  // W*Np each (c2 unused in 2D)
   const double *mi;     // N

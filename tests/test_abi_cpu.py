@@ -58,6 +58,36 @@ def test_graph_matches_oracle(mesh):
     assert np.abs(ex["bnd"] - o.bnd).max() <= 1e-14 * max(np.abs(o.bnd).max(), 1e-300)
 
 
+@pytest.mark.parametrize("mesh", MESHES + [
+    W.Mesh(2, (3, 3), (0.0, 0.0), (1.0, 1.0), (True, True)),
+    W.Mesh(2, (70, 3), (0.0, 0.0), (1.0, 1.0), (False, True)),
+    W.Mesh(3, (2, 2, 2), (0.0,) * 3, (1.0,) * 3, (False,) * 3),
+    W.Mesh(3, (5, 3, 4), (0.0,) * 3, (1.0,) * 3, (True, False, True)),
+], ids=lambda m: f"{m.dim}d{m.n}{m.periodic}")
+def test_kernel_columns_match_graph(mesh):
+    """The kernels derive the column index of every entry from the box mesh
+    instead of loading it: the derived indices equal the graph's (which the
+    test above pins to the oracle), shifted by the mesh's first row in a
+    pack, with isolated padding rows, and the transposed entry of (i, k) is
+    (j, W-1-k)."""
+    g = abi.Graph(mesh)
+    col = g.export()["col"]
+    assert np.array_equal(g.stencil_columns(), col)
+    Wd, N = col.shape
+    for k in range(Wd):
+        j = col[k]
+        ok = j >= 0
+        assert np.array_equal(col[Wd - 1 - k][j[ok]], np.arange(N)[ok])
+    base, pad = 512, 37
+    c2 = g.stencil_columns(base, N + pad)
+    assert np.array_equal(c2[:, :N], np.where(col >= 0, col + base, -1))
+    self_k = Wd // 2
+    assert np.array_equal(c2[self_k, N:], base + np.arange(N, N + pad))
+    assert np.all(np.delete(c2[:, N:], self_k, axis=0) == -1)
+    with pytest.raises(abi.NSError):
+        g.stencil_columns(0, N - 1)
+
+
 def test_graph_exact_antisymmetry():
     """The closed form gives c_ij = -c_ji bit for bit unless both nodes are on
     the wall (where c_ij + c_ji = int phi_i phi_j n)."""
