@@ -30,34 +30,33 @@ from paper_2106_02159_amd import abi, workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes per node per launch of each kernel (sliced ELL with int32
-# columns and uint8 transpose slots; every array a kernel touches counted
-# once; W = 3^d slots, nc = d + 2 components).  With `mixed`, the graph
-# coefficients m_ij, c_ij and alpha, d_ij, F^H and the limiter coefficients
+# Algorithmic bytes per node per launch of each kernel (sliced ELL edge
+# arrays; column indices, m_ij and c_ij derived from the box mesh, not moved;
+# every array a kernel touches counted once; W = 3^d slots, nc = d + 2
+# components).  With `mixed`, alpha, d_ij, F^H and the limiter coefficients
 # are 4-byte values; everything else is FP64.
 def kernel_bytes(name: str, dim: int, mixed: bool = False) -> float:
     Wd = 3 ** dim
     nc = dim + 2
     na = dim + 5
     L = 4 if mixed else 8          # storage of the FP32-capable arrays
-    # column indices are derived from the box mesh, not loaded
-    eL = L * Wd                    # one per-edge array (d, m_ij, l)
-    cL = L * dim * Wd              # c_ij
+    # column indices, m_ij and c_ij are derived from the box mesh, not loaded
+    eL = L * Wd                    # one per-edge array (d, l)
     n8, nL = 8, L
     rows = nc * (2 * n8 + nL)      # U, U^L (or U^(1)) and F^H of the row
     table = {
         "prim": nc * n8 + na * n8,
-        "visc": cL + nc * n8 + (na - 1) * n8 + 1 + eL + nL,
-        "visc_dt": cL + (dim + 3) * n8 + 1 + eL,
+        "visc": nc * n8 + (na - 1) * n8 + 1 + eL + nL,
+        "visc_dt": (dim + 3) * n8 + 1 + eL,
         "dt_partial": eL + n8,
-        "lo": cL + eL + nc * n8 + (dim + 2) * n8 + nL + 3 * n8
+        "lo": eL + nc * n8 + (dim + 2) * n8 + nL + 3 * n8
               + nc * n8 + nc * nL + 3 * n8,
-        "lim1": 2 * eL + rows + nL + 2 * n8 + 3 * n8 + eL,
-        "lim2": (3 * eL + rows + nL + 2 * n8 + 3 * n8 + nc * n8 + eL
+        "lim1": eL + rows + nL + 2 * n8 + 3 * n8 + eL,
+        "lim2": (2 * eL + rows + nL + 2 * n8 + 3 * n8 + nc * n8 + eL
                  if dim == 2 else  # 3D: pass-1 update only
-                 3 * eL + rows + nL + 2 * n8 + nc * n8),
-        "lim2b": 3 * eL + rows + nL + 2 * n8 + 3 * n8 + eL,
-        "fin": 3 * eL + nc * (3 * n8 + nL) + nL + 2 * n8 + nc * n8,
+                 2 * eL + rows + nL + 2 * n8 + nc * n8),
+        "lim2b": 2 * eL + rows + nL + 2 * n8 + 3 * n8 + eL,
+        "fin": 2 * eL + nc * (3 * n8 + nL) + nL + 2 * n8 + nc * n8,
         "combine": 2 * nc * n8 + nc * n8,
         "slip": 0.0,
         "dt_final": 0.0,
@@ -66,14 +65,12 @@ def kernel_bytes(name: str, dim: int, mixed: bool = False) -> float:
 
 
 def stage_algorithmic_bytes(dim: int, mixed: bool = False) -> float:
-    """Bytes per node per forward-Euler stage if the graph (c_ij, m_ij, m_i;
-    the column indices follow from the box mesh) and the state were each
-    moved once: 309 B in 2D, 979 B in 3D (201 B and 547 B with c_ij and m_ij
-    in FP32)."""
-    Wd = 3 ** dim
+    """Bytes per node per forward-Euler stage if m_i and the state were each
+    moved once (the column indices, m_ij and c_ij follow from the box mesh):
+    read U, write the stage result, read U^n in two of the three stages;
+    93 B in 2D, 115 B in 3D, in either precision mode."""
     nc = dim + 2
-    L = 4 if mixed else 8
-    return L * dim * Wd + L * Wd + 8 + 2 * 8 * nc + 8 * nc * 2 / 3
+    return 8 + 2 * 8 * nc + 8 * nc * 2 / 3
 
 
 def source_sha() -> str:
@@ -251,8 +248,8 @@ def main():
                     help="Navier-Stokes: preconditioner of the parabolic CG (gmg: "
                          "FP32 multigrid V-cycle, for the viscous-dominated regime)")
     ap.add_argument("--mixed", action="store_true",
-                    help="mixed precision: FP32 storage of the graph coefficients "
-                         "and of alpha, d_ij, F^H and the limiter coefficients, "
+                    help="mixed precision: FP32 storage of alpha, d_ij, F^H and "
+                         "the limiter coefficients, "
                          "FP64 state and arithmetic; after the timed steps the FP64 "
                          "path is run with the same time steps and the L1 relative "
                          "error is reported")
@@ -378,8 +375,8 @@ def main():
                        f"2D Euler gamma=1.4, Q1 {n}x{n} nodes on [0,1]^2, "
                        f"reflecting walls, seeded four-quadrant Riemann data "
                        f"(seed {args.seed}), SSPRK3 + 2-pass convex limiting, CFL 0.5"
-                       + (", mixed precision (FP32 storage of m_ij, c_ij, alpha, "
-                          "d_ij, F^H, limiter coefficients)" if args.mixed else "")
+                       + (", mixed precision (FP32 storage of alpha, d_ij, F^H, "
+                          "limiter coefficients)" if args.mixed else "")
                        if dim == 2 else
                        f"3D Euler gamma=1.4 (hyperbolic step of the Navier-Stokes "
                        f"configuration), Q1 {n}^3 nodes on [0,1]^3, reflecting walls, "

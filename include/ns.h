@@ -115,13 +115,13 @@ typedef struct ns_params {
                      rho in [(1-r_i) rho_min, (1+r_i) rho_max] and
                      Phi >= (1-r_i) Phi_min, r_i = r0 (m_i/|Omega|)^(3/(2d));
                      0 = the strict bounds of Sec. 3.3                      */
-  int precision;  /* NS_PREC_FP64, or NS_PREC_MIXED: the graph coefficients
-                     m_ij, c_ij and the intermediates alpha_i, d^L_ij, F^H_i
-                     and the limiter coefficients are stored in FP32 (d_ij
-                     rounded up, so it stays an upper bound of the wave-speed
-                     term; limiter coefficients rounded down, so they stay
-                     feasible); the state, the bounds, the line search and
-                     all arithmetic stay FP64                               */
+  int precision;  /* NS_PREC_FP64, or NS_PREC_MIXED: the intermediates
+                     alpha_i, d^L_ij, F^H_i and the limiter coefficients are
+                     stored in FP32 (d_ij rounded up, so it stays an upper
+                     bound of the wave-speed term; limiter coefficients
+                     rounded down, so they stay feasible); the state, the
+                     bounds, the line search and all arithmetic stay FP64
+                     (m_ij and c_ij are computed, never stored)             */
 } ns_params;
 
 enum { NS_PREC_FP64 = 0, NS_PREC_MIXED = 1 };
@@ -415,16 +415,19 @@ const char *ns_server_error(const ns_server *sv, int64_t id);
  * limit, like the step. */
 int ns_fe_stage(ns_solver *s, double dt);
 
-/* Test access: the column indices as the kernels derive them from the box
- * mesh (they are not stored on the device), for the mesh placed at row
+/* Test access: the stencil entries as the kernels derive them from the box
+ * mesh (no graph array is stored on the device), for the mesh placed at row
  * `base` of a solver and followed by padding rows up to base + rows - 1
- * (rows >= N; padding rows are isolated nodes: only their diagonal entry).
- * col: W*rows int32 in slot-major layout, entry (slot k, row base + r) at
- * k*rows + r, -1 where the entry is absent; slot k holds the neighbour at
- * offset (dx,dy,dz), k = (dx+1) + 3(dy+1) + 9(dz+1), and the transposed
- * entry of (i, k) is (col, W-1-k).  Host-only.  NS_EINVAL for rows < N, a
- * negative base or base + rows > 2^31 - 1. */
-int ns_graph_stencil_columns(const ns_graph *g, int64_t base, int64_t rows, int32_t *col);
+ * (rows >= N; padding rows are isolated nodes: only their diagonal entry,
+ * with m_ii = 1 and c_ii = 0).  Host-only.  Layout as ns_graph_export with
+ * `rows` in place of N: col W*rows int32, entry (slot k, row base + r) at
+ * k*rows + r, -1 where absent; slot k holds the neighbour at offset
+ * (dx,dy,dz), k = (dx+1) + 3(dy+1) + 9(dz+1), and the transposed entry of
+ * (i, k) is (col, W-1-k); mij W*rows; cij dim*W*rows, component-major.  The
+ * coefficients of absent entries are unspecified.  Any output may be NULL.
+ * NS_EINVAL for rows < N, a negative base or base + rows > 2^31 - 1. */
+int ns_graph_stencil(const ns_graph *g, int64_t base, int64_t rows, int32_t *col,
+                     double *mij, double *cij);
 
 /* Intermediates of the last stage run (ns_fe_stage, or the last stage of
  * the last step).  Edge arrays use the ELL layout of ns_graph_export. */

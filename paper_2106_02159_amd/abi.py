@@ -28,7 +28,7 @@ DBG = {"stage_out": 0, "d": 1, "alpha": 2, "UL": 3, "FH": 4, "bounds": 5,
 
 EXPORTED = [
     "ns_graph_create", "ns_graph_destroy", "ns_graph_info", "ns_graph_export",
-    "ns_graph_stencil_columns",
+    "ns_graph_stencil",
     "ns_solver_create", "ns_solver_destroy", "ns_set_state", "ns_get_state",
     "ns_compute_dt", "ns_step", "ns_step_cfl", "ns_fe_stage", "ns_get_debug",
     "ns_sync", "ns_stream", "ns_profile_enable", "ns_profile_count",
@@ -81,7 +81,7 @@ def lib() -> C.CDLL:
             "ns_graph_info": (C.c_int, [vp, i64p, i64p, C.POINTER(C.c_int),
                                         C.POINTER(C.c_int)]),
             "ns_graph_export": (C.c_int, [vp, vp, vp, vp, vp, vp]),
-            "ns_graph_stencil_columns": (C.c_int, [vp, C.c_int64, C.c_int64, vp]),
+            "ns_graph_stencil": (C.c_int, [vp, C.c_int64, C.c_int64, vp, vp, vp]),
             "ns_solver_create": (C.c_int, [vp, C.POINTER(Params), vp, C.POINTER(vp)]),
             "ns_solver_destroy": (None, [vp]),
             "ns_set_state": (C.c_int, [vp, vp, C.c_int]),
@@ -184,15 +184,18 @@ class Graph:
                               _ptr(bnd))
         return dict(col=col, mij=mij, cij=cij, mi=mi, bnd=bnd)
 
-    def stencil_columns(self, base=0, rows=None):
-        """Column indices as the kernels derive them (ns_graph_stencil_columns):
-        (W, rows) int32 for the mesh at row `base` plus padding rows."""
+    def stencil(self, base=0, rows=None):
+        """Stencil entries as the kernels derive them (ns_graph_stencil) for
+        the mesh at row `base` plus padding rows: col (W, rows) int32, mij
+        (W, rows), cij (dim, W, rows)."""
         rows = self.N if rows is None else rows
         col = np.empty((self.W, rows), np.int32)
-        rc = lib().ns_graph_stencil_columns(self.h, base, rows, _ptr(col))
+        mij = np.empty((self.W, rows))
+        cij = np.empty((self.dim, self.W, rows))
+        rc = lib().ns_graph_stencil(self.h, base, rows, _ptr(col), _ptr(mij), _ptr(cij))
         if rc != NS_OK:
-            raise NSError(rc, "ns_graph_stencil_columns")
-        return col
+            raise NSError(rc, "ns_graph_stencil")
+        return dict(col=col, mij=mij, cij=cij)
 
     def close(self):
         if getattr(self, "h", None):

@@ -12,10 +12,18 @@ int64_t MeshGraph::nb1(int d, int64_t a, int o) const {
   return b;
 }
 
+void MeshGraph::m1_values(int d, double *inner, double *end, double *off) const {
+  *inner = 2.0 * h[d] / 3.0;
+  *end = h[d] / 3.0;
+  *off = h[d] / 6.0;
+}
+
 double MeshGraph::m1(int d, int64_t a, int o) const {
-  if (o != 0) return h[d] / 6.0;
-  if (wall_lo(d, a) || wall_hi(d, a)) return h[d] / 3.0;
-  return 2.0 * h[d] / 3.0;
+  double inner, end, off;
+  m1_values(d, &inner, &end, &off);
+  if (o != 0) return off;
+  if (wall_lo(d, a) || wall_hi(d, a)) return end;
+  return inner;
 }
 
 double MeshGraph::c1(int d, int64_t a, int o) const {

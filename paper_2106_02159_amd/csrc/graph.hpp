@@ -39,6 +39,9 @@ struct MeshGraph {
   // neighbour index along d, or -1 outside a wall-bounded direction
   int64_t nb1(int d, int64_t a, int o) const;
   double m1(int d, int64_t a, int o) const;
+  // the three values of m1 along d: diagonal of an interior node, diagonal
+  // at a wall end, off-diagonal
+  void m1_values(int d, double *inner, double *end, double *off) const;
   double c1(int d, int64_t a, int o) const;
   double ml(int d, int64_t a) const;
   double bn1(int d, int64_t a) const;

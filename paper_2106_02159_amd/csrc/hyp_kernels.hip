@@ -77,12 +77,12 @@ __device__ __forceinline__ void st_once(T *p, T v) {
 // one mesh, so the mesh's geometry is a uniform (scalar) load.
 template <int DIM, typename LT>
 __device__ __forceinline__ BoxNbr<DIM> block_nbr(const DevGraphT<LT> &G, int64_t i) {
-  return BoxNbr<DIM>(G.geo[G.seg ? G.seg[blockIdx.x] : 0], i);
+  return BoxNbr<DIM>(&G.geo[G.seg ? G.seg[blockIdx.x] : 0], i);
 }
 // Same for a row that is not the lane's own (work-list entries).
 template <int DIM, typename LT>
 __device__ __forceinline__ BoxNbr<DIM> row_nbr(const DevGraphT<LT> &G, int64_t i) {
-  return BoxNbr<DIM>(G.geo[G.seg ? G.seg[i / kBlock] : 0], i);
+  return BoxNbr<DIM>(&G.geo[G.seg ? G.seg[i / kBlock] : 0], i);
 }
 
 __device__ __forceinline__ int64_t row_id() {
@@ -109,13 +109,6 @@ template <typename LT> __device__ __forceinline__ LT to_lt_up(double x) {
 template <typename LT> __device__ __forceinline__ LT to_lt_down(double x) {
   if constexpr (sizeof(LT) == 4) return __double2float_rd(x);
   else return x;
-}
-
-template <int DIM, typename LT>
-__device__ __forceinline__ void load_c(const DevGraphT<LT> &G, int64_t e, double *c) {
-  c[0] = ld_once(&G.c0[e]);
-  c[1] = ld_once(&G.c1[e]);
-  if constexpr (DIM == 3) c[2] = ld_once(&G.c2[e]);
 }
 
 template <int NC, typename T>
@@ -202,7 +195,7 @@ __global__ __launch_bounds__(kBlock) void k_visc(DevGraphT<LT> G,
   const int64_t N = G.N;
   const int64_t i = row_id();
   if (i >= N) return;
-  const BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
+  BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
   double vi[DIM];
 #pragma unroll
   for (int k = 0; k < DIM; ++k) vi[k] = aux[k * N + i];
@@ -230,6 +223,7 @@ __global__ __launch_bounds__(kBlock) void k_visc(DevGraphT<LT> G,
   double num = 0.0, den = 0.0, scl = 0.0;
 #pragma unroll
   for (int ch = 0; ch < C::NCH; ++ch) {
+    jv.fence();
     double c[C::CH][DIM], vj[C::CH][DIM], pj[C::CH], aj[C::CH], bj[C::CH];
     double uj[C::CH][IND == 0 ? NC : 1], etaj[C::CH];
     int32_t jc[C::CH];
@@ -239,7 +233,7 @@ __global__ __launch_bounds__(kBlock) void k_visc(DevGraphT<LT> G,
       const int64_t e = eidx<DIM>(k, i);
       jc[kk] = jv[k];
       const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
-      load_c<DIM>(G, e, c[kk]);
+      jv.grad(k, c[kk]);
 #pragma unroll
       for (int q = 0; q < DIM; ++q) vj[kk][q] = aux[q * N + js];
       pj[kk] = aux[X::P * N + js];
@@ -286,7 +280,7 @@ __global__ __launch_bounds__(kBlock) void k_visc(DevGraphT<LT> G,
         if (wall_i) {
           // both ends may be on the wall: c_ji != -c_ij, take both directions
           double ct[DIM];
-          load_c<DIM>(G, et, ct);
+          grad_transposed<DIM>(k, c[kk], ct);
           double ct2 = 0.0;
 #pragma unroll
           for (int q = 0; q < DIM; ++q) ct2 += ct[q] * ct[q];
@@ -325,7 +319,7 @@ __global__ __launch_bounds__(kBlock) void k_dt_partial(DevGraphT<LT> G,
   double r = INFINITY;
   if (i < N) {
     double dsum = 0.0;
-    const BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
+    BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
 #pragma unroll
     for (int k = 0; k < C::W; ++k) {
       const int64_t e = eidx<DIM>(k, i);
@@ -393,7 +387,7 @@ __global__ __launch_bounds__(kBlock) void k_lo(DevGraphT<LT> G, StageArgsT<LT> A
   const double *__restrict__ aux = A.aux;
   const LT *__restrict__ alpha = A.alpha;
   const LT *__restrict__ dd = A.d;
-  const BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
+  BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
   double ui[NC], vi[DIM];
   load_state<NC>(U, N, i, ui);
 #pragma unroll
@@ -408,6 +402,7 @@ __global__ __launch_bounds__(kBlock) void k_lo(DevGraphT<LT> G, StageArgsT<LT> A
   double rmin = ui[0], rmax = ui[0], phimin = aux[X::PHI * N + i], dsum = 0.0;
 #pragma unroll
   for (int ch = 0; ch < C::NCH; ++ch) {
+    jv.fence();
     double c[C::CH][DIM], uj[C::CH][NC], vj[C::CH][DIM], pj[C::CH], phij[C::CH],
         alj[C::CH], dij[C::CH];
     int32_t jc[C::CH];
@@ -417,7 +412,7 @@ __global__ __launch_bounds__(kBlock) void k_lo(DevGraphT<LT> G, StageArgsT<LT> A
       const int64_t e = eidx<DIM>(k, i);
       jc[kk] = jv[k];
       const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
-      load_c<DIM>(G, e, c[kk]);
+      jv.grad(k, c[kk]);
       load_state<NC>(U, N, js, uj[kk]);
 #pragma unroll
       for (int q = 0; q < DIM; ++q) vj[kk][q] = aux[q * N + js];
@@ -508,14 +503,14 @@ struct PIn {
 
 template <int DIM, typename LT>
 __device__ __forceinline__ void gather_P(const DevGraphT<LT> &G, const StageArgsT<LT> &A,
-                                         int64_t e, int64_t js, PIn<DIM> &x) {
+                                         int64_t e, int64_t js, double mij, PIn<DIM> &x) {
   constexpr int NC = DIM + 2;
   const int64_t N = G.N;
   load_state<NC>(A.U, N, js, x.u);
   load_state<NC>(A.FH, N, js, x.f);
   x.al = A.alpha[js];
   x.d = ld_once(&A.d[e]);
-  x.m = ld_once(&G.mij[e]);
+  x.m = mij;
 }
 
 template <int DIM>
@@ -531,9 +526,9 @@ __device__ __forceinline__ void make_P(const RowCtx<DIM> &R, const PIn<DIM> &x,
 template <int DIM, typename LT>
 __device__ __forceinline__ void compute_P(const DevGraphT<LT> &G, const StageArgsT<LT> &A,
                                           const RowCtx<DIM> &R, int64_t e,
-                                          int32_t j, double *P) {
+                                          int32_t j, double mij, double *P) {
   PIn<DIM> x;
-  gather_P<DIM>(G, A, e, j, x);
+  gather_P<DIM>(G, A, e, j, mij, x);
   make_P<DIM>(R, x, P);
 }
 
@@ -606,7 +601,7 @@ __global__ __launch_bounds__(kBlock) void k_lim1(DevGraphT<LT> G, StageArgsT<LT>
   const int64_t N = G.N;
   const int64_t i = row_id();
   if (i >= N) return;
-  const BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
+  BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
   RowCtx<DIM> R;
   load_row<DIM>(G, A, i, A.tau[member(A, i)], R);
   double ul[NC];
@@ -616,13 +611,14 @@ __global__ __launch_bounds__(kBlock) void k_lim1(DevGraphT<LT> G, StageArgsT<LT>
   uint32_t slow = 0;
 #pragma unroll
   for (int ch = 0; ch < C::NCH; ++ch) {
+    jv.fence();
     PIn<DIM> x[C::CH];
     int32_t jc[C::CH];
 #pragma unroll
     for (int kk = 0; kk < C::CH; ++kk) {
       const int k = ch * C::CH + kk;
       jc[kk] = jv[k];
-      gather_P<DIM>(G, A, eidx<DIM>(k, i), jc[kk] >= 0 ? jc[kk] : i, x[kk]);
+      gather_P<DIM>(G, A, eidx<DIM>(k, i), jc[kk] >= 0 ? jc[kk] : i, jv.mass(k), x[kk]);
     }
 #pragma unroll
     for (int kk = 0; kk < C::CH; ++kk) {
@@ -656,7 +652,7 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraphT<LT> G, StageArgsT<LT>
   const int64_t i = row_id();
   if (i >= N) return;
   const LT *__restrict__ lt1 = A.lt1;
-  const BoxNbr<DIM> colk = block_nbr<DIM>(G, i);
+  BoxNbr<DIM> colk = block_nbr<DIM>(G, i);
   RowCtx<DIM> R;
   load_row<DIM>(G, A, i, A.tau[member(A, i)], R);
   const double lam = 1.0 / G.lfac[i];
@@ -673,6 +669,8 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraphT<LT> G, StageArgsT<LT>
   double lc[CACHE ? C::W : 1];
 #pragma unroll
   for (int ch = 0; ch < C::NCH; ++ch) {
+    // (the 2D cached form holds fewer registers without the fences)
+    if constexpr (!CACHE) colk.fence();
     PIn<DIM> x[C::CH];
     double la[C::CH], lb[C::CH];
     int32_t jc[C::CH];
@@ -682,7 +680,7 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraphT<LT> G, StageArgsT<LT>
       const int64_t e = eidx<DIM>(k, i);
       jc[kk] = colk[k];
       const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
-      gather_P<DIM>(G, A, e, js, x[kk]);
+      gather_P<DIM>(G, A, e, js, colk.mass(k), x[kk]);
       if constexpr (MODE != 2) {
         la[kk] = lt1[e];
         lb[kk] = lt1[eidx<DIM>(tslot<DIM>(k), js)];
@@ -727,6 +725,7 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraphT<LT> G, StageArgsT<LT>
     }
 #pragma unroll
     for (int ch = 0; ch < C::NCH; ++ch) {
+      if constexpr (!CACHE) colk.fence();
       double P[C::CH][NC], l[C::CH];
       int32_t jc[C::CH];
       if constexpr (CACHE) {
@@ -755,7 +754,7 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraphT<LT> G, StageArgsT<LT>
           const int64_t e = eidx<DIM>(k, i);
           jc[kk] = colk[k];
           const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
-          gather_P<DIM>(G, A, e, js, x[kk]);
+          gather_P<DIM>(G, A, e, js, colk.mass(k), x[kk]);
           la[kk] = lt1[e];
           lb[kk] = lt1[eidx<DIM>(tslot<DIM>(k), js)];
         }
@@ -799,7 +798,7 @@ __global__ __launch_bounds__(kBlock) void k_lim2b(DevGraphT<LT> G, StageArgsT<LT
   if (i >= N) return;
   const LT *__restrict__ lt1 = A.lt1;
   LT *__restrict__ lt2 = A.lt2;
-  const BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
+  BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
   RowCtx<DIM> R;
   load_row<DIM>(G, A, i, A.tau[member(A, i)], R);
   double u1[NC];
@@ -808,6 +807,7 @@ __global__ __launch_bounds__(kBlock) void k_lim2b(DevGraphT<LT> G, StageArgsT<LT
   uint32_t slow = 0;
 #pragma unroll
   for (int ch = 0; ch < C::NCH; ++ch) {
+    jv.fence();
     PIn<DIM> x[C::CH];
     double la[C::CH], lb[C::CH];
     int32_t jc[C::CH];
@@ -817,7 +817,7 @@ __global__ __launch_bounds__(kBlock) void k_lim2b(DevGraphT<LT> G, StageArgsT<LT
       const int64_t e = eidx<DIM>(k, i);
       jc[kk] = jv[k];
       const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
-      gather_P<DIM>(G, A, e, js, x[kk]);
+      gather_P<DIM>(G, A, e, js, jv.mass(k), x[kk]);
       la[kk] = lt1[e];
       lb[kk] = lt1[eidx<DIM>(tslot<DIM>(k), js)];
     }
@@ -868,13 +868,14 @@ __global__ __launch_bounds__(kBlock) void k_root(DevGraphT<LT> G, StageArgsT<LT>
     const int64_t e = q[t];
     const int64_t i = edge_row<DIM>(e);
     const int k = (int)((e >> 6) % (DIM == 2 ? 9 : 27));
-    const int32_t j = row_nbr<DIM>(G, i)[k];
+    const BoxNbr<DIM> nb = row_nbr<DIM>(G, i);
+    const int32_t j = nb[k];
     RowCtx<DIM> R;
     load_row<DIM>(G, A, i, A.tau[member(A, i)], R);
     double u[NC], P[NC];
     load_state<NC>(PASS == 1 ? A.UL : A.U1, N, i, u);
     const Bounds b = load_bounds(A, N, i);
-    compute_P<DIM>(G, A, R, e, j, P);
+    compute_P<DIM>(G, A, R, e, j, nb.mass(k), P);
     double s1 = 1.0;
     if constexpr (PASS == 2) {
       s1 = 1.0 - fmin(A.lt1[e], A.lt1[eidx<DIM>(tslot<DIM>(k), j)]);
@@ -894,7 +895,7 @@ __global__ __launch_bounds__(kBlock) void k_fin(DevGraphT<LT> G, StageArgsT<LT> 
   const int64_t i = row_id();
   if (i >= N) return;
   const LT *__restrict__ lt2 = A.lt2;
-  const BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
+  BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
   RowCtx<DIM> R;
   load_row<DIM>(G, A, i, A.tau[member(A, i)], R);
   const double lam = 1.0 / G.lfac[i];
@@ -902,6 +903,7 @@ __global__ __launch_bounds__(kBlock) void k_fin(DevGraphT<LT> G, StageArgsT<LT> 
   load_state<NC>(A.U1, N, i, u2);
 #pragma unroll
   for (int ch = 0; ch < C::NCH; ++ch) {
+    jv.fence();
     PIn<DIM> x[C::CH];
     double l2a[C::CH], l2b[C::CH];
     int32_t jc[C::CH];
@@ -912,7 +914,7 @@ __global__ __launch_bounds__(kBlock) void k_fin(DevGraphT<LT> G, StageArgsT<LT> 
       jc[kk] = jv[k];
       const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
       const int64_t et = eidx<DIM>(tslot<DIM>(k), js);
-      gather_P<DIM>(G, A, e, js, x[kk]);
+      gather_P<DIM>(G, A, e, js, jv.mass(k), x[kk]);
       l2a[kk] = lt2[e];
       l2b[kk] = lt2[et];
     }

@@ -43,13 +43,11 @@ template <typename LT>
 struct DevGraphT {
   int64_t N;
   int W;
-  // column indices: derived from the box mesh of the row (box_nbr.hpp);
-  // geo has one entry per mesh, seg maps each 256-row block to its mesh
-  // (null for a single mesh)
+  // column indices, m_ij and c_ij: derived from the box mesh of the row
+  // (box_nbr.hpp); geo has one entry per mesh, seg maps each 256-row block
+  // to its mesh (null for a single mesh)
   const BoxGeom *geo;
   const int32_t *seg;
-  const LT *mij;        // W*Np
-  const LT *c0, *c1, *c2;  // W*Np each (c2 unused in 2D)
   const double *mi;     // N
   const double *rmi;    // N: 1 / m_i
   const double *lfac;   // N: |I(i)| - 1 = 1 / lambda_i

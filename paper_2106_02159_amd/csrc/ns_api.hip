@@ -125,14 +125,12 @@ struct ns_solver {
   bool own_stream = false;
   std::vector<void *> allocs;
   int64_t bytes = 0;
-  // graph on the device: one box geometry per mesh (the column indices are
-  // derived from it), m_ij, c_ij
+  // graph on the device: one box geometry per mesh (the kernels derive the
+  // column indices, m_ij and c_ij from it) and the per-node data
   ns::BoxGeom *geo = nullptr;
-  double *mij = nullptr, *c[3] = {nullptr, nullptr, nullptr};
-  // mixed precision: FP32 storage of the graph coefficients and of alpha,
-  // d_ij, F^H and the limiter coefficients (the FP64 arrays stay null)
+  // mixed precision: FP32 storage of alpha, d_ij, F^H and the limiter
+  // coefficients (the FP64 arrays stay null)
   bool mixed = false;
-  float *mijf = nullptr, *cf[3] = {nullptr, nullptr, nullptr};
   float *alphaf = nullptr, *df = nullptr, *FHf = nullptr, *lt1f = nullptr,
         *lt2f = nullptr;
   double *mi = nullptr, *rmi = nullptr, *lfac = nullptr, *rrel = nullptr;
@@ -191,15 +189,13 @@ struct ns_solver {
 
   ns::DevGraph devgraph() const {
     ns::DevGraph g;
-    g.N = N; g.W = W; g.geo = geo; g.seg = seg; g.mij = mij;
-    g.c0 = c[0]; g.c1 = c[1]; g.c2 = c[2] ? c[2] : c[1];
+    g.N = N; g.W = W; g.geo = geo; g.seg = seg;
     g.mi = mi; g.rmi = rmi; g.lfac = lfac; g.rrel = rrel; g.wall = wall;
     return g;
   }
   ns::DevGraphT<float> devgraph32() const {
     ns::DevGraphT<float> g;
-    g.N = N; g.W = W; g.geo = geo; g.seg = seg; g.mij = mijf;
-    g.c0 = cf[0]; g.c1 = cf[1]; g.c2 = cf[2] ? cf[2] : cf[1];
+    g.N = N; g.W = W; g.geo = geo; g.seg = seg;
     g.mi = mi; g.rmi = rmi; g.lfac = lfac; g.rrel = rrel; g.wall = wall;
     return g;
   }
@@ -564,27 +560,52 @@ int ns_graph_export(const ns_graph *g, int32_t *col, double *mij, double *cij,
   return NS_OK;
 }
 
-int ns_graph_stencil_columns(const ns_graph *g, int64_t base, int64_t rows, int32_t *col) {
-  if (!g || !col) return NS_EINVAL;
-  const ns::MeshGraph &m = g->mg;
-  if (rows < m.N || base < 0 || base + rows > INT32_MAX) return NS_EINVAL;
-  ns::BoxGeom geo;
-  geo.base = (int32_t)base;
-  geo.nn = (int32_t)m.N;
-  geo.per = 0;
+extern "C++" {
+namespace {
+// Geometry of a box mesh placed at row `base`: sizes, periodic flags and
+// the graph builder's own 1D mass factors.
+ns::BoxGeom box_geom(const ns::MeshGraph &m, int64_t base) {
+  ns::BoxGeom b{};
+  b.base = (int32_t)base;
+  b.nn = (int32_t)m.N;
+  b.per = 0;
   for (int d = 0; d < 3; ++d) {
-    geo.n[d] = d < m.dim ? (int32_t)m.n[d] : 1;
-    if (d < m.dim && m.periodic[d]) geo.per |= 1 << d;
+    b.n[d] = d < m.dim ? (int32_t)m.n[d] : 1;
+    if (d < m.dim && m.periodic[d]) b.per |= 1 << d;
+    b.m_inner[d] = b.m_end[d] = b.m_off[d] = 1.0;
+    if (d < m.dim) m.m1_values(d, &b.m_inner[d], &b.m_end[d], &b.m_off[d]);
   }
+  return b;
+}
+
+template <int DIM>
+void stencil_rows(const ns::BoxGeom &geo, int64_t rows, int32_t *col, double *mij,
+                  double *cij) {
+  constexpr int W = DIM == 2 ? 9 : 27;
   for (int64_t r = 0; r < rows; ++r) {
-    if (m.dim == 2) {
-      const ns::BoxNbr<2> nb(geo, base + r);
-      for (int k = 0; k < 9; ++k) col[k * rows + r] = nb[k];
-    } else {
-      const ns::BoxNbr<3> nb(geo, base + r);
-      for (int k = 0; k < 27; ++k) col[k * rows + r] = nb[k];
+    const ns::BoxNbr<DIM> nb(&geo, geo.base + r);
+    for (int k = 0; k < W; ++k) {
+      if (col) col[k * rows + r] = nb[k];
+      if (mij) mij[k * rows + r] = nb.mass(k);
+      if (cij) {
+        double c[3];
+        nb.grad(k, c);
+        for (int e = 0; e < DIM; ++e) cij[((int64_t)e * W + k) * rows + r] = c[e];
+      }
     }
   }
+}
+}  // namespace
+}  // extern "C++"
+
+int ns_graph_stencil(const ns_graph *g, int64_t base, int64_t rows, int32_t *col,
+                     double *mij, double *cij) {
+  if (!g) return NS_EINVAL;
+  const ns::MeshGraph &m = g->mg;
+  if (rows < m.N || base < 0 || base + rows > INT32_MAX) return NS_EINVAL;
+  const ns::BoxGeom geo = box_geom(m, base);
+  if (m.dim == 2) stencil_rows<2>(geo, rows, col, mij, cij);
+  else stencil_rows<3>(geo, rows, col, mij, cij);
   return NS_OK;
 }
 
@@ -651,7 +672,6 @@ int64_t footprint(const Layout &Lt, const ns_params *p) {
   int64_t nslip = 0;
   for (const ns::MeshGraph *g : Lt.mgs) nslip += slip_count(*g);
   int64_t b = 0;
-  b += W * Np * L * (1 + dim);                        // m_ij, c_ij
   b += nm * (int64_t)sizeof(ns::BoxGeom);             // box geometry
   b += 4 * N * 8 + N;                                // m_i, 1/m_i, lfac, r_i, wall
   b += 3 * nc * N * 8 + (dim + 5) * N * 8;           // states, aux
@@ -764,13 +784,6 @@ int create_impl(const Layout &Lt, const ns_params *p, void *stream, ns_solver **
     }                                                                       \
   } while (0)
   NS_ALLOC(s->geo, s->nmem);
-  if (s->mixed) {
-    NS_ALLOC(s->mijf, W * Np);
-    for (int k = 0; k < dim; ++k) NS_ALLOC(s->cf[k], W * Np);
-  } else {
-    NS_ALLOC(s->mij, W * Np);
-    for (int k = 0; k < dim; ++k) NS_ALLOC(s->c[k], W * Np);
-  }
   NS_ALLOC(s->mi, N);
   NS_ALLOC(s->rmi, N);
   NS_ALLOC(s->lfac, N);
@@ -810,64 +823,25 @@ int create_impl(const Layout &Lt, const ns_params *p, void *stream, ns_solver **
   e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return bail(NS_EHIP, "stream synchronize");
 
-  // --- upload the graph: generate slot by slot, place into the sliced ELL
-  // layout (entry (k, i) at ((i/64)*W + k)*64 + i%64) on the host, upload;
-  // the column indices are not stored: the kernels derive them from the box
-  // geometry of each mesh
+  // --- the graph: one box geometry per mesh (the kernels derive the column
+  // indices, m_ij and c_ij of every entry from it); |I(i)| per row from the
+  // graph builder's columns
   {
     const int nm = s->nmem;
-    const int kc = (int)(W - 1) / 2;  // slot of the zero offset: the node itself
     auto mend = [&](int r) { return r + 1 < nm ? Lt.base[r + 1] : N; };
     std::vector<int> cnt(N, 0);
-    auto sl = [W](int k, int64_t i) { return ((i >> 6) * W + k) * 64 + (i & 63); };
-    // m_ij and the components of c_ij, one array at a time; member r's rows
-    // are shifted by its first row
-    for (int a = -1; a < dim; ++a) {
-      std::vector<double> sv(W * Np, 0.0);
-      for (int r = 0; r < nm; ++r) {
-        const ns::MeshGraph &m = *Lt.mgs[r];
-        const int64_t b0 = Lt.base[r], Nr = m.N;
-        std::vector<int32_t> col(Nr);
-        std::vector<double> tmp(Nr), cc((size_t)dim * Nr);
-        for (int k = 0; k < W; ++k) {
-          double *cp[3] = {cc.data(), cc.data() + Nr, dim == 3 ? cc.data() + 2 * Nr : nullptr};
-          m.fill_slot(k, a < 0 ? col.data() : nullptr, nullptr, a < 0 ? tmp.data() : nullptr,
-                      a < 0 ? nullptr : cp);
-          const double *src = a < 0 ? tmp.data() : cc.data() + (size_t)a * Nr;
-          for (int64_t i = 0; i < Nr; ++i) sv[sl(k, b0 + i)] = src[i];
-          if (a < 0)
-            for (int64_t i = 0; i < Nr; ++i) cnt[b0 + i] += col[i] >= 0;
-        }
-        // padding rows of a pack: isolated nodes (only the diagonal entry,
-        // m_ii = 1, c_ii = 0)
-        for (int64_t i = b0 + Nr; i < mend(r); ++i) {
-          if (a < 0) cnt[i] = 1;
-          sv[sl(kc, i)] = a < 0 ? 1.0 : 0.0;
-        }
-      }
-      if (s->mixed) {
-        // FP32 storage: rounding to nearest keeps c_ij = -c_ji and m_ij = m_ji
-        const std::vector<float> svf(sv.begin(), sv.end());
-        e = hipMemcpyAsync(a < 0 ? s->mijf : s->cf[a], svf.data(), W * Np * sizeof(float),
-                           hipMemcpyHostToDevice, s->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-      } else {
-        e = hipMemcpyAsync(a < 0 ? s->mij : s->c[a], sv.data(), W * Np * sizeof(double),
-                           hipMemcpyHostToDevice, s->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-      }
-      if (e != hipSuccess) return bail(NS_EHIP, "graph upload failed");
-    }
     std::vector<ns::BoxGeom> geo(nm);
     for (int r = 0; r < nm; ++r) {
       const ns::MeshGraph &m = *Lt.mgs[r];
-      geo[r].base = (int32_t)Lt.base[r];
-      geo[r].nn = (int32_t)m.N;
-      geo[r].per = 0;
-      for (int d = 0; d < 3; ++d) {
-        geo[r].n[d] = d < dim ? (int32_t)m.n[d] : 1;
-        if (d < dim && m.periodic[d]) geo[r].per |= 1 << d;
+      const int64_t b0 = Lt.base[r], Nr = m.N;
+      geo[r] = box_geom(m, b0);
+      std::vector<int32_t> col(Nr);
+      for (int k = 0; k < W; ++k) {
+        m.fill_slot(k, col.data(), nullptr, nullptr, nullptr);
+        for (int64_t i = 0; i < Nr; ++i) cnt[b0 + i] += col[i] >= 0;
       }
+      // padding rows of a pack: isolated nodes (only the diagonal entry)
+      for (int64_t i = b0 + Nr; i < mend(r); ++i) cnt[i] = 1;
     }
     e = hipMemcpyAsync(s->geo, geo.data(), nm * sizeof(ns::BoxGeom), hipMemcpyHostToDevice,
                        s->stream);

@@ -64,28 +64,38 @@ def test_graph_matches_oracle(mesh):
     W.Mesh(3, (2, 2, 2), (0.0,) * 3, (1.0,) * 3, (False,) * 3),
     W.Mesh(3, (5, 3, 4), (0.0,) * 3, (1.0,) * 3, (True, False, True)),
 ], ids=lambda m: f"{m.dim}d{m.n}{m.periodic}")
-def test_kernel_columns_match_graph(mesh):
-    """The kernels derive the column index of every entry from the box mesh
-    instead of loading it: the derived indices equal the graph's (which the
-    test above pins to the oracle), shifted by the mesh's first row in a
-    pack, with isolated padding rows, and the transposed entry of (i, k) is
-    (j, W-1-k)."""
+def test_kernel_stencil_matches_graph(mesh):
+    """The kernels derive the column index, m_ij and c_ij of every entry from
+    the box mesh instead of loading them: the derived entries equal the
+    graph's (which the test above pins to the oracle) bit for bit, shifted by
+    the mesh's first row in a pack, with isolated padding rows (m_ii = 1,
+    c_ii = 0), and the transposed entry of (i, k) is (j, W-1-k)."""
     g = abi.Graph(mesh)
-    col = g.export()["col"]
-    assert np.array_equal(g.stencil_columns(), col)
+    ex = g.export()
+    col = ex["col"]
+    st = g.stencil()
+    assert np.array_equal(st["col"], col)
+    ok = col >= 0
+    assert np.array_equal(st["mij"][ok], ex["mij"][ok])
+    for e in range(mesh.dim):
+        assert np.array_equal(st["cij"][e][ok], ex["cij"][e][ok])
     Wd, N = col.shape
     for k in range(Wd):
         j = col[k]
-        ok = j >= 0
-        assert np.array_equal(col[Wd - 1 - k][j[ok]], np.arange(N)[ok])
+        okk = j >= 0
+        assert np.array_equal(col[Wd - 1 - k][j[okk]], np.arange(N)[okk])
     base, pad = 512, 37
-    c2 = g.stencil_columns(base, N + pad)
-    assert np.array_equal(c2[:, :N], np.where(col >= 0, col + base, -1))
+    s2 = g.stencil(base, N + pad)
+    c2 = s2["col"]
+    assert np.array_equal(c2[:, :N], np.where(ok, col + base, -1))
+    assert np.array_equal(s2["mij"][:, :N][ok], ex["mij"][ok])
+    assert np.array_equal(s2["cij"][:, :, :N][:, ok], ex["cij"][:, ok])
     self_k = Wd // 2
     assert np.array_equal(c2[self_k, N:], base + np.arange(N, N + pad))
     assert np.all(np.delete(c2[:, N:], self_k, axis=0) == -1)
+    assert np.all(s2["mij"][self_k, N:] == 1.0) and np.all(s2["cij"][:, self_k, N:] == 0.0)
     with pytest.raises(abi.NSError):
-        g.stencil_columns(0, N - 1)
+        g.stencil(0, N - 1)
 
 
 def test_graph_exact_antisymmetry():

@@ -1,10 +1,9 @@
-"""Mixed precision (FP32 storage of the graph coefficients, alpha, d_ij,
-F^H and the limiter coefficients; FP64 state, bounds, line search and
+"""Mixed precision (FP32 storage of alpha, d_ij, F^H and the limiter
+coefficients; FP64 graph coefficients, state, bounds, line search and
 arithmetic) against the FP64 oracle.
 
 What is fixed and checked: mass and total energy conserved to round-off
-(c_ij stays antisymmetric and m_ij symmetric after rounding, d_ij and the
-limiter coefficients stay symmetric); every stage admissible (no positivity
+(d_ij and the limiter coefficients stay symmetric after rounding); every stage admissible (no positivity
 violation); the state after 50 SSPRK(3,3) steps of the four-quadrant
 problem within an L1 relative error of 1e-6 in density of the FP64 oracle
 (and reported for momentum and energy); the stage result inside the
