@@ -46,10 +46,10 @@ def kernel_bytes(name: str, dim: int, mixed: bool = False) -> float:
     rows = nc * (2 * n8 + nL)      # U, U^L (or U^(1)) and F^H of the row
     table = {
         "prim": nc * n8 + na * n8,
-        "visc": nc * n8 + (na - 1) * n8 + 1 + eL + nL,
+        "visc": nc * n8 + 3 * n8 + 1 + eL + nL,  # U, a, b, eta (v, p from U)
         "visc_dt": (dim + 3) * n8 + 1 + eL,
         "dt_partial": eL + n8,
-        "lo": eL + nc * n8 + (dim + 2) * n8 + nL + 3 * n8
+        "lo": eL + nc * n8 + 1 * n8 + nL + 3 * n8  # U, Phi (v, p from U), alpha, ...
               + nc * n8 + nc * nL + 3 * n8,
         "lim1": eL + rows + nL + 2 * n8 + 3 * n8 + eL,
         "lim2": (2 * eL + rows + nL + 2 * n8 + 3 * n8 + nc * n8 + eL

@@ -145,6 +145,23 @@ __device__ __forceinline__ double block_min(double v) {
   return v;
 }
 
+// Velocity and pressure of a conserved state.  k_prim stores them per node;
+// the sweeps that gather a neighbour's whole state anyway recompute them
+// with this same function instead of gathering them too.
+template <int DIM>
+__device__ __forceinline__ double vel_pres(const Gas &g, const double *u, double *v,
+                                           double &p) {
+  const double ir = 1.0 / u[0];
+  double m2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) m2 += u[1 + k] * u[1 + k];
+  const double eps = u[DIM + 1] - 0.5 * m2 * ir;  // rho e
+  p = g.gm1 * eps;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) v[k] = u[1 + k] * ir;
+  return eps;
+}
+
 // ---------------------------------------------------------------------------
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_prim(int64_t N,
@@ -154,21 +171,14 @@ __global__ __launch_bounds__(kBlock) void k_prim(int64_t N,
   const int64_t i = plain_id();
   if (i >= N) return;
   using X = Aux<DIM>;
-  const double r = U[i];
-  double m[DIM], m2 = 0.0;
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) {
-    m[k] = U[(1 + k) * N + i];
-    m2 += m[k] * m[k];
-  }
-  const double E = U[(DIM + 1) * N + i];
-  const double ir = 1.0 / r;
-  const double eps = E - 0.5 * m2 * ir;
-  const double p = g.gm1 * eps;
-  const double a = sqrt(g.gamma * p * ir);
+  double u[DIM + 2], v[DIM], p;
+  load_state<DIM + 2>(U, N, i, u);
+  const double r = u[0];
+  const double eps = vel_pres<DIM>(g, u, v, p);
+  const double a = sqrt(g.gamma * p * (1.0 / r));
   const double s = log(eps) - g.gamma * log(r);
 #pragma unroll
-  for (int k = 0; k < DIM; ++k) aux[k * N + i] = m[k] * ir;
+  for (int k = 0; k < DIM; ++k) aux[k * N + i] = v[k];
   aux[X::P * N + i] = p;
   aux[X::A * N + i] = a;
   aux[X::B * N + i] = a * pow(p, -g.ex);
@@ -196,29 +206,31 @@ __global__ __launch_bounds__(kBlock) void k_visc(DevGraphT<LT> G,
   const int64_t i = row_id();
   if (i >= N) return;
   BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
-  double vi[DIM];
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) vi[k] = aux[k * N + i];
-  const double pi = aux[X::P * N + i], ai = aux[X::A * N + i],
-               bi = aux[X::B * N + i];
+  double vi[DIM], pi;
+  const double ai = aux[X::A * N + i], bi = aux[X::B * N + i];
   const bool wall_i = G.wall[i] != 0;
   double etap[NC];
   if constexpr (IND == 0) {
-    const double ri = U[i];
+    double ui[NC];
+    load_state<NC>(U, N, i, ui);
+    const double eps = vel_pres<DIM>(g, ui, vi, pi);  // rho e
+    const double ri = ui[0];
     double m2 = 0.0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-      const double mk = U[(1 + k) * N + i];
-      m2 += mk * mk;
-      etap[1 + k] = mk;
+      m2 += ui[1 + k] * ui[1 + k];
+      etap[1 + k] = ui[1 + k];
     }
-    const double eps = pi / g.gm1;
     const double s = -aux[X::ETA * N + i] / ri;
     const double ie = 1.0 / eps;
     etap[0] = g.gamma - s - m2 / (2.0 * ri * eps);
 #pragma unroll
     for (int k = 0; k < DIM; ++k) etap[1 + k] *= ie;
     etap[NC - 1] = -ri * ie;
+  } else {
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) vi[k] = aux[k * N + i];
+    pi = aux[X::P * N + i];
   }
   double num = 0.0, den = 0.0, scl = 0.0;
 #pragma unroll
@@ -234,14 +246,16 @@ __global__ __launch_bounds__(kBlock) void k_visc(DevGraphT<LT> G,
       jc[kk] = jv[k];
       const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
       jv.grad(k, c[kk]);
-#pragma unroll
-      for (int q = 0; q < DIM; ++q) vj[kk][q] = aux[q * N + js];
-      pj[kk] = aux[X::P * N + js];
       aj[kk] = aux[X::A * N + js];
       bj[kk] = aux[X::B * N + js];
       if constexpr (IND == 0) {
+        // the indicator needs the whole state; v and p follow from it
         load_state<NC>(U, N, js, uj[kk]);
         etaj[kk] = aux[X::ETA * N + js];
+      } else {
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) vj[kk][q] = aux[q * N + js];
+        pj[kk] = aux[X::P * N + js];
       }
     }
 #pragma unroll
@@ -249,6 +263,7 @@ __global__ __launch_bounds__(kBlock) void k_visc(DevGraphT<LT> G,
       const int k = ch * C::CH + kk;
       const int32_t j = jc[kk];
       if (j < 0) continue;
+      if constexpr (IND == 0) vel_pres<DIM>(g, uj[kk], vj[kk], pj[kk]);
       double c2 = 0.0;
 #pragma unroll
       for (int q = 0; q < DIM; ++q) c2 += c[kk][q] * c[kk][q];
@@ -388,11 +403,9 @@ __global__ __launch_bounds__(kBlock) void k_lo(DevGraphT<LT> G, StageArgsT<LT> A
   const LT *__restrict__ alpha = A.alpha;
   const LT *__restrict__ dd = A.d;
   BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
-  double ui[NC], vi[DIM];
+  double ui[NC], vi[DIM], pi;
   load_state<NC>(U, N, i, ui);
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) vi[k] = aux[k * N + i];
-  const double pi = aux[X::P * N + i];
+  vel_pres<DIM>(g, ui, vi, pi);
   const double ali = alpha[i];
   const int mem = member(A, i);
   const double tau = A.tau[mem];
@@ -403,8 +416,7 @@ __global__ __launch_bounds__(kBlock) void k_lo(DevGraphT<LT> G, StageArgsT<LT> A
 #pragma unroll
   for (int ch = 0; ch < C::NCH; ++ch) {
     jv.fence();
-    double c[C::CH][DIM], uj[C::CH][NC], vj[C::CH][DIM], pj[C::CH], phij[C::CH],
-        alj[C::CH], dij[C::CH];
+    double c[C::CH][DIM], uj[C::CH][NC], phij[C::CH], alj[C::CH], dij[C::CH];
     int32_t jc[C::CH];
 #pragma unroll
     for (int kk = 0; kk < C::CH; ++kk) {
@@ -413,10 +425,7 @@ __global__ __launch_bounds__(kBlock) void k_lo(DevGraphT<LT> G, StageArgsT<LT> A
       jc[kk] = jv[k];
       const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
       jv.grad(k, c[kk]);
-      load_state<NC>(U, N, js, uj[kk]);
-#pragma unroll
-      for (int q = 0; q < DIM; ++q) vj[kk][q] = aux[q * N + js];
-      pj[kk] = aux[X::P * N + js];
+      load_state<NC>(U, N, js, uj[kk]);  // v and p follow from it
       phij[kk] = aux[X::PHI * N + js];
       alj[kk] = alpha[js];
       dij[kk] = ld_once(&dd[e]);
@@ -432,8 +441,9 @@ __global__ __launch_bounds__(kBlock) void k_lo(DevGraphT<LT> G, StageArgsT<LT> A
         for (int q = 0; q < NC; ++q) fh[q] -= fci[q];
         continue;
       }
-      double fcj[NC];
-      flux_dot<DIM>(uj[kk], vj[kk], pj[kk], c[kk], fcj);
+      double fcj[NC], vj[DIM], pj;
+      vel_pres<DIM>(g, uj[kk], vj, pj);
+      flux_dot<DIM>(uj[kk], vj, pj, c[kk], fcj);
       const double dk = dij[kk];
       // density of the bar state (eq. bar_state) for the local bounds
       const double rbar = 0.5 * (ui[0] + uj[kk][0]) - (fcj[0] - fci[0]) / (2.0 * dk);
