@@ -45,7 +45,7 @@ def kernel_bytes(name: str, dim: int, mixed: bool = False) -> float:
     n8, nL = 8, L
     rows = nc * (2 * n8 + nL)      # U, U^L (or U^(1)) and F^H of the row
     table = {
-        "prim": nc * n8 + na * n8,
+        "prim": nc * n8 + (na - dim - 1) * n8,  # U -> a, b, eta, Phi
         "visc": nc * n8 + 3 * n8 + 1 + eL + nL,  # U, a, b, eta (v, p from U)
         "visc_dt": (dim + 3) * n8 + 1 + eL,
         "dt_partial": eL + n8,

@@ -145,9 +145,9 @@ __device__ __forceinline__ double block_min(double v) {
   return v;
 }
 
-// Velocity and pressure of a conserved state.  k_prim stores them per node;
-// the sweeps that gather a neighbour's whole state anyway recompute them
-// with this same function instead of gathering them too.
+// Velocity and pressure of a conserved state.  k_prim stores them per node
+// for k_visc without the indicator; the sweeps that gather a neighbour's
+// whole state anyway compute them with this same function instead.
 template <int DIM>
 __device__ __forceinline__ double vel_pres(const Gas &g, const double *u, double *v,
                                            double &p) {
@@ -163,7 +163,9 @@ __device__ __forceinline__ double vel_pres(const Gas &g, const double *u, double
 }
 
 // ---------------------------------------------------------------------------
-template <int DIM>
+// VP: also store v and p (read only by k_visc without the indicator; the
+// other sweeps compute them from the states they gather).
+template <int DIM, bool VP>
 __global__ __launch_bounds__(kBlock) void k_prim(int64_t N,
                                                  const double *__restrict__ U,
                                                  double *__restrict__ aux,
@@ -177,9 +179,11 @@ __global__ __launch_bounds__(kBlock) void k_prim(int64_t N,
   const double eps = vel_pres<DIM>(g, u, v, p);
   const double a = sqrt(g.gamma * p * (1.0 / r));
   const double s = log(eps) - g.gamma * log(r);
+  if constexpr (VP) {
 #pragma unroll
-  for (int k = 0; k < DIM; ++k) aux[k * N + i] = v[k];
-  aux[X::P * N + i] = p;
+    for (int k = 0; k < DIM; ++k) aux[k * N + i] = v[k];
+    aux[X::P * N + i] = p;
+  }
   aux[X::A * N + i] = a;
   aux[X::B * N + i] = a * pow(p, -g.ex);
   aux[X::ETA * N + i] = -r * s;
@@ -1039,8 +1043,12 @@ void stage_impl(const Gas &gas, const DevGraphT<LT> &G, const StageArgsT<LT> &A,
     __VA_ARGS__;                                              \
     after(prof);                                              \
   } while (0)
-  NS_LAUNCH("prim", hipLaunchKernelGGL(k_prim<DIM>, grid, block, 0, s, G.N, A.U,
-                                       A.aux, gas));
+  if (indicator == 0)
+    NS_LAUNCH("prim", hipLaunchKernelGGL((k_prim<DIM, false>), grid, block, 0, s, G.N, A.U,
+                                         A.aux, gas));
+  else
+    NS_LAUNCH("prim", hipLaunchKernelGGL((k_prim<DIM, true>), grid, block, 0, s, G.N, A.U,
+                                         A.aux, gas));
   if (indicator == 0)
     NS_LAUNCH("visc", hipLaunchKernelGGL((k_visc<DIM, 0, SEV, LT>), grid, block, 0, s, G,
                                          A.U, A.aux, A.d, A.alpha, gas));
@@ -1103,7 +1111,7 @@ void dt_impl(const Gas &gas, const DevGraphT<LT> &G, const StageArgsT<LT> &A, do
              void (*after)(void *), void *prof) {
   const dim3 grid = grid_for(G.N), block(kBlock);
   before(prof, "prim");
-  hipLaunchKernelGGL(k_prim<DIM>, grid, block, 0, s, G.N, A.U, A.aux, gas);
+  hipLaunchKernelGGL((k_prim<DIM, true>), grid, block, 0, s, G.N, A.U, A.aux, gas);
   after(prof);
   before(prof, "visc_dt");
   hipLaunchKernelGGL((k_visc<DIM, 2, SEV, LT>), grid, block, 0, s, G, A.U, A.aux, A.d,
