@@ -782,12 +782,16 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraphT<LT> G, StageArgsT<LT>
       for (int kk = 0; kk < C::CH; ++kk) {
         const int k = ch * C::CH + kk;
         if (jc[kk] < 0 || jc[kk] == i) continue;
-        double l2;
+        // s1 = 0 (pass 1 took the whole P): the stored product is 0 and a
+        // zero direction never needs a root, so the search is skipped
+        double l2 = 0.0;
         const double s1 = 1.0 - l[kk];
+        if (s1 != 0.0) {
 #pragma unroll
-        for (int q = 0; q < NC; ++q) P[kk][q] *= s1;
-        if (limit_fast<DIM, SEV>(g, u1, P[kk], b, &l2)) slow |= 1u << k;
-        else l2 *= s1;
+          for (int q = 0; q < NC; ++q) P[kk][q] *= s1;
+          if (limit_fast<DIM, SEV>(g, u1, P[kk], b, &l2)) slow |= 1u << k;
+          else l2 *= s1;
+        }
         st_once(&lt2[eidx<DIM>(k, i)], to_lt_down<LT>(l2));
       }
     }
@@ -822,7 +826,6 @@ __global__ __launch_bounds__(kBlock) void k_lim2b(DevGraphT<LT> G, StageArgsT<LT
 #pragma unroll
   for (int ch = 0; ch < C::NCH; ++ch) {
     jv.fence();
-    PIn<DIM> x[C::CH];
     double la[C::CH], lb[C::CH];
     int32_t jc[C::CH];
 #pragma unroll
@@ -831,7 +834,6 @@ __global__ __launch_bounds__(kBlock) void k_lim2b(DevGraphT<LT> G, StageArgsT<LT
       const int64_t e = eidx<DIM>(k, i);
       jc[kk] = jv[k];
       const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
-      gather_P<DIM>(G, A, e, js, jv.mass(k), x[kk]);
       la[kk] = lt1[e];
       lb[kk] = lt1[eidx<DIM>(tslot<DIM>(k), js)];
     }
@@ -839,13 +841,19 @@ __global__ __launch_bounds__(kBlock) void k_lim2b(DevGraphT<LT> G, StageArgsT<LT
     for (int kk = 0; kk < C::CH; ++kk) {
       const int k = ch * C::CH + kk;
       if (jc[kk] < 0 || jc[kk] == i) continue;
-      double P[NC], l2;
-      make_P<DIM>(R, x[kk], P);
+      double P[NC], l2 = 0.0;
       const double s1 = 1.0 - fmin(la[kk], lb[kk]);
+      // else the stored product is 0 (see k_lim2), and P_ij's inputs are
+      // not gathered
+      if (s1 != 0.0) {
+        PIn<DIM> x;
+        gather_P<DIM>(G, A, eidx<DIM>(k, i), jc[kk], jv.mass(k), x);
+        make_P<DIM>(R, x, P);
 #pragma unroll
-      for (int q = 0; q < NC; ++q) P[q] *= s1;
-      if (limit_fast<DIM, SEV>(g, u1, P, b, &l2)) slow |= 1u << k;
-      else l2 *= s1;
+        for (int q = 0; q < NC; ++q) P[q] *= s1;
+        if (limit_fast<DIM, SEV>(g, u1, P, b, &l2)) slow |= 1u << k;
+        else l2 *= s1;
+      }
       st_once(&lt2[eidx<DIM>(k, i)], to_lt_down<LT>(l2));
     }
   }
@@ -918,7 +926,6 @@ __global__ __launch_bounds__(kBlock) void k_fin(DevGraphT<LT> G, StageArgsT<LT> 
 #pragma unroll
   for (int ch = 0; ch < C::NCH; ++ch) {
     jv.fence();
-    PIn<DIM> x[C::CH];
     double l2a[C::CH], l2b[C::CH];
     int32_t jc[C::CH];
 #pragma unroll
@@ -927,20 +934,24 @@ __global__ __launch_bounds__(kBlock) void k_fin(DevGraphT<LT> G, StageArgsT<LT> 
       const int64_t e = eidx<DIM>(k, i);
       jc[kk] = jv[k];
       const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
-      const int64_t et = eidx<DIM>(tslot<DIM>(k), js);
-      gather_P<DIM>(G, A, e, js, jv.mass(k), x[kk]);
       l2a[kk] = lt2[e];
-      l2b[kk] = lt2[et];
+      l2b[kk] = lt2[eidx<DIM>(tslot<DIM>(k), js)];
     }
 #pragma unroll
     for (int kk = 0; kk < C::CH; ++kk) {
+      const int k = ch * C::CH + kk;
       if (jc[kk] < 0 || jc[kk] == i) continue;
       // lt2 holds l~'_ij (1 - l_ij) with l_ij the symmetric pass-1 limiter;
       // (1 - l_ij) >= 0 and equal at ij and ji, and rounding is monotone, so
       // the smaller stored product is min(l~'_ij, l~'_ji) (1 - l_ij) itself
       const double w = lam * fmin(l2a[kk], l2b[kk]);
+      // w = 0 wherever pass 1 took the whole P_ij (most entries away from
+      // shocks): no contribution, and P_ij's inputs are not gathered
+      if (w == 0.0) continue;
+      PIn<DIM> x;
+      gather_P<DIM>(G, A, eidx<DIM>(k, i), jc[kk], jv.mass(k), x);
       double P[NC];
-      make_P<DIM>(R, x[kk], P);
+      make_P<DIM>(R, x, P);
 #pragma unroll
       for (int q = 0; q < NC; ++q) u2[q] += w * P[q];
     }
