@@ -130,9 +130,10 @@ typedef struct ns_solver ns_solver;
 
 /* Creates a solver on the current HIP device.  `stream` is a hipStream_t to
  * order all work on, or NULL for a stream the solver creates and owns.  All
- * device memory (graph arrays, three state buffers, per-edge d_ij and
- * limiter arrays, per-node scratch, the limiter's root work lists) is
- * allocated here.
+ * device memory (per-node graph data -- m_i, 1/m_i, |I(i)| - 1, r_i, wall
+ * flags; the column indices, m_ij and c_ij are computed in the kernels from
+ * the box mesh -- three state buffers, per-edge d_ij and limiter arrays,
+ * per-node scratch, the limiter's root work lists) is allocated here.
  * Errors: NS_EINVAL for bad parameters or a mesh whose edge count (width x
  * N rounded up to 64) exceeds 2^32 - 1; NS_ENOMEM if the device footprint
  * does not fit; NS_EHIP. */
