@@ -66,6 +66,25 @@ static int cmp_long(const void *a, const void *b) {
 /* value of the 1D hat factor (a = 0: 1 - xi, a = 1: xi) */
 static double hat(int a, double xi) { return a ? xi : 1.0 - xi; }
 
+/* Planes [p0, p1) along a direction of n nodes owned by the calling
+   thread of an OpenMP team (all of them outside a parallel region). */
+static void own_planes(long n, long *p0, long *p1) {
+#ifdef _OPENMP
+  const long t = omp_get_thread_num(), T = omp_get_num_threads();
+#else
+  const long t = 0, T = 1;
+#endif
+  *p0 = t * n / T;
+  *p1 = (t + 1) * n / T;
+}
+
+/* Does cell layer L (nodes on planes L and L+1, wrapped) touch a plane in
+   [p0, p1)? */
+static int layer_touches(long L, long n, long p0, long p1) {
+  const long a = L, b = (L + 1) % n;
+  return (a >= p0 && a < p1) || (b >= p0 && b < p1);
+}
+
 int orc_graph_build(int dim, const long *n, const double *lo, const double *hi,
                     const int *periodic, orc_graph **out) {
   if (dim != 2 && dim != 3) return -1;
@@ -90,35 +109,54 @@ int orc_graph_build(int dim, const long *n, const double *lo, const double *hi,
   for (int d = 0; d < 3; ++d)
     ncell[d] = d < dim ? (g->periodic[d] ? g->n[d] : g->n[d] - 1) : 1;
 
+  /* Every loop over cells below is split by rows: a thread owns the
+     nodes of a range of planes along the last direction D and visits, in
+     the order of the serial loop, only the cell layers touching them,
+     writing only to its own rows.  Each row therefore receives its
+     contributions in exactly the serial order (bit-identical sums). */
+  const int D = dim - 1;
+
   /* --- sparsity: j in I(i) iff phi_i and phi_j share a cell --- */
   const int maxrow = dim == 2 ? 9 : 27;
   long *nb = (long *)malloc(sizeof(long) * N * maxrow);
   int *cnt = (int *)calloc(N, sizeof(int));
-  long kc[3], ka[3];
-  for (kc[2] = 0; kc[2] < ncell[2]; ++kc[2])
-    for (kc[1] = 0; kc[1] < ncell[1]; ++kc[1])
-      for (kc[0] = 0; kc[0] < ncell[0]; ++kc[0]) {
-        long gl[8];
-        for (int a = 0; a < nloc; ++a) {
-          for (int d = 0; d < 3; ++d)
-            ka[d] = d < dim ? (kc[d] + ((a >> d) & 1)) % g->n[d] : 0;
-          gl[a] = nidx(g, ka);
-        }
-        for (int a = 0; a < nloc; ++a)
-          for (int b = 0; b < nloc; ++b) {
-            long i = gl[a], j = gl[b];
-            int found = 0;
-            for (int t = 0; t < cnt[i]; ++t)
-              if (nb[i * maxrow + t] == j) found = 1;
-            if (!found) nb[i * maxrow + cnt[i]++] = j;
+#pragma omp parallel
+  {
+    long p0, p1;
+    own_planes(g->n[D], &p0, &p1);
+    long kc[3], ka[3];
+    for (kc[2] = 0; kc[2] < ncell[2]; ++kc[2])
+      for (kc[1] = 0; kc[1] < ncell[1]; ++kc[1]) {
+        if (!layer_touches(kc[D], g->n[D], p0, p1)) continue;
+        for (kc[0] = 0; kc[0] < ncell[0]; ++kc[0]) {
+          long gl[8];
+          int own[8];
+          for (int a = 0; a < nloc; ++a) {
+            for (int d = 0; d < 3; ++d)
+              ka[d] = d < dim ? (kc[d] + ((a >> d) & 1)) % g->n[d] : 0;
+            gl[a] = nidx(g, ka);
+            own[a] = ka[D] >= p0 && ka[D] < p1;
           }
+          for (int a = 0; a < nloc; ++a) {
+            if (!own[a]) continue;
+            for (int b = 0; b < nloc; ++b) {
+              long i = gl[a], j = gl[b];
+              int found = 0;
+              for (int t = 0; t < cnt[i]; ++t)
+                if (nb[i * maxrow + t] == j) found = 1;
+              if (!found) nb[i * maxrow + cnt[i]++] = j;
+            }
+          }
+        }
       }
+  }
   g->row_ptr = (long *)malloc(sizeof(long) * (N + 1));
   g->row_ptr[0] = 0;
   for (long i = 0; i < N; ++i) g->row_ptr[i + 1] = g->row_ptr[i] + cnt[i];
   const long nnz = g->row_ptr[N];
   g->nnz = nnz;
   g->col = (long *)malloc(sizeof(long) * nnz);
+#pragma omp parallel for schedule(static)
   for (long i = 0; i < N; ++i) {
     qsort(nb + i * maxrow, cnt[i], sizeof(long), cmp_long);
     memcpy(g->col + g->row_ptr[i], nb + i * maxrow, sizeof(long) * cnt[i]);
@@ -126,6 +164,7 @@ int orc_graph_build(int dim, const long *n, const double *lo, const double *hi,
   free(nb);
   free(cnt);
   g->tr = (long *)malloc(sizeof(long) * nnz);
+#pragma omp parallel for schedule(static)
   for (long i = 0; i < N; ++i)
     for (long e = g->row_ptr[i]; e < g->row_ptr[i + 1]; ++e)
       g->tr[e] = find_entry(g, g->col[e], i);
@@ -143,75 +182,94 @@ int orc_graph_build(int dim, const long *n, const double *lo, const double *hi,
   double vol = 1.0;
   for (int d = 0; d < dim; ++d) vol *= g->h[d];
   const double wq = vol / nloc; /* each of the 2^dim points */
-  for (kc[2] = 0; kc[2] < ncell[2]; ++kc[2])
-    for (kc[1] = 0; kc[1] < ncell[1]; ++kc[1])
-      for (kc[0] = 0; kc[0] < ncell[0]; ++kc[0]) {
-        long gl[8];
-        for (int a = 0; a < nloc; ++a) {
-          for (int d = 0; d < 3; ++d)
-            ka[d] = d < dim ? (kc[d] + ((a >> d) & 1)) % g->n[d] : 0;
-          gl[a] = nidx(g, ka);
-        }
-        for (int q = 0; q < nloc; ++q) {
-          double xi[3];
-          for (int d = 0; d < dim; ++d) xi[d] = gp[(q >> d) & 1];
-          double phi[8], grad[8][3];
+#pragma omp parallel
+  {
+    long p0, p1;
+    own_planes(g->n[D], &p0, &p1);
+    long kc[3], ka[3];
+    for (kc[2] = 0; kc[2] < ncell[2]; ++kc[2])
+      for (kc[1] = 0; kc[1] < ncell[1]; ++kc[1]) {
+        if (!layer_touches(kc[D], g->n[D], p0, p1)) continue;
+        for (kc[0] = 0; kc[0] < ncell[0]; ++kc[0]) {
+          long gl[8];
+          int own[8];
           for (int a = 0; a < nloc; ++a) {
-            phi[a] = 1.0;
-            for (int d = 0; d < dim; ++d) phi[a] *= hat((a >> d) & 1, xi[d]);
-            for (int e = 0; e < dim; ++e) {
-              double gv = (((a >> e) & 1) ? 1.0 : -1.0) / g->h[e];
+            for (int d = 0; d < 3; ++d)
+              ka[d] = d < dim ? (kc[d] + ((a >> d) & 1)) % g->n[d] : 0;
+            gl[a] = nidx(g, ka);
+            own[a] = ka[D] >= p0 && ka[D] < p1;
+          }
+          /* entry of (gl[a], gl[b]) for the rows owned here, looked up once
+             per cell; every sum below still runs over the quadrature points
+             in order */
+          long ent[8][8];
+          for (int a = 0; a < nloc; ++a)
+            for (int b = 0; b < nloc; ++b)
+              ent[a][b] = own[a] ? find_entry(g, gl[a], gl[b]) : -1;
+          for (int q = 0; q < nloc; ++q) {
+            double xi[3];
+            for (int d = 0; d < dim; ++d) xi[d] = gp[(q >> d) & 1];
+            double phi[8], grad[8][3];
+            for (int a = 0; a < nloc; ++a) {
+              phi[a] = 1.0;
+              for (int d = 0; d < dim; ++d) phi[a] *= hat((a >> d) & 1, xi[d]);
+              for (int e = 0; e < dim; ++e) {
+                double gv = (((a >> e) & 1) ? 1.0 : -1.0) / g->h[e];
+                for (int d = 0; d < dim; ++d)
+                  if (d != e) gv *= hat((a >> d) & 1, xi[d]);
+                grad[a][e] = gv;
+              }
+            }
+            for (int a = 0; a < nloc; ++a) {
+              if (!own[a]) continue;
+              g->mi[gl[a]] += wq * phi[a];
+              for (int b = 0; b < nloc; ++b) {
+                const long e = ent[a][b];
+                g->mij[e] += wq * (phi[a] * phi[b]);
+                for (int k = 0; k < dim; ++k)
+                  g->cij[(size_t)k * nnz + e] += wq * phi[a] * grad[b][k];
+              }
+            }
+          }
+          /* --- boundary faces on non-periodic walls --- */
+          for (int fdir = 0; fdir < dim; ++fdir) {
+            if (g->periodic[fdir]) continue;
+            for (int side = 0; side < 2; ++side) {
+              if (side == 0 && kc[fdir] != 0) continue;
+              if (side == 1 && kc[fdir] != ncell[fdir] - 1) continue;
+              const double nrm = side ? 1.0 : -1.0;
+              double farea = 1.0;
               for (int d = 0; d < dim; ++d)
-                if (d != e) gv *= hat((a >> d) & 1, xi[d]);
-              grad[a][e] = gv;
-            }
-          }
-          for (int a = 0; a < nloc; ++a) {
-            g->mi[gl[a]] += wq * phi[a];
-            for (int b = 0; b < nloc; ++b) {
-              long e = find_entry(g, gl[a], gl[b]);
-              g->mij[e] += wq * (phi[a] * phi[b]);
-              for (int k = 0; k < dim; ++k)
-                g->cij[(size_t)k * nnz + e] += wq * phi[a] * grad[b][k];
-            }
-          }
-        }
-        /* --- boundary faces on non-periodic walls --- */
-        for (int fdir = 0; fdir < dim; ++fdir) {
-          if (g->periodic[fdir]) continue;
-          for (int side = 0; side < 2; ++side) {
-            if (side == 0 && kc[fdir] != 0) continue;
-            if (side == 1 && kc[fdir] != ncell[fdir] - 1) continue;
-            const double nrm = side ? 1.0 : -1.0;
-            double farea = 1.0;
-            for (int d = 0; d < dim; ++d)
-              if (d != fdir) farea *= g->h[d];
-            const int nfq = 1 << (dim - 1);
-            const double wf = farea / nfq;
-            for (int q = 0; q < nfq; ++q) {
-              double xi[3];
-              int t = 0;
-              for (int d = 0; d < dim; ++d) {
-                if (d == fdir) xi[d] = (double)side;
-                else xi[d] = gp[(q >> (t++)) & 1];
-              }
-              double phi[8];
-              for (int a = 0; a < nloc; ++a) {
-                phi[a] = 1.0;
-                for (int d = 0; d < dim; ++d) phi[a] *= hat((a >> d) & 1, xi[d]);
-              }
-              for (int a = 0; a < nloc; ++a) {
-                g->bnd[(size_t)fdir * N + gl[a]] += wf * phi[a] * nrm;
-                g->bface[(size_t)(2 * fdir + side) * N + gl[a]] += wf * phi[a];
-                for (int b = 0; b < nloc; ++b) {
-                  long e = find_entry(g, gl[a], gl[b]);
-                  g->bpair[(size_t)fdir * nnz + e] += wf * (phi[a] * phi[b]) * nrm;
+                if (d != fdir) farea *= g->h[d];
+              const int nfq = 1 << (dim - 1);
+              const double wf = farea / nfq;
+              for (int q = 0; q < nfq; ++q) {
+                double xi[3];
+                int t = 0;
+                for (int d = 0; d < dim; ++d) {
+                  if (d == fdir) xi[d] = (double)side;
+                  else xi[d] = gp[(q >> (t++)) & 1];
+                }
+                double phi[8];
+                for (int a = 0; a < nloc; ++a) {
+                  phi[a] = 1.0;
+                  for (int d = 0; d < dim; ++d) phi[a] *= hat((a >> d) & 1, xi[d]);
+                }
+                for (int a = 0; a < nloc; ++a) {
+                  if (!own[a]) continue;
+                  g->bnd[(size_t)fdir * N + gl[a]] += wf * phi[a] * nrm;
+                  g->bface[(size_t)(2 * fdir + side) * N + gl[a]] += wf * phi[a];
+                  for (int b = 0; b < nloc; ++b) {
+                    const long e = ent[a][b];
+                    g->bpair[(size_t)fdir * nnz + e] += wf * (phi[a] * phi[b]) * nrm;
+                  }
                 }
               }
             }
           }
         }
       }
+  }
   /* wall nodes: on a face of a non-periodic direction */
   long k[3];
   for (k[2] = 0; k[2] < g->n[2]; ++k[2])
