@@ -169,3 +169,88 @@ def test_full_size_navier_stokes_3d():
         assert np.all(U[0] > 0) and np.all(eps > 0)
     a, b = np.dot(m, Uin[0]), np.dot(m, U3[0])
     assert abs(b - a) <= 1e-12 * a
+
+
+def active_blocks(U_prev, U_next, dim, n, width, count, taken=()):
+    """Block corners around the nodes whose state changed most in one step
+    (the moving shocks and contacts), at least a block width apart from
+    each other and from the blocks already taken."""
+    change = np.abs(U_next[0] - U_prev[0]) / np.abs(U_prev[0]).max()
+    order = np.argsort(change)[::-1]
+    picked = list(taken)
+    count += len(picked)
+    for i in order[:200000]:
+        c = [(int(i) // int(np.prod(n[:d]))) % n[d] for d in range(dim)]
+        b = tuple(int(min(max(c[d] - width // 2, 0), n[d] - width)) for d in range(dim))
+        if all(max(abs(b[d] - p[d]) for d in range(dim)) >= width for p in picked):
+            picked.append(b)
+        if len(picked) == count:
+            break
+    return picked[len(taken):]
+
+
+LATE = {
+    # the schedule's late steps: C2 step 50, C3 step 20
+    "2d": dict(make=lambda: W.four_quadrant_state(4096, seed=0), step=50, width=16,
+               fixed=[(0, 0), (4080, 4080), (2040, 2040), (0, 2040)], n_active=6,
+               n_random=4),
+    "3d": dict(make=lambda: W.shock_tube_state(256, seed=0), step=20, width=8,
+               fixed=[(0, 0, 0), (248, 248, 248), (120, 0, 124)], n_active=4,
+               n_random=2),
+}
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("key", ["2d", "3d"])
+def test_full_size_late_step(key):
+    """The full-size workload stepped by the GPU with its own CFL time steps
+    up to step k-1 (k = 50 in 2D, 20 in 3D); from that state the oracle's
+    time step on the whole mesh (1e-14), then step k with it on both sides:
+    sampled blocks (corners, the most active fronts, seeded interior points)
+    against the oracle on windows, and admissibility and conservation of
+    mass and total energy since the initial state on the whole field."""
+    from oracle import oracle as O
+    cfg = LATE[key]
+    mesh, U0 = cfg["make"]()
+    k = cfg["step"]
+    say("late step", key, mesh.n, "build")
+    g = abi.Graph(mesh)
+    s = abi.Solver(g, gamma=1.4, cfl=0.5)
+    s.set_state(U0)
+    Uin = s.get_state()
+    for _ in range(k - 1):
+        s.step_cfl()
+    cur = s.get_state()
+    say("oracle dt on the whole mesh at step", k - 1)
+    og = O.Graph(mesh.dim, mesh.n, mesh.lo, mesh.hi, mesh.periodic, export=False)
+    tau = og.compute_dt(O.params(cfl=0.5), cur)
+    del og
+    t_gpu = s.compute_dt()
+    say("dt gpu", t_gpu, "oracle", tau)
+    assert t_gpu == pytest.approx(tau, rel=1e-14, abs=0)
+    s.step(tau)
+    nxt = s.get_state()
+    del s
+
+    m = lumped_mass(mesh)
+    dim = mesh.dim
+    assert np.all(nxt[0] > 0)
+    eps = nxt[dim + 1] - 0.5 * (nxt[1:1 + dim] ** 2).sum(axis=0) / nxt[0]
+    assert np.all(eps > 0)
+    for c in (0, dim + 1):
+        a, b = np.dot(m, Uin[c]), np.dot(m, nxt[c])
+        assert abs(b - a) <= 1e-12 * abs(a), (c, a, b)
+
+    w = cfg["width"]
+    scale = state_scale(cur)
+    todo = (list(cfg["fixed"])
+            + active_blocks(cur, nxt, dim, mesh.n, w, cfg["n_active"], cfg["fixed"])
+            + blocks(mesh, [], cfg["n_random"], w, seed=11))
+    # the window oracle projects its input on the walls, which the GPU's
+    # state already satisfies to round-off
+    for b in todo:
+        say("window", b)
+        idx, ref = oracle_window_step(mesh, cur, b, (w,) * dim, tau)
+        err = state_rel_err(nxt[:, idx], ref, scale=scale)
+        say("  err", err.max())
+        assert err.max() <= TOL, (key, k, b, err)

@@ -278,3 +278,47 @@ def test_multigrid_in_the_viscous_dominated_regime(dim):
         assert ig.it_v * 3 <= ij.it_v and ig.it_e * 3 <= ij.it_e
     first, last = its[sizes[0]], its[sizes[-1]]
     assert last[2] <= 1.6 * first[2] + 2 and last[3] <= 1.6 * first[3] + 2
+
+
+# The Navier-Stokes configuration's data (Mach-3 shock tube with seeded 1%
+# density noise, mu = 1e-4, lambda = 0, kappa = 1.4e-4, cv = 2.5, no-slip
+# insulated walls, Jacobi CG, CFL 0.5) at the largest meshes the oracle
+# steps within seconds; cg_rtol as configured (1e-10) and tight (1e-13).
+C3_VISC = dict(mu=1e-4, lam=0.0, kappa=1.4e-4, cv=2.5)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("n,rtol", [(64, 1e-10), (48, 1e-13)])
+def test_strang_c3_configuration(n, rtol):
+    """Two Strang steps (each from the GPU's own state, with the oracle's
+    tau).  Where both CG solves take the same number of iterations the two
+    sides differ by round-off only and the bar is 1e-12; where a count
+    differs by one, the results are two different iterates that both meet
+    ||r|| <= rtol ||b||, and the bar is 10 rtol (the mass-dominated system
+    is well conditioned)."""
+    mesh, U = W.shock_tube_state(n, seed=0)
+    og = O.Graph(3, mesh.n, mesh.lo, mesh.hi, mesh.periodic, export=False)
+    U = og.slip_bc(U)
+    prm = O.params(cfl=0.5)
+    ov = O.visc(cg_rtol=rtol, cg_maxit=20000, **C3_VISC)
+    s = abi.Solver(abi.Graph(mesh), cfl=0.5)
+    s.set_state(U, project=False)
+    s.set_viscous(cg_rtol=rtol, cg_maxit=20000, **C3_VISC)
+    cur = U
+    for k in range(2):
+        tau = og.compute_dt(prm, cur)
+        ref, st, oi = og.strang_step(prm, ov, cur, tau)
+        assert st == 0
+        s.set_state(cur, project=False)
+        s.step_strang(tau)
+        cur = s.get_state()
+        gi = s.parabolic_info()
+        check_info(gi, oi)
+        same = gi.it_v == oi.it_v and gi.it_e == oi.it_e
+        tol = TOL if same else max(TOL, 10.0 * rtol)
+        err = state_rel_err(cur, ref, scale=state_scale(ref))
+        say("C3 configuration", n, "rtol", rtol, "step", k + 1, "err", err.max(),
+            "iters", gi.it_v, gi.it_e, "oracle", oi.it_v, oi.it_e)
+        assert err.max() <= tol, (n, rtol, k, err)
+    eps = cur[4] - 0.5 * (cur[1:4] ** 2).sum(axis=0) / cur[0]
+    assert np.all(cur[0] > 0) and np.all(eps > 0)
