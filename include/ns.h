@@ -9,7 +9,7 @@
  * maximum wave speed, low-order update, local bounds, high-order flux with
  * the approximate inverse mass matrix, convex limiting (Sec. 3, Algorithm 1),
  * SSPRK(3,3) with slip post-processing after every stage (Sec. 4.1-4.2) or
- * non-reflecting post-processing on chosen faces (Sec. 4.3.2), the adaptive
+ * non-reflecting post-processing on chosen faces (Sec. 4.3), the adaptive
  * CFL number of the Remark on high aspect-ratio meshes; the parabolic
  * (viscous) sub-step with matrix-free conjugate gradients (diagonal or
  * single-precision multigrid preconditioner) and the Strang composition of
@@ -259,7 +259,7 @@ int ns_parabolic_info(ns_solver *s, ns_par_info *out);
 /* ---- boundary kinds: slip and non-reflecting faces ----------------------
  * Every face of a non-periodic direction (f = 2*dir + side: side 0 the low
  * end with outward normal -e_dir, side 1 the high end) is slip (the
- * default: eq. slip_bc) or non-reflecting (Sec. 4.3.2) with a far-field
+ * default: eq. slip_bc) or non-reflecting (Sec. 4.3) with a far-field
  * (Dirichlet) state: post-processing by the characteristic variables (eqs.
  * Supersonic_inflow, Subsonic_inflow, Subsonic_outflow, Supersonic_outflow)
  * or by Godunov's method (eq. Godunov_bc, the exact Riemann solution at the
@@ -448,6 +448,40 @@ enum {
                         /*        finder, limiter passes 1 and 2          */
 };
 int ns_get_debug(ns_solver *s, int what, double *out);
+
+/* ---- statistics ------------------------------------------------------- *
+ * Admissibility of the current state (Sec. 3: rho > 0 and internal energy
+ * > 0, preserved by every stage, Lemma 3.1) and the activity of the convex
+ * limiter of Sec. 3.3 in the last forward-Euler stage run (the last stage
+ * of the last step, or ns_fe_stage): l_ij = min(l~_ij, l~_ji) is the
+ * symmetric pass-1 limiter, l'_ij the pass-2 one; an entry counts as limited
+ * after pass 2 when the fraction of P_ij finally applied,
+ * l_ij + l'_ij (1 - l_ij), is below 1.  The parabolic counts are those of
+ * the last parabolic step (0 before any). */
+typedef struct ns_stats_t {
+  double min_rho;      /* min_i rho_i of the current state                  */
+  double min_eps;      /* min_i E_i - |m_i|^2 / (2 rho_i) (internal energy
+                          per unit volume)                                  */
+  int64_t argmin_rho;  /* first node attaining min_rho                      */
+  int64_t argmin_eps;  /* first node attaining min_eps                      */
+  int64_t edges;       /* off-diagonal stencil entries (i != j)             */
+  int64_t limited1;    /* entries with l_ij < 1 after pass 1; -1 without
+                          convex limiting or before the first stage         */
+  int64_t limited2;    /* entries still limited after pass 2; -1 unless
+                          two passes have run                               */
+  int64_t roots1;      /* entries whose pass-1 line search needed the root
+                          of the entropy bound (-1 as limited1)             */
+  int64_t roots2;      /* same, pass 2 (-1 as limited2)                     */
+  int cg_it_v, cg_it_e, cg_it_l;  /* CG iterations of the last parabolic
+                                     step: velocity, energy, low-order    */
+  int fct;             /* 1 if that step used the limited internal energy   */
+  double min_eH;       /* its minimum Crank-Nicolson internal energy        */
+} ns_stats_t;
+/* Computes the statistics on the device (a reduction over all rows) and
+ * waits for it; device scratch for the partial results (about 57 KB) is
+ * allocated from the stream-ordered pool for the call.  NS_ESTATE without
+ * a state; NS_ENOMEM if the scratch does not fit. */
+int ns_stats(ns_solver *s, ns_stats_t *out);
 
 /* ---- timing and diagnostics ------------------------------------------- */
 /* Waits for all work queued on the solver's stream. */

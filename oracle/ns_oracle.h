@@ -76,6 +76,7 @@ void orc_graph_free(orc_graph *g);
 long orc_graph_N(const orc_graph *g);
 /* Number of OpenMP threads the row loops use (1 without OpenMP). */
 int orc_num_threads(void);
+void orc_set_num_threads(int n);
 long orc_graph_nnz(const orc_graph *g);
 /* Copies the graph out into caller-owned arrays (any may be NULL). */
 void orc_graph_export(const orc_graph *g, long *row_ptr, long *col, long *tr,
@@ -104,7 +105,7 @@ int orc_ssprk3_step(const orc_graph *g, const orc_params *p, const double *U,
                     double tau, double *Uout);
 /* ---- boundary post-processing with non-reflecting faces (ns_oracle_bc.c)
  * Faces f = 2*dir + side of non-periodic directions are slip or
- * non-reflecting (Sec. 4.3.2).  A node lies in the slip set if some slip face
+ * non-reflecting (Sec. 4.3).  A node lies in the slip set if some slip face
  * touches it, in the non-reflecting set if some non-reflecting face does;
  * its normal in each set is int phi_i n over that set's faces, normalised
  * (eq. def_ns_nio).  After a stage the non-reflecting post-processing runs
@@ -119,8 +120,8 @@ typedef struct orc_boundary {
   double state[6][5];   /* far-field state of each non-reflecting face:    */
                         /* rho, m (dim components), E                      */
 } orc_boundary;
-/* Exact Riemann problem of the gamma-law gas in 1D (Sec. 4.3.2 Godunov
- * variant): star pressure by bisection on the monotone pressure function,
+/* Exact Riemann problem of the gamma-law gas in 1D (Sec. 4.3.1, Godunov's
+ * method): star pressure by bisection on the monotone pressure function,
  * star velocity, and the solution at x/t = xi.  side_out is -1 if xi lies
  * left of the contact, +1 if right.  Returns 0, or 1 if the data generate
  * vacuum (no positive star pressure). */

@@ -42,7 +42,7 @@ EXPORTED = [
     "ns_server_stats_get", "ns_server_error", "ns_pack_footprint", "ns_pack_create",
     "ns_pack_destroy", "ns_pack_set_state", "ns_pack_get_state", "ns_pack_step_cfl_async",
     "ns_pack_inflight", "ns_pack_finish", "ns_pack_error", "ns_set_boundary",
-    "ns_step_adaptive",
+    "ns_step_adaptive", "ns_stats",
 ]
 
 
@@ -106,6 +106,7 @@ def lib() -> C.CDLL:
             "ns_step_strang": (C.c_int, [vp, C.c_double]),
             "ns_step_strang_cfl": (C.c_int, [vp, dp]),
             "ns_parabolic_info": (C.c_int, [vp, C.POINTER(ParInfo)]),
+            "ns_stats": (C.c_int, [vp, C.POINTER(Stats)]),
             "ns_step_cfl_async": (C.c_int, [vp, C.c_int]),
             "ns_query": (C.c_int, [vp, C.POINTER(C.c_int)]),
             "ns_inflight": (C.c_int, [vp, C.POINTER(C.c_int)]),
@@ -220,6 +221,15 @@ PC_JACOBI, PC_GMG = 0, 1
 
 class ParInfo(C.Structure):
     _fields_ = [("it_v", C.c_int), ("it_e", C.c_int), ("it_l", C.c_int),
+                ("fct", C.c_int), ("min_eH", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("min_rho", C.c_double), ("min_eps", C.c_double),
+                ("argmin_rho", C.c_int64), ("argmin_eps", C.c_int64),
+                ("edges", C.c_int64), ("limited1", C.c_int64), ("limited2", C.c_int64),
+                ("roots1", C.c_int64), ("roots2", C.c_int64),
+                ("cg_it_v", C.c_int), ("cg_it_e", C.c_int), ("cg_it_l", C.c_int),
                 ("fct", C.c_int), ("min_eH", C.c_double)]
 
 
@@ -477,6 +487,11 @@ class Solver:
         info = ParInfo()
         self._check(lib().ns_parabolic_info(self.h, C.byref(info)))
         return info
+
+    def stats(self) -> Stats:
+        out = Stats()
+        self._check(lib().ns_stats(self.h, C.byref(out)))
+        return out
 
     # -- asynchronous stepping ---------------------------------------------
     def step_cfl_async(self, nsteps: int):

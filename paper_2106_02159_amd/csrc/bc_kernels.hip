@@ -1,4 +1,5 @@
-// bc_kernels.hip -- non-reflecting boundary post-processing (Sec. 4.3.2):
+// bc_kernels.hip -- non-reflecting boundary post-processing (Sec. 4.3:
+// Godunov's method, Sec. 4.3.1; characteristic variables, Sec. 4.3.2):
 // one lane per listed boundary node, after each forward-Euler stage.
 //
 // Characteristic variables (gamma-law, locally isentropic flow): with the

@@ -1040,6 +1040,111 @@ __global__ __launch_bounds__(kBlock) void k_check_state(int64_t N,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Diagnostics (ns_stats): minimum density and internal energy of a state and
+// the limiter activity of the last stage.  Rows are strided over a fixed grid
+// so that the partial results need kStatsParts slots whatever N is.
+struct MinArg {
+  double v;
+  int64_t i;
+};
+__device__ __forceinline__ MinArg min_arg(MinArg a, MinArg b) {
+  // smaller value, ties to the smaller index (NaN never wins)
+  return (b.v < a.v || (b.v == a.v && b.i < a.i)) ? b : a;
+}
+__device__ __forceinline__ MinArg shfl_min_arg(MinArg a, int off) {
+  MinArg b;
+  b.v = __shfl_xor(a.v, off);
+  b.i = __shfl_xor(a.i, off);
+  return min_arg(a, b);
+}
+
+// Block reduction of the stats tuple; thread 0 holds the result.
+__device__ __forceinline__ void block_stats(MinArg &r, MinArg &e, double &c0, double &c1,
+                                            double &c2) {
+  __shared__ MinArg sr[kBlock / 64], se[kBlock / 64];
+  __shared__ double sc[3][kBlock / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    r = shfl_min_arg(r, off);
+    e = shfl_min_arg(e, off);
+    c0 += __shfl_xor(c0, off);
+    c1 += __shfl_xor(c1, off);
+    c2 += __shfl_xor(c2, off);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    sr[wid] = r; se[wid] = e; sc[0][wid] = c0; sc[1][wid] = c1; sc[2][wid] = c2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / 64; ++w) {
+      r = min_arg(r, sr[w]);
+      e = min_arg(e, se[w]);
+      c0 += sc[0][w]; c1 += sc[1][w]; c2 += sc[2][w];
+    }
+  }
+}
+
+// part[b*7 + ...] = min rho, its node, min eps, its node, off-diagonal
+// entries, entries with l < 1 after pass 1, entries with l + l'(1 - l) < 1
+// after pass 2 (counts as doubles: exact below 2^53).
+template <int DIM, typename LT>
+__global__ __launch_bounds__(kBlock) void k_stats_partial(DevGraphT<LT> G,
+                                                          const double *__restrict__ U,
+                                                          const LT *__restrict__ lt1,
+                                                          const LT *__restrict__ lt2,
+                                                          int mode, double *__restrict__ part) {
+  constexpr int NC = DIM + 2, W = DIM == 2 ? 9 : 27;
+  const int64_t N = G.N;
+  MinArg r{INFINITY, INT64_MAX}, e{INFINITY, INT64_MAX};
+  double cnt = 0.0, c1 = 0.0, c2 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * kBlock) {
+    double u[NC];
+    load_state<NC>(U, N, i, u);
+    double m2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) m2 += u[1 + k] * u[1 + k];
+    r = min_arg(r, MinArg{u[0], i});
+    e = min_arg(e, MinArg{u[NC - 1] - 0.5 * m2 / u[0], i});
+    const BoxNbr<DIM> nb = row_nbr<DIM>(G, i);
+    for (int k = 0; k < W; ++k) {
+      const int32_t j = nb[k];
+      if (j < 0 || j == i) continue;
+      cnt += 1.0;
+      if (mode == 0) continue;
+      const int64_t ea = eidx<DIM>(k, i), eb = eidx<DIM>(tslot<DIM>(k), j);
+      const double l = fmin((double)lt1[ea], (double)lt1[eb]);
+      if (l < 1.0) c1 += 1.0;
+      if (mode == 2 && l + fmin((double)lt2[ea], (double)lt2[eb]) < 1.0) c2 += 1.0;
+    }
+  }
+  block_stats(r, e, cnt, c1, c2);
+  if (threadIdx.x == 0) {
+    double *o = part + 7 * (int64_t)blockIdx.x;
+    o[0] = r.v; o[1] = (double)r.i; o[2] = e.v; o[3] = (double)e.i;
+    o[4] = cnt; o[5] = c1; o[6] = c2;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_stats_final(const double *__restrict__ part,
+                                                        int nparts, double *__restrict__ out) {
+  MinArg r{INFINITY, INT64_MAX}, e{INFINITY, INT64_MAX};
+  double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += kBlock) {
+    const double *o = part + 7 * (int64_t)b;
+    r = min_arg(r, MinArg{o[0], (int64_t)o[1]});
+    e = min_arg(e, MinArg{o[2], (int64_t)o[3]});
+    c0 += o[4]; c1 += o[5]; c2 += o[6];
+  }
+  block_stats(r, e, c0, c1, c2);
+  if (threadIdx.x == 0) {
+    out[0] = r.v; out[1] = (double)r.i; out[2] = e.v; out[3] = (double)e.i;
+    out[4] = c0; out[5] = c1; out[6] = c2;
+  }
+}
+
 inline dim3 grid_for(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
 
 template <int DIM, int SEV, typename LT>
@@ -1228,6 +1333,25 @@ void launch_clear_flags(int *flags, hipStream_t s, int n) {
   hipLaunchKernelGGL(k_clear_flags, dim3((unsigned)((4 * n + 63) / 64)), dim3(64), 0, s,
                      flags, n);
 }
+
+template <typename LT>
+int launch_stats(int dim, const DevGraphT<LT> &g, const double *U, const LT *lt1,
+                 const LT *lt2, int mode, double *part, double *out, hipStream_t s) {
+  const int nparts = (int)std::min<int64_t>((g.N + kBlock - 1) / kBlock, kStatsParts);
+  if (dim == 2)
+    hipLaunchKernelGGL((k_stats_partial<2, LT>), dim3(nparts), dim3(kBlock), 0, s, g, U, lt1,
+                       lt2, mode, part);
+  else
+    hipLaunchKernelGGL((k_stats_partial<3, LT>), dim3(nparts), dim3(kBlock), 0, s, g, U, lt1,
+                       lt2, mode, part);
+  hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(kBlock), 0, s, part, nparts, out);
+  return nparts;
+}
+template int launch_stats<double>(int, const DevGraphT<double> &, const double *,
+                                  const double *, const double *, int, double *, double *,
+                                  hipStream_t);
+template int launch_stats<float>(int, const DevGraphT<float> &, const double *, const float *,
+                                 const float *, int, double *, double *, hipStream_t);
 
 void launch_check_state(int dim, int64_t N, const double *U, int *flags,
                         hipStream_t s) {

@@ -128,6 +128,16 @@ void launch_add_scalar(double *acc, const double *v, hipStream_t s,
 // (bandwidth and counter calibration)
 void launch_copy(const void *src, void *dst, int64_t n16, int word,
                  hipStream_t s);
+// Diagnostics of a state U (nc*N, on the device) and of the limiter arrays
+// of the last stage: out[0..6] = min rho, its node, min (E - |m|^2/(2 rho)),
+// its node, off-diagonal entries, entries with l_ij < 1 after pass 1,
+// entries with l_ij + l'_ij (1 - l_ij) < 1 after pass 2 (mode 0: no limiter
+// arrays, counts 0; 1: pass 1 only; 2: both passes).  part must hold
+// 7 * kStatsParts doubles; returns the number of partial slots used.
+constexpr int kStatsParts = 1024;
+template <typename LT>
+int launch_stats(int dim, const DevGraphT<LT> &g, const double *U, const LT *lt1,
+                 const LT *lt2, int mode, double *part, double *out, hipStream_t s);
 void launch_clear_flags(int *flags, hipStream_t s, int n = 1);  // n groups of 4
 void launch_check_state(int dim, int64_t N, const double *U, int *flags,
                         hipStream_t s);

@@ -123,6 +123,7 @@ struct ns_solver {
   int32_t *seg = nullptr, *mblk = nullptr;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  int device = 0;  // the HIP device current at creation
   std::vector<void *> allocs;
   int64_t bytes = 0;
   // graph on the device: one box geometry per mesh (the kernels derive the
@@ -175,6 +176,7 @@ struct ns_solver {
   bool async_open = false;
   double htau[1] = {0.0};
   int last_out = 1;        // buffer holding the last stage output
+  bool stage_ran = false;  // a stage has run: its limiter arrays hold data
   // parabolic step (allocated by ns_set_viscous)
   bool viscous = false;
   ns_viscous vprm{};
@@ -294,6 +296,7 @@ int read_flags(ns_solver *s) {
 
 void run_stage(ns_solver *s, int in, int out, double sa, double sb, int check,
                bool auto_dt) {
+  s->stage_ran = true;
   if (s->mixed)
     ns::launch_stage(s->dim, s->gas, s->devgraph32(), s->args32(in, out, sa, sb, check),
                      s->prm.indicator, s->prm.limiter, s->prm.passes, auto_dt,
@@ -772,6 +775,7 @@ int create_impl(const Layout &Lt, const ns_params *p, void *stream, ns_solver **
     s->own_stream = true;
   }
   s->prof.stream = s->stream;
+  s->device = ns::current_device();
   const int64_t N = s->N, W = s->W, nc = s->nc, dim = s->dim, Np = s->Np;
   const int64_t nblocks = (N + ns::kBlock - 1) / ns::kBlock;
 #define NS_ALLOC(ptr, count)                                                \
@@ -1641,6 +1645,63 @@ int ns_get_debug(ns_solver *s, int what, double *out) {
         out[k * N + i] = tmp[((i >> 6) * W + k) * 64 + (i & 63)];
   }
   return NS_OK;
+}
+
+extern "C++" {
+namespace {
+// Fills *out from the current state and the last stage's limiter arrays;
+// part holds 7 * kStatsParts + 7 doubles of device scratch (the last 7 the
+// result).  Synchronises the solver's stream.
+int stats_into(ns_solver *s, double *part, ns_stats_t *out) {
+  const int lim = s->prm.limiter == NS_LIM_CONVEX && s->stage_ran;
+  const int mode = lim ? (s->prm.passes == 2 ? 2 : 1) : 0;
+  double *res = part + 7 * ns::kStatsParts;
+  const double *U = s->S[s->cur];
+  if (s->mixed)
+    ns::launch_stats(s->dim, s->devgraph32(), U, s->lt1f, s->lt2f, mode, part, res, s->stream);
+  else
+    ns::launch_stats(s->dim, s->devgraph(), U, s->lt1, s->lt2, mode, part, res, s->stream);
+  double h[7];
+  uint32_t c[2] = {0, 0};
+  hipError_t e = hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c, s->qcnt, sizeof(c), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return s->hipfail(e, "statistics");
+  *out = ns_stats_t{};
+  out->min_rho = h[0];
+  out->argmin_rho = (int64_t)h[1];
+  out->min_eps = h[2];
+  out->argmin_eps = (int64_t)h[3];
+  out->edges = (int64_t)h[4];
+  out->limited1 = mode >= 1 ? (int64_t)h[5] : -1;
+  out->limited2 = mode == 2 ? (int64_t)h[6] : -1;
+  out->roots1 = lim ? (int64_t)c[0] : -1;
+  out->roots2 = mode == 2 ? (int64_t)c[1] : -1;
+  out->cg_it_v = s->pinfo.it_v;
+  out->cg_it_e = s->pinfo.it_e;
+  out->cg_it_l = s->pinfo.it_l;
+  out->fct = s->pinfo.fct;
+  out->min_eH = s->pinfo.min_eH;
+  return NS_OK;
+}
+}  // namespace
+}  // extern "C++"
+
+int ns_stats(ns_solver *s, ns_stats_t *out) {
+  if (!s || !out) return NS_EINVAL;
+  if (!s->has_state) return s->fail(NS_ESTATE, "no state set");
+  double *part = nullptr;
+  hipError_t e = hipMallocAsync((void **)&part, (7 * ns::kStatsParts + 7) * sizeof(double),
+                                s->stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return s->fail(NS_ENOMEM, "statistics scratch does not fit");
+  }
+  const int rc = stats_into(s, part, out);
+  (void)hipFreeAsync(part, s->stream);
+  return rc;
 }
 
 int ns_sync(ns_solver *s) {

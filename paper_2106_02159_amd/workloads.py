@@ -230,7 +230,7 @@ def serving_requests(count: int = 256, seed: int = 0, nmin: int = 64,
 def nr_vortex_state(n: int = 80, mach: float = 0.5, vbar: float = 0.75, r0: float = 0.25,
                     gamma: float = 1.4):
     """Vortex convected through [-1,1]^2 by a uniform stream (the
-    non-reflecting boundary tests of the paper's Sec. 5): rho = 1,
+    non-reflecting boundary tests of the paper's Sec. 6.2): rho = 1,
     v = v_inf + vbar/r0 psi(|x|) (-y, x), p = p_inf - rho vbar^2 psi^2 / 2,
     psi(r) = exp((1 - r^2/r0^2)/2), v_inf = (1, 0), a_inf = 1/mach,
     p_inf = a_inf^2/gamma; centre 0 and r0 = 0.25 (not given in the paper).

@@ -1,4 +1,4 @@
-"""Non-reflecting boundaries (Sec. 4.3.2) on the GPU: the HIP path through
+"""Non-reflecting boundaries (Sec. 4.3) on the GPU: the HIP path through
 the C ABI against the oracle step by step (characteristic variables and
 Godunov's method; all faces non-reflecting, mixed slip / non-reflecting
 faces in 2D and 3D, supersonic inflow); an all-slip boundary equal to the

@@ -1,5 +1,5 @@
 """Pins of the oracle's boundary post-processing with non-reflecting faces
-(Sec. 4.3.2): the exact Riemann solver against published exact solutions
+(Sec. 4.3): the exact Riemann solver against published exact solutions
 and the jump relations it must satisfy; the characteristic-variable cases
 against the invariants that define them (eqs. Supersonic_inflow,
 Subsonic_inflow, Subsonic_outflow, Supersonic_outflow); admissibility of
