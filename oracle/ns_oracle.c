@@ -299,6 +299,15 @@ int orc_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Threads of the following parallel loops (timing the oracle on n cores). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
 long orc_graph_nnz(const orc_graph *g) { return g->nnz; }
 
 void orc_graph_export(const orc_graph *g, long *row_ptr, long *col, long *tr,

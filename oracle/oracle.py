@@ -99,6 +99,7 @@ def lib():
         L.orc_graph_nnz.argtypes = [C.c_void_p]
         L.orc_graph_nnz.restype = C.c_long
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
         L.orc_graph_export.argtypes = [C.c_void_p] + [C.c_void_p] * 9
         L.orc_pressure.argtypes = [C.c_double, C.c_int, dp]
         L.orc_pressure.restype = C.c_double
@@ -145,6 +146,11 @@ def _dp(a: np.ndarray):
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads used by the oracle's parallel row loops from now on."""
+    lib().orc_set_num_threads(int(n))
 
 
 def params(gamma=1.4, cfl=0.5, indicator=IND_ENTROPY, limiter=LIM_CONVEX,
