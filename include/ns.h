@@ -483,6 +483,21 @@ typedef struct ns_stats_t {
  * a state; NS_ENOMEM if the scratch does not fit. */
 int ns_stats(ns_solver *s, ns_stats_t *out);
 
+/* ns_stats for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same statistics, bit for bit, with the partial results kept in a
+ * fixed array of 7 * 1024 + 7 doubles (about 57 KB) that the library holds
+ * in each device's memory until the process ends; the kernels stride over
+ * the rows with at most 1024 workgroups, so every mesh fits.  No
+ * hipMalloc/hipFree; the device address of the array is looked up once per
+ * device on the first call there.  Every call on one GPU shares that
+ * GPU's array (each call overwrites the slots it reads, nothing needs to
+ * start at zero): calls that overlap on one GPU -- from several threads,
+ * or on solvers with different streams -- race.  Waits for the solver's
+ * stream; NS_ESTATE without a state; NS_EHIP if the array's address
+ * cannot be found. */
+int ns_stats_noalloc(ns_solver *s, ns_stats_t *out);
+
 /* ---- timing and diagnostics ------------------------------------------- */
 /* Waits for all work queued on the solver's stream. */
 int ns_sync(ns_solver *s);

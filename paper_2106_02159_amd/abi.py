@@ -42,7 +42,7 @@ EXPORTED = [
     "ns_server_stats_get", "ns_server_error", "ns_pack_footprint", "ns_pack_create",
     "ns_pack_destroy", "ns_pack_set_state", "ns_pack_get_state", "ns_pack_step_cfl_async",
     "ns_pack_inflight", "ns_pack_finish", "ns_pack_error", "ns_set_boundary",
-    "ns_step_adaptive", "ns_stats",
+    "ns_step_adaptive", "ns_stats", "ns_stats_noalloc",
 ]
 
 
@@ -107,6 +107,7 @@ def lib() -> C.CDLL:
             "ns_step_strang_cfl": (C.c_int, [vp, dp]),
             "ns_parabolic_info": (C.c_int, [vp, C.POINTER(ParInfo)]),
             "ns_stats": (C.c_int, [vp, C.POINTER(Stats)]),
+            "ns_stats_noalloc": (C.c_int, [vp, C.POINTER(Stats)]),
             "ns_step_cfl_async": (C.c_int, [vp, C.c_int]),
             "ns_query": (C.c_int, [vp, C.POINTER(C.c_int)]),
             "ns_inflight": (C.c_int, [vp, C.POINTER(C.c_int)]),
@@ -491,6 +492,11 @@ class Solver:
     def stats(self) -> Stats:
         out = Stats()
         self._check(lib().ns_stats(self.h, C.byref(out)))
+        return out
+
+    def stats_noalloc(self) -> Stats:
+        out = Stats()
+        self._check(lib().ns_stats_noalloc(self.h, C.byref(out)))
         return out
 
     # -- asynchronous stepping ---------------------------------------------

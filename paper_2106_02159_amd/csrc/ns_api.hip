@@ -1704,6 +1704,56 @@ int ns_stats(ns_solver *s, ns_stats_t *out) {
   return rc;
 }
 
+// ---- statistics without allocation ------------------------------------
+// The partial results of ns_stats_noalloc live in this fixed array, one copy
+// in each device's memory for as long as the process runs.  In host code its
+// name only stands in for the device array: the device address is looked up
+// once per device with hipGetSymbolAddress and kept in g_scratch.
+static __device__ __align__(256) double scratch[7 * ns::kStatsParts + 7];
+
+extern "C++" {
+namespace {
+std::mutex g_scratch_mu;
+std::vector<double *> g_scratch;  // index: device; null until looked up
+
+// Device address of `scratch` on device dev, which must be current.
+hipError_t scratch_address(int dev, double **p) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch.size() <= dev) g_scratch.resize(dev + 1, nullptr);
+  if (!g_scratch[dev]) {
+    void *q = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[dev] = static_cast<double *>(q);
+  }
+  *p = g_scratch[dev];
+  return hipSuccess;
+}
+}  // namespace
+}  // extern "C++"
+
+int ns_stats_noalloc(ns_solver *s, ns_stats_t *out) {
+  if (!s || !out) return NS_EINVAL;
+  if (!s->has_state) return s->fail(NS_ESTATE, "no state set");
+  // the statistics kernels stride over the rows with at most kStatsParts
+  // workgroups, so the partial results of any mesh fit in `scratch`
+  static_assert(sizeof(scratch) == (7 * ns::kStatsParts + 7) * sizeof(double),
+                "statistics scratch size");
+  const int prev = ns::current_device();
+  if (prev != s->device) ns::use_device(s->device);
+  double *part = nullptr;
+  int rc = NS_OK;
+  const hipError_t e = scratch_address(s->device, &part);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    rc = s->fail(NS_EHIP, std::string("statistics scratch lookup: ") + hipGetErrorString(e));
+  } else {
+    rc = stats_into(s, part, out);
+  }
+  if (prev != s->device) ns::use_device(prev);
+  return rc;
+}
+
 int ns_sync(ns_solver *s) {
   if (!s) return NS_EINVAL;
   hipError_t e = hipStreamSynchronize(s->stream);
