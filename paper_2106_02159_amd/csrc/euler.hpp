@@ -14,6 +14,7 @@ struct Gas {
   double ex;       // (gamma - 1) / (2 gamma)
   double inv_ex;   // 2 gamma / (gamma - 1)
   double cg;       // (gamma + 1) / (2 gamma)
+  double lgm1;     // log(gamma - 1)
   int seven;       // 1 when gamma == 7/5
 };
 

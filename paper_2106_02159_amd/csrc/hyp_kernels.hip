@@ -178,14 +178,17 @@ __global__ __launch_bounds__(kBlock) void k_prim(int64_t N,
   const double r = u[0];
   const double eps = vel_pres<DIM>(g, u, v, p);
   const double a = sqrt(g.gamma * p * (1.0 / r));
-  const double s = log(eps) - g.gamma * log(r);
+  // log p = log(gamma - 1) + log(rho e): one logarithm serves the specific
+  // entropy and p^(-(gamma-1)/(2 gamma)) = exp(-ex log p)
+  const double le = log(eps);
+  const double s = le - g.gamma * log(r);
   if constexpr (VP) {
 #pragma unroll
     for (int k = 0; k < DIM; ++k) aux[k * N + i] = v[k];
     aux[X::P * N + i] = p;
   }
   aux[X::A * N + i] = a;
-  aux[X::B * N + i] = a * pow(p, -g.ex);
+  aux[X::B * N + i] = a * exp(-g.ex * (g.lgm1 + le));
   aux[X::ETA * N + i] = -r * s;
   aux[X::PHI * N + i] = exp(s);
 }

@@ -758,6 +758,7 @@ int create_impl(const Layout &Lt, const ns_params *p, void *stream, ns_solver **
   s->gas.ex = (gm - 1.0) / (2.0 * gm);
   s->gas.inv_ex = 2.0 * gm / (gm - 1.0);
   s->gas.cg = (gm + 1.0) / (2.0 * gm);
+  s->gas.lgm1 = std::log(gm - 1.0);
   s->gas.seven = gm == 1.4 ? 1 : 0;
 
   auto bail = [&](int code, const std::string &msg) {
