@@ -50,6 +50,9 @@ extern "C" {
 #define NS_ESTATE (-7)          /* no state has been set                     */
 #define NS_ECG (-8)             /* a CG solve of the parabolic step did not
                                    converge within its iteration limit      */
+#define NS_EABORT (-9)          /* persistent steps gave up waiting (wait
+                                   limit reached or give-up word set): the
+                                   state is undefined until a new one is set */
 
 /* ---- options ------------------------------------------------------------ */
 /* Entropy-production indicator alpha_i of Sec. 3.2 (d^H_ij = (alpha_i +
@@ -301,6 +304,33 @@ int ns_query(ns_solver *s, int *done);
 int ns_inflight(ns_solver *s, int *calls);
 int ns_async_finish(ns_solver *s, double *t);
 
+/* Persistent steps: as ns_step_cfl_async, but the nsteps SSPRK(3,3) steps
+ * (each with its CFL time step, eq. dtCfl, computed on the device) run as ONE
+ * kernel launch instead of about 30 launches per step.  The launch's
+ * workgroups stay resident and take work items -- (step, stage, phase,
+ * member, row block) -- in order from a counter; the phases of a stage are
+ * the sweeps of Algorithm 1 (node precompute, graph viscosity and time
+ * step, low-order update and bounds, the two limiter passes with their
+ * root work lists, final update, slip projection of Sec. 4.2).  An item runs
+ * once its member has finished the earlier phases (a completion counter per
+ * member), so each member of a pack moves through the stage on its own.
+ * Results are bit-identical to those of ns_step_cfl_async (same per-row
+ * arithmetic, same time steps).  Every wait of the kernel is bounded: by
+ * wait_s seconds of the device's wall clock (> 0), and by the give-up word
+ * that ns_cancel sets; a wait that ends either way stops the whole launch
+ * (every workgroup exits at its next item), later launches of the run stop
+ * as well, and ns_async_finish / ns_pack_finish report NS_EABORT (the state
+ * is then undefined until ns_set_state / ns_pack_set_state).  Needs
+ * NS_IND_ENTROPY, NS_LIM_CONVEX with 2 passes and no non-reflecting nodes
+ * (else NS_EINVAL); NS_ENOMEM if no give-up word is left (one per solver,
+ * 1024 per process, in pinned host memory).  Status, time and completion
+ * are those of ns_step_cfl_async (ns_query, ns_inflight, ns_async_finish);
+ * both kinds of call may be mixed in one run. */
+int ns_step_cfl_persistent(ns_solver *s, int nsteps, double wait_s);
+/* Sets the solver's give-up word: its persistent launches in flight stop at
+ * their next wait or item (a run's first call clears the word). */
+int ns_cancel(ns_solver *s);
+
 /* ---- packs: several meshes advanced by the same kernel launches ---------
  * A pack holds `count` independent problems (graphs of one dimension) in one
  * solver.  Every member's rows start at a 256-row workgroup boundary (the
@@ -334,6 +364,10 @@ int ns_pack_inflight(ns_pack *k, int *calls);
  * NS_ECFL or NS_EBOUNDS, sticky since the last finish) and t[r] (time
  * advanced since then).  Returns NS_OK, or NS_EHIP if the device failed. */
 int ns_pack_finish(ns_pack *k, int *status, double *t);
+/* As ns_step_cfl_persistent / ns_cancel, for all members (status NS_EABORT
+ * for every member of a run that gave up). */
+int ns_pack_step_cfl_persistent(ns_pack *k, int nsteps, double wait_s);
+int ns_pack_cancel(ns_pack *k);
 const char *ns_pack_error(const ns_pack *k);
 
 /* ---- serving: continuous batching of independent simulations ------------
@@ -365,6 +399,11 @@ typedef struct ns_server_params {
   int64_t pack_nodes; /* rows of a pack at most (meshes rounded up to 256  */
                       /* rows; 0: every request gets its own solver)       */
   int pack_max;       /* members of a pack at most, >= 2 with packs        */
+  int64_t persistent_rows; /* units (solvers or packs) of at most this many
+                              rows are stepped by persistent launches
+                              (ns_step_cfl_persistent, one launch per
+                              chunk, 10 s wait limit); larger ones by
+                              ns_step_cfl_async; 0: none                  */
 } ns_server_params;
 enum { NS_REQ_QUEUED = 0, NS_REQ_RUNNING = 1, NS_REQ_FINISHED = 2 };
 typedef struct ns_request_info {

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libns.so")
 # status codes (ns.h)
 NS_OK, NS_EINVAL, NS_ENOMEM, NS_EHIP = 0, -1, -2, -3
 NS_ENOTADMISSIBLE, NS_ECFL, NS_EBOUNDS, NS_ESTATE, NS_ECG = -4, -5, -6, -7, -8
+NS_EABORT = -9
 FCT_AUTO, FCT_ALWAYS = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 IND_ENTROPY, IND_ONE, IND_ZERO = 0, 1, 2
@@ -42,7 +43,8 @@ EXPORTED = [
     "ns_server_stats_get", "ns_server_error", "ns_pack_footprint", "ns_pack_create",
     "ns_pack_destroy", "ns_pack_set_state", "ns_pack_get_state", "ns_pack_step_cfl_async",
     "ns_pack_inflight", "ns_pack_finish", "ns_pack_error", "ns_set_boundary",
-    "ns_step_adaptive", "ns_stats", "ns_stats_noalloc",
+    "ns_step_adaptive", "ns_stats", "ns_stats_noalloc", "ns_step_cfl_persistent",
+    "ns_cancel", "ns_pack_step_cfl_persistent", "ns_pack_cancel",
 ]
 
 
@@ -133,6 +135,10 @@ def lib() -> C.CDLL:
             "ns_pack_error": (C.c_char_p, [vp]),
             "ns_set_boundary": (C.c_int, [vp, C.POINTER(Boundary)]),
             "ns_step_adaptive": (C.c_int, [vp, C.c_double, dp, dp]),
+            "ns_step_cfl_persistent": (C.c_int, [vp, C.c_int, C.c_double]),
+            "ns_cancel": (C.c_int, [vp]),
+            "ns_pack_step_cfl_persistent": (C.c_int, [vp, C.c_int, C.c_double]),
+            "ns_pack_cancel": (C.c_int, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -245,7 +251,7 @@ NR_CHARACTERISTIC, NR_GODUNOV = 0, 1
 class ServerParams(C.Structure):
     _fields_ = [("mem_bytes", C.c_int64), ("max_running", C.c_int), ("chunk", C.c_int),
                 ("depth", C.c_int), ("solver", Params), ("pack_nodes", C.c_int64),
-                ("pack_max", C.c_int)]
+                ("pack_max", C.c_int), ("persistent_rows", C.c_int64)]
 
 
 class RequestInfo(C.Structure):
@@ -325,6 +331,12 @@ class Pack:
     def step_cfl_async(self, nsteps: int):
         self._check(lib().ns_pack_step_cfl_async(self.h, int(nsteps)))
 
+    def step_cfl_persistent(self, nsteps: int, wait_s: float = 10.0):
+        self._check(lib().ns_pack_step_cfl_persistent(self.h, int(nsteps), float(wait_s)))
+
+    def cancel(self):
+        self._check(lib().ns_pack_cancel(self.h))
+
     def inflight(self) -> int:
         n = C.c_int()
         self._check(lib().ns_pack_inflight(self.h, C.byref(n)))
@@ -351,11 +363,13 @@ class Server:
     """ns_server_*: continuous batching of independent simulations."""
 
     def __init__(self, mem_bytes, max_running=64, gamma=1.4, cfl=0.5,
-                 precision=PREC_FP64, chunk=2, depth=2, pack_nodes=0, pack_max=64):
+                 precision=PREC_FP64, chunk=2, depth=2, pack_nodes=0, pack_max=64,
+                 persistent_rows=0):
         L = lib()
         self.prm = ServerParams(int(mem_bytes), int(max_running), int(chunk), int(depth),
                                 Params(gamma, cfl, IND_ENTROPY, LIM_CONVEX, 2, 1.0,
-                                       precision), int(pack_nodes), int(pack_max))
+                                       precision), int(pack_nodes), int(pack_max),
+                                int(persistent_rows))
         h = C.c_void_p()
         rc = L.ns_server_create(C.byref(self.prm), C.byref(h))
         if rc != NS_OK:
@@ -502,6 +516,13 @@ class Solver:
     # -- asynchronous stepping ---------------------------------------------
     def step_cfl_async(self, nsteps: int):
         return self._check(lib().ns_step_cfl_async(self.h, int(nsteps)))
+
+    def step_cfl_persistent(self, nsteps: int, wait_s: float = 10.0):
+        """nsteps CFL steps as one persistent launch (asynchronous)."""
+        return self._check(lib().ns_step_cfl_persistent(self.h, int(nsteps), float(wait_s)))
+
+    def cancel(self):
+        return self._check(lib().ns_cancel(self.h))
 
     def step_adaptive(self, c_start: float):
         """(dt, c) of one step with the adaptive CFL number."""

@@ -32,6 +32,20 @@ struct BoxGeom {
   int32_t per;   // bit d set: direction d is periodic
 };
 
+// Reads of the mesh geometry.  On the device they go through the constant
+// address space: the geometry is never written by a kernel, and its
+// addresses are uniform over a workgroup, so they become scalar loads even
+// in kernels that also store to global memory (where a plain load could
+// alias a store and would have to be a vector load).
+template <typename T>
+__host__ __forceinline__ T geo_ld(const T *p) {
+  return *p;
+}
+template <typename T>
+__device__ __forceinline__ T geo_ld(const T *p) {
+  return *(const __attribute__((address_space(4))) T *)p;
+}
+
 // Per lane only the row, the ends of the mesh it lies on and the absent
 // directions; the steps between neighbours are the same for all rows of a
 // mesh (scalar registers when the mesh is uniform over the wavefront).
@@ -47,31 +61,34 @@ struct BoxNbr {
 
   __host__ __device__ __forceinline__ BoxNbr(const BoxGeom *geo, int64_t row)
       : g(geo), i((int32_t)row), ends(0), bad(0) {
-    const uint32_t li = (uint32_t)(row - g->base);
-    const bool iso = li >= (uint32_t)g->nn;
+    const uint32_t li = (uint32_t)(row - geo_ld(&g->base));
+    const bool iso = li >= (uint32_t)geo_ld(&g->nn);
     uint32_t a[3] = {0, 0, 0};
     if (!iso) {
-      const uint32_t t = li / (uint32_t)g->n[0];
-      a[0] = li - t * (uint32_t)g->n[0];
+      const uint32_t n0 = (uint32_t)geo_ld(&g->n[0]);
+      const uint32_t t = li / n0;
+      a[0] = li - t * n0;
       if constexpr (DIM == 3) {
-        a[2] = t / (uint32_t)g->n[1];
-        a[1] = t - a[2] * (uint32_t)g->n[1];
+        const uint32_t n1 = (uint32_t)geo_ld(&g->n[1]);
+        a[2] = t / n1;
+        a[1] = t - a[2] * n1;
       } else {
         a[1] = t;
       }
     }
     int32_t st = 1;
     uint32_t wall = 0;
+    const int32_t per = geo_ld(&g->per);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       stride[d] = st;
       wrap[d] = 0;
       if (d >= DIM) continue;
-      const int32_t n = g->n[d];
+      const int32_t n = geo_ld(&g->n[d]);
       wrap[d] = (n - 1) * st;
       if (a[d] == 0) ends |= 1u << (2 * d);
       if ((int32_t)a[d] == n - 1) ends |= 2u << (2 * d);
-      if (!((g->per >> d) & 1)) wall |= 3u << (2 * d);
+      if (!((per >> d) & 1)) wall |= 3u << (2 * d);
       st *= n;
     }
     bad = iso ? 0x3fu : (ends & wall);
@@ -115,11 +132,11 @@ struct BoxNbr {
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       if (o[d] != 0) {
-        f[d] = g->m_off[d];
+        f[d] = geo_ld(&g->m_off[d]);
         c1[d] = o[d] < 0 ? -0.5 : 0.5;
       } else {
         const uint32_t w = (bad >> (2 * d)) & 3u;
-        f[d] = w ? g->m_end[d] : g->m_inner[d];
+        f[d] = w ? geo_ld(&g->m_end[d]) : geo_ld(&g->m_inner[d]);
         c1[d] = w == 1u ? -0.5 : (w == 2u ? 0.5 : 0.0);
       }
     }

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <type_traits>
 
 namespace ns {
 
@@ -75,9 +76,11 @@ __device__ __forceinline__ void st_once(T *p, T v) {
 
 // Neighbours of row i (in its box mesh); the rows of a workgroup belong to
 // one mesh, so the mesh's geometry is a uniform (scalar) load.
+// blk is the row block (kBlock rows) of i, uniform over the workgroup.
 template <int DIM, typename LT>
-__device__ __forceinline__ BoxNbr<DIM> block_nbr(const DevGraphT<LT> &G, int64_t i) {
-  return BoxNbr<DIM>(&G.geo[G.seg ? G.seg[blockIdx.x] : 0], i);
+__device__ __forceinline__ BoxNbr<DIM> block_nbr(const DevGraphT<LT> &G, uint32_t blk,
+                                                 int64_t i) {
+  return BoxNbr<DIM>(&G.geo[G.seg ? geo_ld(&G.seg[blk]) : 0], i);
 }
 // Same for a row that is not the lane's own (work-list entries).
 template <int DIM, typename LT>
@@ -166,11 +169,9 @@ __device__ __forceinline__ double vel_pres(const Gas &g, const double *u, double
 // VP: also store v and p (read only by k_visc without the indicator; the
 // other sweeps compute them from the states they gather).
 template <int DIM, bool VP>
-__global__ __launch_bounds__(kBlock) void k_prim(int64_t N,
-                                                 const double *__restrict__ U,
-                                                 double *__restrict__ aux,
-                                                 Gas g) {
-  const int64_t i = plain_id();
+__device__ __forceinline__ void prim_row(int64_t N, const double *__restrict__ U,
+                                         double *__restrict__ aux, const Gas &g,
+                                         int64_t i) {
   if (i >= N) return;
   using X = Aux<DIM>;
   double u[DIM + 2], v[DIM], p;
@@ -193,6 +194,14 @@ __global__ __launch_bounds__(kBlock) void k_prim(int64_t N,
   aux[X::PHI * N + i] = exp(s);
 }
 
+template <int DIM, bool VP>
+__global__ __launch_bounds__(kBlock) void k_prim(int64_t N,
+                                                 const double *__restrict__ U,
+                                                 double *__restrict__ aux,
+                                                 Gas g) {
+  prim_row<DIM, VP>(N, U, aux, g, plain_id());
+}
+
 // ---------------------------------------------------------------------------
 // Graph viscosity d^L_ij (j > i, stored at (i,j) and (j,i)) and alpha_i.
 // The column indices of the row follow from its place in the box mesh; each
@@ -200,19 +209,17 @@ __global__ __launch_bounds__(kBlock) void k_prim(int64_t N,
 // read row i itself) so that the loads of a chunk are in flight together, and the
 // arithmetic is predicated on the entry being present.
 template <int DIM, int IND, int SEV, typename LT>
-__global__ __launch_bounds__(kBlock) void k_visc(DevGraphT<LT> G,
-                                                 const double *__restrict__ U,
-                                                 const double *__restrict__ aux,
-                                                 LT *__restrict__ d,
-                                                 LT *__restrict__ alpha,
-                                                 Gas g) {
+__device__ __forceinline__ void visc_row(const DevGraphT<LT> &G,
+                                         const double *__restrict__ U,
+                                         const double *__restrict__ aux,
+                                         LT *__restrict__ d, LT *__restrict__ alpha,
+                                         const Gas &g, uint32_t blk, int64_t i) {
   using X = Aux<DIM>;
   using C = Cfg<DIM, NS_CH_VISC>;
   constexpr int NC = C::NC;
   const int64_t N = G.N;
-  const int64_t i = row_id();
   if (i >= N) return;
-  BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
+  BoxNbr<DIM> jv = block_nbr<DIM>(G, blk, i);
   double vi[DIM], pi;
   const double ai = aux[X::A * N + i], bi = aux[X::B * N + i];
   const bool wall_i = G.wall[i] != 0;
@@ -249,7 +256,6 @@ __global__ __launch_bounds__(kBlock) void k_visc(DevGraphT<LT> G,
 #pragma unroll
     for (int kk = 0; kk < C::CH; ++kk) {
       const int k = ch * C::CH + kk;
-      const int64_t e = eidx<DIM>(k, i);
       jc[kk] = jv[k];
       const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
       jv.grad(k, c[kk]);
@@ -329,19 +335,30 @@ __global__ __launch_bounds__(kBlock) void k_visc(DevGraphT<LT> G,
   else alpha[i] = LT(0);
 }
 
+template <int DIM, int IND, int SEV, typename LT>
+__global__ __launch_bounds__(kBlock) void k_visc(DevGraphT<LT> G,
+                                                 const double *__restrict__ U,
+                                                 const double *__restrict__ aux,
+                                                 LT *__restrict__ d,
+                                                 LT *__restrict__ alpha,
+                                                 Gas g) {
+  visc_row<DIM, IND, SEV, LT>(G, U, aux, d, alpha, g, blockIdx.x, row_id());
+}
+
 // ---------------------------------------------------------------------------
 // Time step: per-block min of m_i / (2 sum_{j != i} d_ij) = -m_i / (2 d_ii).
+// (every thread of the workgroup calls it: it ends in a workgroup reduction)
 template <int DIM, typename LT>
-__global__ __launch_bounds__(kBlock) void k_dt_partial(DevGraphT<LT> G,
-                                                       const LT *__restrict__ d,
-                                                       double *__restrict__ partial) {
+__device__ __forceinline__ void dt_partial_blk(const DevGraphT<LT> &G,
+                                               const LT *__restrict__ d,
+                                               double *__restrict__ partial, uint32_t blk,
+                                               int64_t i) {
   using C = Cfg<DIM>;
   const int64_t N = G.N;
-  const int64_t i = row_id();
   double r = INFINITY;
   if (i < N) {
     double dsum = 0.0;
-    BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
+    BoxNbr<DIM> jv = block_nbr<DIM>(G, blk, i);
 #pragma unroll
     for (int k = 0; k < C::W; ++k) {
       const int64_t e = eidx<DIM>(k, i);
@@ -352,7 +369,14 @@ __global__ __launch_bounds__(kBlock) void k_dt_partial(DevGraphT<LT> G,
     r = G.mi[i] / (2.0 * dsum);
   }
   r = block_min(r);
-  if (threadIdx.x == 0) partial[blockIdx.x] = r;
+  if (threadIdx.x == 0) partial[blk] = r;
+}
+
+template <int DIM, typename LT>
+__global__ __launch_bounds__(kBlock) void k_dt_partial(DevGraphT<LT> G,
+                                                       const LT *__restrict__ d,
+                                                       double *__restrict__ partial) {
+  dt_partial_blk<DIM, LT>(G, d, partial, blockIdx.x, row_id());
 }
 
 // One workgroup per member of a pack: the member's workgroups are
@@ -393,23 +417,24 @@ __global__ __launch_bounds__(1024) void k_dt_final(const double *__restrict__ pa
 
 // ---------------------------------------------------------------------------
 // Low-order update, bounds and high-order flux (stored divided by m_i).
+// first: the lane that empties the limiter work lists of this stage
 template <int DIM, typename LT>
-__global__ __launch_bounds__(kBlock) void k_lo(DevGraphT<LT> G, StageArgsT<LT> A, Gas g) {
+__device__ __forceinline__ void lo_row(const DevGraphT<LT> &G, const StageArgsT<LT> &A,
+                                       const Gas &g, uint32_t blk, int64_t i, bool first) {
   using X = Aux<DIM>;
   using C = Cfg<DIM, NS_CH_LO>;
   constexpr int NC = C::NC;
   const int64_t N = G.N;
-  const int64_t i = row_id();
-  if (i >= N) return;
-  if (i == 0) {  // the limiter work lists of this stage start empty
+  if (first) {
     A.qcnt[0] = 0;
     A.qcnt[1] = 0;
   }
+  if (i >= N) return;
   const double *__restrict__ U = A.U;
   const double *__restrict__ aux = A.aux;
   const LT *__restrict__ alpha = A.alpha;
   const LT *__restrict__ dd = A.d;
-  BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
+  BoxNbr<DIM> jv = block_nbr<DIM>(G, blk, i);
   double ui[NC], vi[DIM], pi;
   load_state<NC>(U, N, i, ui);
   vel_pres<DIM>(g, ui, vi, pi);
@@ -487,6 +512,12 @@ __global__ __launch_bounds__(kBlock) void k_lo(DevGraphT<LT> G, StageArgsT<LT> A
   A.bnds[i] = (1.0 - r) * rmin;
   A.bnds[N + i] = (1.0 + r) * rmax;
   A.bnds[2 * N + i] = (1.0 - r) * phimin;
+}
+
+template <int DIM, typename LT>
+__global__ __launch_bounds__(kBlock) void k_lo(DevGraphT<LT> G, StageArgsT<LT> A, Gas g) {
+  const int64_t i = row_id();
+  lo_row<DIM, LT>(G, A, g, blockIdx.x, i, i == 0);
 }
 
 // P_ij = tau/(m_i lambda_i) (b_ij F_j - b_ji F_i + (dH - d)(U_j - U_i)) with
@@ -612,13 +643,13 @@ __device__ __forceinline__ int limit_fast(const Gas &g, const double *u,
 }
 
 template <int DIM, int SEV, typename LT>
-__global__ __launch_bounds__(kBlock) void k_lim1(DevGraphT<LT> G, StageArgsT<LT> A, Gas g) {
+__device__ __forceinline__ void lim1_row(const DevGraphT<LT> &G, const StageArgsT<LT> &A,
+                                         const Gas &g, uint32_t blk, int64_t i) {
   using C = Cfg<DIM, NS_CH_LIM1>;
   constexpr int NC = C::NC;
   const int64_t N = G.N;
-  const int64_t i = row_id();
   if (i >= N) return;
-  BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
+  BoxNbr<DIM> jv = block_nbr<DIM>(G, blk, i);
   RowCtx<DIM> R;
   load_row<DIM>(G, A, i, A.tau[member(A, i)], R);
   double ul[NC];
@@ -657,19 +688,24 @@ __global__ __launch_bounds__(kBlock) void k_lim1(DevGraphT<LT> G, StageArgsT<LT>
   }
 }
 
+template <int DIM, int SEV, typename LT>
+__global__ __launch_bounds__(kBlock) void k_lim1(DevGraphT<LT> G, StageArgsT<LT> A, Gas g) {
+  lim1_row<DIM, SEV, LT>(G, A, g, blockIdx.x, row_id());
+}
+
 // MODE 0: convex, pass-1 update + pass-2 line search; 1: convex with one
 // pass, final; 2: l = 1 (unlimited high order), final; 3: convex, pass-1
 // update only (3D: the pass-2 search is k_lim2b, since both in one kernel
 // need more registers than a SIMD lane has).
 template <int DIM, int MODE, int SEV, typename LT>
-__global__ __launch_bounds__(kBlock) void k_lim2(DevGraphT<LT> G, StageArgsT<LT> A, Gas g) {
+__device__ __forceinline__ void lim2_row(const DevGraphT<LT> &G, const StageArgsT<LT> &A,
+                                         const Gas &g, uint32_t blk, int64_t i) {
   using C = Cfg<DIM, NS_CH_LIM2>;
   constexpr int NC = C::NC;
   const int64_t N = G.N;
-  const int64_t i = row_id();
   if (i >= N) return;
   const LT *__restrict__ lt1 = A.lt1;
-  BoxNbr<DIM> colk = block_nbr<DIM>(G, i);
+  BoxNbr<DIM> colk = block_nbr<DIM>(G, blk, i);
   RowCtx<DIM> R;
   load_row<DIM>(G, A, i, A.tau[member(A, i)], R);
   const double lam = 1.0 / G.lfac[i];
@@ -809,17 +845,22 @@ __global__ __launch_bounds__(kBlock) void k_lim2(DevGraphT<LT> G, StageArgsT<LT>
   }
 }
 
+template <int DIM, int MODE, int SEV, typename LT>
+__global__ __launch_bounds__(kBlock) void k_lim2(DevGraphT<LT> G, StageArgsT<LT> A, Gas g) {
+  lim2_row<DIM, MODE, SEV, LT>(G, A, g, blockIdx.x, row_id());
+}
+
 // Pass-2 line search on (1 - l_ij) P_ij from U^(1) (stored by k_lim2<3>).
 template <int DIM, int SEV, typename LT>
-__global__ __launch_bounds__(kBlock) void k_lim2b(DevGraphT<LT> G, StageArgsT<LT> A, Gas g) {
+__device__ __forceinline__ void lim2b_row(const DevGraphT<LT> &G, const StageArgsT<LT> &A,
+                                          const Gas &g, uint32_t blk, int64_t i) {
   using C = Cfg<DIM, NS_CH_LIM2>;
   constexpr int NC = C::NC;
   const int64_t N = G.N;
-  const int64_t i = row_id();
   if (i >= N) return;
   const LT *__restrict__ lt1 = A.lt1;
   LT *__restrict__ lt2 = A.lt2;
-  BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
+  BoxNbr<DIM> jv = block_nbr<DIM>(G, blk, i);
   RowCtx<DIM> R;
   load_row<DIM>(G, A, i, A.tau[member(A, i)], R);
   double u1[NC];
@@ -870,6 +911,11 @@ __global__ __launch_bounds__(kBlock) void k_lim2b(DevGraphT<LT> G, StageArgsT<LT
   }
 }
 
+template <int DIM, int SEV, typename LT>
+__global__ __launch_bounds__(kBlock) void k_lim2b(DevGraphT<LT> G, StageArgsT<LT> A, Gas g) {
+  lim2b_row<DIM, SEV, LT>(G, A, g, blockIdx.x, row_id());
+}
+
 // Row of a sliced-ELL edge index (inverse of eidx in the row).
 template <int DIM>
 __device__ __forceinline__ int64_t edge_row(int64_t e) {
@@ -881,15 +927,16 @@ __device__ __forceinline__ int64_t edge_row(int64_t e) {
 // one lane per listed entry, grid-stride over the list, so the rare root
 // finder runs at full occupancy instead of stalling a row sweep's wavefront.
 // The line search's density limit l_rho was stored in lt by the sweep.
+// List entries start, start + stride, ... below the list length.
 template <int DIM, int PASS, int SEV, typename LT>
-__global__ __launch_bounds__(kBlock) void k_root(DevGraphT<LT> G, StageArgsT<LT> A, Gas g) {
+__device__ __forceinline__ void root_range(const DevGraphT<LT> &G, const StageArgsT<LT> &A,
+                                           const Gas &g, uint32_t start, uint32_t stride) {
   constexpr int NC = DIM + 2;
   const int64_t N = G.N;
   const uint32_t n = A.qcnt[PASS - 1];
   const uint32_t *__restrict__ q = A.q;
   LT *__restrict__ lt = PASS == 1 ? A.lt1 : A.lt2;
-  for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < n;
-       t += gridDim.x * kBlock) {
+  for (uint32_t t = start; t < n; t += stride) {
     const int64_t e = q[t];
     const int64_t i = edge_row<DIM>(e);
     const int k = (int)((e >> 6) % (DIM == 2 ? 9 : 27));
@@ -912,15 +959,21 @@ __global__ __launch_bounds__(kBlock) void k_root(DevGraphT<LT> G, StageArgsT<LT>
   }
 }
 
+template <int DIM, int PASS, int SEV, typename LT>
+__global__ __launch_bounds__(kBlock) void k_root(DevGraphT<LT> G, StageArgsT<LT> A, Gas g) {
+  root_range<DIM, PASS, SEV, LT>(G, A, g, blockIdx.x * kBlock + threadIdx.x,
+                                 gridDim.x * kBlock);
+}
+
 template <int DIM, typename LT>
-__global__ __launch_bounds__(kBlock) void k_fin(DevGraphT<LT> G, StageArgsT<LT> A, Gas g) {
+__device__ __forceinline__ void fin_row(const DevGraphT<LT> &G, const StageArgsT<LT> &A,
+                                        const Gas &g, uint32_t blk, int64_t i) {
   using C = Cfg<DIM, NS_CH_FIN>;
   constexpr int NC = C::NC;
   const int64_t N = G.N;
-  const int64_t i = row_id();
   if (i >= N) return;
   const LT *__restrict__ lt2 = A.lt2;
-  BoxNbr<DIM> jv = block_nbr<DIM>(G, i);
+  BoxNbr<DIM> jv = block_nbr<DIM>(G, blk, i);
   RowCtx<DIM> R;
   load_row<DIM>(G, A, i, A.tau[member(A, i)], R);
   const double lam = 1.0 / G.lfac[i];
@@ -963,6 +1016,11 @@ __global__ __launch_bounds__(kBlock) void k_fin(DevGraphT<LT> G, StageArgsT<LT> 
 }
 
 template <int DIM, typename LT>
+__global__ __launch_bounds__(kBlock) void k_fin(DevGraphT<LT> G, StageArgsT<LT> A, Gas g) {
+  fin_row<DIM, LT>(G, A, g, blockIdx.x, row_id());
+}
+
+template <int DIM, typename LT>
 __global__ __launch_bounds__(kBlock) void k_combine_low(DevGraphT<LT> G, StageArgsT<LT> A) {
   constexpr int NC = DIM + 2;
   const int64_t i = row_id();
@@ -972,14 +1030,12 @@ __global__ __launch_bounds__(kBlock) void k_combine_low(DevGraphT<LT> G, StageAr
   finish<DIM>(G, A, i, u);
 }
 
+// Slip projection of list entry t (entries below end).
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_slip(int nslip,
-                                                 const int32_t *__restrict__ idx,
-                                                 const double *__restrict__ nrm,
-                                                 int stride, int64_t N,
-                                                 double *__restrict__ U) {
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  if (t >= nslip) return;
+__device__ __forceinline__ void slip_one(int t, int end, const int32_t *__restrict__ idx,
+                                         const double *__restrict__ nrm, int stride,
+                                         int64_t N, double *__restrict__ U) {
+  if (t >= end) return;
   const int64_t i = idx[t];
   double n[DIM], mn = 0.0;
 #pragma unroll
@@ -989,6 +1045,15 @@ __global__ __launch_bounds__(kBlock) void k_slip(int nslip,
   }
 #pragma unroll
   for (int k = 0; k < DIM; ++k) U[(1 + k) * N + i] -= mn * n[k];
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_slip(int nslip,
+                                                 const int32_t *__restrict__ idx,
+                                                 const double *__restrict__ nrm,
+                                                 int stride, int64_t N,
+                                                 double *__restrict__ U) {
+  slip_one<DIM>(blockIdx.x * kBlock + threadIdx.x, nslip, idx, nrm, stride, N, U);
 }
 
 __global__ __launch_bounds__(kBlock) void k_copy(const double2 *__restrict__ src,
@@ -1145,6 +1210,231 @@ __global__ __launch_bounds__(kBlock) void k_stats_final(const double *__restrict
   if (threadIdx.x == 0) {
     out[0] = r.v; out[1] = (double)r.i; out[2] = e.v; out[3] = (double)e.i;
     out[4] = c0; out[5] = c1; out[6] = c2;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent steps (PersistArgsT).  The workgroups take items in sequence
+// order, so every item a workgroup waits for was taken earlier by a running
+// workgroup, and the earliest unfinished item never waits: the launch makes
+// progress whatever the number of resident workgroups.  A member's items of
+// one phase depend only on that member's earlier phases, so members move
+// through a stage independently.  Completion is published with a release at
+// device scope (the stores of the item reach the device-coherent level
+// before the counter moves) and a wait ends with an acquire (no stale cached
+// copy is read afterwards).
+
+// The two state buffers other than c, ascending (k = 0, 1).
+__device__ __forceinline__ int other_buf(int c, int k) {
+  return k == 0 ? (c == 0 ? 1 : 0) : (c == 2 ? 1 : 2);
+}
+
+// tau = cfl min over the member's row blocks; the time advanced grows by it
+// (every thread of the workgroup calls it).
+__device__ __forceinline__ void dt_final_member(const double *__restrict__ partial,
+                                                int32_t b0, int32_t b1, double cfl,
+                                                double *tau, double *tacc) {
+  double v = INFINITY;
+  for (int64_t b = b0 + threadIdx.x; b < b1; b += kBlock) v = fmin(v, partial[b]);
+  v = block_min(v);
+  if (threadIdx.x == 0) {
+    const double t = cfl * v;
+    *tau = t;
+    *tacc += t;
+  }
+}
+
+template <typename LT>
+__device__ __forceinline__ bool persist_stopped(const PersistArgsT<LT> &P) {
+  return __hip_atomic_load(P.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+template <typename LT>
+__device__ __forceinline__ void persist_raise(const PersistArgsT<LT> &P, int why) {
+  atomicCAS(P.stop + 1, 0, why);
+  atomicOr(P.stop + 2, 1 << why);
+  __hip_atomic_store(P.stop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename LT>
+__device__ __forceinline__ bool persist_give_up(const PersistArgsT<LT> &P) {
+  return P.give_up &&
+         __hip_atomic_load(P.give_up, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0;
+}
+
+// Wave 0: waits until *ctr >= need (every lane polls the same word, so
+// every branch is uniform over the wave).  The counter is polled with
+// relaxed loads (an acquire per poll would invalidate the caches the working
+// workgroups read, on every poll of every waiting workgroup); the acquire
+// follows once, after the wait.  The wait is bounded by wait_ticks of the
+// wall clock and ends early when the launch is stopped or the give-up word
+// is set; then it returns false (after stopping the launch).
+template <typename LT>
+__device__ bool persist_wait(const PersistArgsT<LT> &P, const uint32_t *ctr, uint32_t need) {
+  auto done = [&] {
+    return __builtin_amdgcn_readfirstlane(
+               __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >= need;
+  };
+  if (!done()) {
+    const uint64_t t0 = wall_clock64();
+    for (uint32_t it = 0;; ++it) {
+      if (__builtin_amdgcn_readfirstlane(persist_stopped(P))) return false;
+      if ((it & 63u) == 0) {
+        if (__builtin_amdgcn_readfirstlane(persist_give_up(P))) {
+          if (threadIdx.x == 0) persist_raise(P, 2);
+          return false;
+        }
+        if (__builtin_amdgcn_readfirstlane(wall_clock64() - t0 >= P.wait_ticks)) {
+          if (threadIdx.x == 0) persist_raise(P, 1);
+          return false;
+        }
+      }
+      __builtin_amdgcn_s_sleep(8);
+      if (done()) break;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return true;
+}
+
+// The control path (ticket, wait, completion) runs on wave 0 with conditions
+// uniform over the wave, and only the atomics themselves on lane 0: a
+// barrier reached under a condition the compiler takes as divergent within
+// a wave -- e.g. thread 0 alone on both sides of the loop's back edge --
+// lets the structurizer nest the loop so that the other lanes repeat the
+// barriers and the item on their own.
+template <int DIM, int SEV, typename LT>
+__global__ __launch_bounds__(kBlock) void k_persist(DevGraphT<LT> G, PersistArgsT<LT> P,
+                                                    Gas g) {
+  constexpr int W = DIM == 2 ? 9 : 27;
+  __shared__ uint32_t s_item;
+  __shared__ int s_go, s_ok;
+  const int tid = threadIdx.x;
+  const bool wave0 = __builtin_amdgcn_readfirstlane(tid) == 0;
+  const PersistPlan &pl = P.plan;
+  for (;;) {
+    if (wave0) {
+      int go = 0;
+      uint32_t t = 0;
+      if (!__builtin_amdgcn_readfirstlane(persist_stopped(P))) {
+        uint32_t mine = 0;
+        if (tid == 0) mine = atomicAdd(P.ticket, 1u);
+        t = __builtin_amdgcn_readfirstlane(mine);
+        if (t < P.items) {
+          // the give-up word is also read every 16 items, so that it stops
+          // a launch whose waits all end at once
+          if ((t & 15u) == 0 && __builtin_amdgcn_readfirstlane(persist_give_up(P))) {
+            if (tid == 0) persist_raise(P, 2);
+          } else {
+            go = 1;
+          }
+        }
+      }
+      if (tid == 0) {
+        s_item = t;
+        s_go = go;
+      }
+    }
+    __syncthreads();
+    if (!__builtin_amdgcn_readfirstlane(s_go)) return;
+    const uint32_t t = __builtin_amdgcn_readfirstlane(s_item);
+    // item -> step, phase, member, item within the member's phase
+    const uint32_t step = t / P.items_step;
+    const uint32_t u = t - step * P.items_step;
+    int p = 0;
+    while (p + 1 < pl.nph && pl.off[p + 1] <= u) ++p;
+    const int ph = pl.phase[p], st = pl.stage[p];
+    const int kind = persist_kind(ph);
+    uint32_t r = u - (uint32_t)pl.off[p];
+    int m = 0;
+    if (kind == PK_ONE) {
+      m = (int)r;
+      r = 0;
+    } else {
+      // (the member tables are read-only: scalar loads, uniform results)
+      const int32_t *cum = kind == PK_ROW ? P.mblk : kind == PK_ROOT ? P.rblk : P.sblk;
+      int lo = 0, hi = P.A.nmem;  // largest m with cum[m] <= r
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((uint32_t)geo_ld(&cum[mid]) <= r) lo = mid;
+        else hi = mid;
+      }
+      m = lo;
+      r -= (uint32_t)geo_ld(&cum[m]);
+    }
+    const int32_t mb0 = geo_ld(&P.mblk[m]), mb1 = geo_ld(&P.mblk[m + 1]);
+    const uint32_t nb = mb1 - mb0, nr = geo_ld(&P.rblk[m + 1]) - geo_ld(&P.rblk[m]),
+                   ns = geo_ld(&P.sblk[m + 1]) - geo_ld(&P.sblk[m]);
+    auto before = [&](int q) {
+      return pl.pre[q][PK_ROW] * nb + pl.pre[q][PK_ROOT] * nr + pl.pre[q][PK_SLIP] * ns +
+             (uint32_t)pl.pre[q][PK_ONE];
+    };
+    const uint32_t need = step * before(pl.nph) + before(p);
+    if (wave0) {
+      const bool ok = persist_wait(P, P.done + m, need);
+      if (tid == 0) s_ok = ok;
+    }
+    __syncthreads();  // (the acquire of wave 0 covers the workgroup's CU)
+    if (!__builtin_amdgcn_readfirstlane(s_ok)) return;
+    // buffers of the stage (as the launch path rotates them)
+    int c = P.cur;
+    for (uint32_t k = 0; k < step; ++k) c = other_buf(c, 0);
+    const int o1 = other_buf(c, 0), o2 = other_buf(c, 1);
+    StageArgsT<LT> A = P.A;
+    A.Un = P.S[c];
+    if (st == 0) {
+      A.U = P.S[c]; A.out = P.S[o1]; A.sa = 0.0; A.sb = 1.0; A.check_cfl = 0;
+    } else if (st == 1) {
+      A.U = P.S[o1]; A.out = P.S[o2]; A.sa = 0.75; A.sb = 0.25; A.check_cfl = 1;
+    } else {
+      A.U = P.S[o2]; A.out = P.S[o1]; A.sa = 1.0 / 3.0; A.sb = 2.0 / 3.0; A.check_cfl = 1;
+    }
+    // the member's own work lists: its slice of q and its two counters
+    A.q = P.A.q + (int64_t)W * kBlock * mb0;
+    A.qcnt = P.pcnt + 2 * m;
+    const uint32_t blk = kind == PK_ROW ? (uint32_t)mb0 + r : 0u;
+    const int64_t i = (int64_t)blk * kBlock + tid;
+    switch (ph) {
+      case PP_PRIM: prim_row<DIM, false>(G.N, A.U, A.aux, g, i); break;
+      case PP_VISC: visc_row<DIM, 0, SEV, LT>(G, A.U, A.aux, A.d, A.alpha, g, blk, i); break;
+      case PP_DTP: dt_partial_blk<DIM, LT>(G, A.d, A.partial, blk, i); break;
+      case PP_DTF:
+        dt_final_member(A.partial, mb0, mb1, P.cfl, A.tau + m, P.tacc + m);
+        break;
+      case PP_LO: lo_row<DIM, LT>(G, A, g, blk, i, r == 0 && tid == 0); break;
+      case PP_LIM1: lim1_row<DIM, SEV, LT>(G, A, g, blk, i); break;
+      case PP_ROOT1: root_range<DIM, 1, SEV, LT>(G, A, g, r * kBlock + tid, nr * kBlock); break;
+      case PP_LIM2: lim2_row<DIM, DIM == 2 ? 0 : 3, SEV, LT>(G, A, g, blk, i); break;
+      case PP_LIM2B:
+        if constexpr (DIM == 3) lim2b_row<DIM, SEV, LT>(G, A, g, blk, i);
+        break;
+      case PP_ROOT2: root_range<DIM, 2, SEV, LT>(G, A, g, r * kBlock + tid, nr * kBlock); break;
+      case PP_FIN: fin_row<DIM, LT>(G, A, g, blk, i); break;
+      case PP_SLIP:
+        slip_one<DIM>(geo_ld(&P.mslip[m]) + (int)(r * kBlock) + tid, geo_ld(&P.mslip[m + 1]),
+                      P.slip_idx, P.slip_n, P.nslip, G.N, A.out);
+        break;
+      default: break;
+    }
+    // every wave's stores complete and reach the device-coherent level
+    // before the barrier, so the counter moves after all of them
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (wave0 && tid == 0)
+      __hip_atomic_fetch_add(P.done + m, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__global__ void k_persist_reset(uint32_t *done, uint32_t *pcnt, uint32_t *ticket, int *stop,
+                                int nmem, int run_start) {
+  const int t = blockIdx.x * 64 + threadIdx.x;
+  if (t < nmem) done[t] = 0;
+  if (t < 2 * nmem) pcnt[t] = 0;
+  if (t == 0) {
+    *ticket = 0;
+    if (run_start) stop[2] = 0;
+    stop[0] = stop[2] != 0;  // a launch after one that gave up stops at once
+    stop[1] = 0;
   }
 }
 
@@ -1330,6 +1620,94 @@ void launch_copy(const void *src, void *dst, int64_t n16, int word,
     hipLaunchKernelGGL(k_copy, grid_for(n16), dim3(kBlock), 0, s,
                        static_cast<const double2 *>(src),
                        static_cast<double2 *>(dst), n16);
+}
+
+void persist_plan(int dim, int64_t rows_tot, int64_t roots_tot, int64_t slips_tot,
+                  int nmem, PersistPlan *pl) {
+  int n = 0;
+  auto add = [&](int ph, int st) {
+    pl->phase[n] = (int8_t)ph;
+    pl->stage[n] = (int8_t)st;
+    ++n;
+  };
+  for (int st = 0; st < 3; ++st) {
+    add(PP_PRIM, st);
+    add(PP_VISC, st);
+    if (st == 0) {  // the CFL time step of the step
+      add(PP_DTP, st);
+      add(PP_DTF, st);
+    }
+    add(PP_LO, st);
+    add(PP_LIM1, st);
+    add(PP_ROOT1, st);
+    add(PP_LIM2, st);
+    if (dim == 3) add(PP_LIM2B, st);
+    add(PP_ROOT2, st);
+    add(PP_FIN, st);
+    add(PP_SLIP, st);
+  }
+  pl->nph = n;
+  int16_t c[4] = {0, 0, 0, 0};
+  int64_t off = 0;
+  for (int p = 0; p <= n; ++p) {
+    for (int k = 0; k < 4; ++k) pl->pre[p][k] = c[k];
+    pl->off[p] = off;
+    if (p == n) break;
+    const int kind = persist_kind(pl->phase[p]);
+    ++c[kind];
+    off += kind == PK_ROW ? rows_tot : kind == PK_ROOT ? roots_tot
+           : kind == PK_SLIP ? slips_tot : nmem;
+  }
+}
+
+namespace {
+template <typename F>
+const void *persist_kernel(int dim, bool seven, F pick) {
+  return dim == 2 ? (seven ? pick(std::integral_constant<int, 2>{}, std::integral_constant<int, 1>{})
+                           : pick(std::integral_constant<int, 2>{}, std::integral_constant<int, 0>{}))
+                  : (seven ? pick(std::integral_constant<int, 3>{}, std::integral_constant<int, 1>{})
+                           : pick(std::integral_constant<int, 3>{}, std::integral_constant<int, 0>{}));
+}
+template <typename LT>
+const void *persist_kernel_lt(int dim, bool seven) {
+  return persist_kernel(dim, seven, [](auto d, auto sev) {
+    return (const void *)k_persist<decltype(d)::value, decltype(sev)::value, LT>;
+  });
+}
+}  // namespace
+
+int persist_grid(int dim, bool seven, bool fp32) {
+  const void *k = fp32 ? persist_kernel_lt<float>(dim, seven)
+                       : persist_kernel_lt<double>(dim, seven);
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kBlock, 0) != hipSuccess) return 0;
+  return std::max(per, 1) * cus;
+}
+
+template <typename LT>
+void launch_persistent(int dim, const Gas &gas, const DevGraphT<LT> &g,
+                       const PersistArgsT<LT> &p, int grid, hipStream_t s) {
+  const dim3 gr((unsigned)grid), bl(kBlock);
+  if (dim == 2) {
+    if (gas.seven) hipLaunchKernelGGL((k_persist<2, 1, LT>), gr, bl, 0, s, g, p, gas);
+    else hipLaunchKernelGGL((k_persist<2, 0, LT>), gr, bl, 0, s, g, p, gas);
+  } else {
+    if (gas.seven) hipLaunchKernelGGL((k_persist<3, 1, LT>), gr, bl, 0, s, g, p, gas);
+    else hipLaunchKernelGGL((k_persist<3, 0, LT>), gr, bl, 0, s, g, p, gas);
+  }
+}
+template void launch_persistent<double>(int, const Gas &, const DevGraphT<double> &,
+                                        const PersistArgsT<double> &, int, hipStream_t);
+template void launch_persistent<float>(int, const Gas &, const DevGraphT<float> &,
+                                       const PersistArgsT<float> &, int, hipStream_t);
+
+void launch_persist_reset(uint32_t *done, uint32_t *pcnt, uint32_t *ticket, int *stop,
+                          int nmem, bool run_start, hipStream_t s) {
+  hipLaunchKernelGGL(k_persist_reset, dim3((unsigned)((2 * nmem + 63) / 64)), dim3(64), 0, s,
+                     done, pcnt, ticket, stop, nmem, run_start ? 1 : 0);
 }
 
 void launch_clear_flags(int *flags, hipStream_t s, int n) {

@@ -96,6 +96,84 @@ struct StageArgsT {
 using DevGraph = DevGraphT<double>;
 using StageArgs = StageArgsT<double>;
 
+// ---------------------------------------------------------------------------
+// Persistent execution of whole SSPRK(3,3) steps with the CFL time step (the
+// serving path): one launch runs `nsteps` steps of every member of a solver
+// or pack.  The work is a sequence of items -- (step, stage, phase, member,
+// block) -- in phase-major order; a phase is one of the sweeps above over
+// one member (its row blocks, its work-list slices, its slip nodes or its
+// time-step reduction).  Workgroups take items in sequence order from a
+// ticket counter and run each item after the member has finished all its
+// items of earlier phases (one completion counter per member).
+constexpr int kMaxPhases = 40;
+enum PersistPhase : int8_t {
+  PP_PRIM = 0, PP_VISC, PP_DTP, PP_DTF, PP_LO, PP_LIM1, PP_ROOT1, PP_LIM2, PP_LIM2B,
+  PP_ROOT2, PP_FIN, PP_SLIP
+};
+// item kinds: one per row block, one per work-list slice, one per 256 slip
+// nodes, one per member
+enum PersistKind { PK_ROW = 0, PK_ROOT = 1, PK_SLIP = 2, PK_ONE = 3 };
+__host__ __device__ constexpr int persist_kind(int ph) {
+  return ph == PP_ROOT1 || ph == PP_ROOT2 ? PK_ROOT
+         : ph == PP_SLIP                  ? PK_SLIP
+         : ph == PP_DTF                   ? PK_ONE
+                                          : PK_ROW;
+}
+
+// The phase sequence of one step, with the prefix counts every item needs:
+// member m has cnt(m, kind) items of each phase of that kind, so its items
+// before phase p number pre[p][ROW] nb_m + pre[p][ROOT] nr_m +
+// pre[p][SLIP] ns_m + pre[p][ONE]; off[p] is the first item of phase p
+// within a step (all members).
+struct PersistPlan {
+  int nph;
+  int8_t phase[kMaxPhases], stage[kMaxPhases];
+  int16_t pre[kMaxPhases + 1][4];
+  int64_t off[kMaxPhases + 1];
+};
+// Phases of one step (2D: 29, 3D: 32) for the entropy indicator, convex
+// limiting with two passes; totals of the members' row blocks, work-list
+// slices and slip slices; nmem members.
+void persist_plan(int dim, int64_t rows_tot, int64_t roots_tot, int64_t slips_tot,
+                  int nmem, PersistPlan *plan);
+
+template <typename LT>
+struct PersistArgsT {
+  StageArgsT<LT> A;  // U, Un, out, sa, sb, check_cfl, q and qcnt set per item
+  double *S[3];      // state buffers; step 0 starts from S[cur]
+  int cur, nsteps;
+  double cfl;
+  double *tacc;      // per member: time advanced
+  // per member (nmem + 1 entries): first row block, first work-list slice,
+  // first slip slice, first slip entry
+  const int32_t *mblk, *rblk, *sblk, *mslip;
+  const int32_t *slip_idx;
+  const double *slip_n;  // normal component k of slip entry t at k*nslip + t
+  int nslip;
+  uint32_t *pcnt;    // 2 per member: work-list lengths of the two passes
+  uint32_t *done;    // per member: completed items
+  uint32_t *ticket;  // next item
+  int *stop;         // [0] set: every workgroup exits; [1] why (1 wait
+                     // limit, 2 give-up word); [2] bit `why` of every stop
+                     // since it was last cleared (not cleared per launch)
+  const int *give_up;    // host-written word (pinned host memory), or null
+  uint64_t wait_ticks;   // bound of one wait, in wall-clock ticks
+  uint32_t items;        // items of the launch (nsteps steps)
+  uint32_t items_step;
+  PersistPlan plan;
+};
+
+// Workgroups of a persistent launch that fit on the device at once.
+int persist_grid(int dim, bool seven, bool fp32);
+template <typename LT>
+void launch_persistent(int dim, const Gas &gas, const DevGraphT<LT> &g,
+                       const PersistArgsT<LT> &p, int grid, hipStream_t s);
+// Before a launch: zeroes done[0..nmem), pcnt[0..2 nmem), *ticket and
+// stop[1]; stop[0] is set only if a launch of the run gave up (stop[2]);
+// run_start: a new run, stop[2] is zeroed first.
+void launch_persist_reset(uint32_t *done, uint32_t *pcnt, uint32_t *ticket, int *stop,
+                          int nmem, bool run_start, hipStream_t s);
+
 template <typename LT>
 void launch_stage(int dim, const Gas &gas, const DevGraphT<LT> &g,
                   const StageArgsT<LT> &a, int indicator, int limiter, int passes,

@@ -177,6 +177,17 @@ struct ns_solver {
   double htau[1] = {0.0};
   int last_out = 1;        // buffer holding the last stage output
   bool stage_ran = false;  // a stage has run: its limiter arrays hold data
+  // persistent steps (ns_step_cfl_persistent): per member (nmem + 1
+  // entries) the first row block, work-list slice, slip slice and slip
+  // entry; list counters, completion counters, ticket, stop words; the
+  // give-up word (pinned host memory, shared pool) and the launch width
+  int32_t *pmblk = nullptr, *prblk = nullptr, *psblk = nullptr, *pmslip = nullptr;
+  uint32_t *pcnt = nullptr, *pdone = nullptr, *pticket = nullptr;
+  int *pstop = nullptr;
+  int64_t rows_tot = 0, roots_tot = 0, slips_tot = 0;
+  int *give_up = nullptr;
+  int pgrid = 0;
+  int hpstop[4] = {0, 0, 0, 0};
   // parabolic step (allocated by ns_set_viscous)
   bool viscous = false;
   ns_viscous vprm{};
@@ -255,9 +266,47 @@ struct ns_solver {
 
 namespace {
 
+// Give-up words of the persistent steps: one int per solver in pinned host
+// memory, which the host writes and the kernel polls across the bus.  One
+// block of slots is allocated per process and kept until it ends (releasing
+// pinned memory would wait for the whole device); solvers take a slot on
+// their first persistent step and return it when destroyed.
+constexpr int kGiveUpSlots = 1024;
+std::mutex g_give_up_mu;
+int *g_give_up_host = nullptr;
+std::vector<int> g_give_up_free;
+
+int *take_give_up_word() {
+  std::lock_guard<std::mutex> lk(g_give_up_mu);
+  if (!g_give_up_host) {
+    void *p = nullptr;
+    if (hipHostMalloc(&p, kGiveUpSlots * sizeof(int),
+                      hipHostMallocMapped | hipHostMallocPortable | hipHostMallocCoherent) !=
+        hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_give_up_host = static_cast<int *>(p);
+    for (int k = kGiveUpSlots - 1; k >= 0; --k) g_give_up_free.push_back(k);
+  }
+  if (g_give_up_free.empty()) return nullptr;
+  const int k = g_give_up_free.back();
+  g_give_up_free.pop_back();
+  __atomic_store_n(g_give_up_host + k, 0, __ATOMIC_SEQ_CST);
+  return g_give_up_host + k;
+}
+
+void return_give_up_word(int *w) {
+  if (!w) return;
+  std::lock_guard<std::mutex> lk(g_give_up_mu);
+  g_give_up_free.push_back((int)(w - g_give_up_host));
+}
+
 void release(ns_solver *s) {
   if (!s) return;
   if (s->stream) (void)hipStreamSynchronize(s->stream);
+  return_give_up_word(s->give_up);
+  s->give_up = nullptr;
   s->prof.destroy();
   for (void *p : s->allocs) (void)hipFreeAsync(p, s->stream);
   s->allocs.clear();
@@ -684,6 +733,7 @@ int64_t footprint(const Layout &Lt, const ns_params *p) {
   b += W * Np * 4 + 2 * 4;                           // root work list
   b += nslip * 4 + dim * nslip * 8;                  // slip list
   if (Lt.pack) b += nblocks * 4 + (nm + 1) * 4;      // member of each workgroup
+  b += 4 * (nm + 1) * 4 + 3 * nm * 4 + 4 + 4 * 4;    // persistent-step tables
   return b;
 }
 }  // namespace
@@ -823,6 +873,14 @@ int create_impl(const Layout &Lt, const ns_params *p, void *stream, ns_solver **
   // limiter root work list, large enough for every edge
   NS_ALLOC(s->q, W * Np);
   NS_ALLOC(s->qcnt, 2);
+  NS_ALLOC(s->pmblk, s->nmem + 1);
+  NS_ALLOC(s->prblk, s->nmem + 1);
+  NS_ALLOC(s->psblk, s->nmem + 1);
+  NS_ALLOC(s->pmslip, s->nmem + 1);
+  NS_ALLOC(s->pcnt, 2 * s->nmem);
+  NS_ALLOC(s->pdone, s->nmem);
+  NS_ALLOC(s->pticket, 1);
+  NS_ALLOC(s->pstop, 4);
   // the uploads below are synchronous copies: the stream-ordered allocations
   // must have completed
   e = hipStreamSynchronize(s->stream);
@@ -897,7 +955,28 @@ int create_impl(const Layout &Lt, const ns_params *p, void *stream, ns_solver **
       }
       hmblk.push_back((int32_t)nblocks);
     }
+    // persistent steps: per member its row blocks, its work-list slices (one
+    // per 8 row blocks: the lists hold a small fraction of the edges) and
+    // its slip slices (256 entries each), as running sums
+    std::vector<int32_t> pmb(nm + 1), prb(nm + 1), psb(nm + 1), pms(nm + 1);
+    for (int r = 0; r <= nm; ++r) {
+      pmb[r] = s->pack ? hmblk[r] : (r == 0 ? 0 : (int32_t)nblocks);
+      pms[r] = (int32_t)s->mslip[r];
+    }
+    prb[0] = psb[0] = 0;
+    for (int r = 0; r < nm; ++r) {
+      const int32_t nb = pmb[r + 1] - pmb[r], ns = pms[r + 1] - pms[r];
+      prb[r + 1] = prb[r] + std::max<int32_t>(1, nb / 8);
+      psb[r + 1] = psb[r] + (ns + ns::kBlock - 1) / ns::kBlock;
+    }
+    s->rows_tot = pmb[nm];
+    s->roots_tot = prb[nm];
+    s->slips_tot = psb[nm];
     struct { void *dst; const void *src; size_t n; } ups[] = {
+        {s->pmblk, pmb.data(), pmb.size() * sizeof(int32_t)},
+        {s->prblk, prb.data(), prb.size() * sizeof(int32_t)},
+        {s->psblk, psb.data(), psb.size() * sizeof(int32_t)},
+        {s->pmslip, pms.data(), pms.size() * sizeof(int32_t)},
         {s->mi, mi.data(), N * sizeof(double)},
         {s->rmi, rmi.data(), N * sizeof(double)},
         {s->lfac, lfac.data(), N * sizeof(double)},
@@ -1368,22 +1447,98 @@ hipGraphExec_t step_graph(ns_solver *s) {
 }
 }  // namespace
 
+extern "C++" {
+namespace {
+// An event for the end of an asynchronous call (from the pool, or new).
+int take_event(ns_solver *s, hipEvent_t *ev) {
+  *ev = nullptr;
+  if (!s->ev_pool.empty()) {
+    *ev = s->ev_pool.back();
+    s->ev_pool.pop_back();
+    return NS_OK;
+  }
+  hipError_t e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+  if (e != hipSuccess) return s->hipfail(e, "event create");
+  return NS_OK;
+}
+
+// A new asynchronous run: the sticky status and the time start at 0.
+void open_async(ns_solver *s) {
+  if (s->async_open) return;
+  ns::launch_clear_flags(s->flags, s->stream, s->nmem);
+  ns::launch_persist_reset(s->pdone, s->pcnt, s->pticket, s->pstop, s->nmem, true, s->stream);
+  ns::launch_set_scalar(s->tacc, 0.0, s->stream, s->nmem);
+  if (s->give_up) __atomic_store_n(s->give_up, 0, __ATOMIC_SEQ_CST);
+  s->async_open = true;
+}
+
+// After a run's status readback (hpstop): did a persistent launch of the run
+// give up?  Then its steps stopped part-way: the state is undefined until a
+// new one is set, and the give-up word is cleared for the next run.
+bool persistent_gave_up(ns_solver *s) {
+  if (s->hpstop[2] == 0) return false;
+  s->has_state = false;
+  std::fill(s->mset.begin(), s->mset.end(), 0);
+  if (s->give_up) __atomic_store_n(s->give_up, 0, __ATOMIC_SEQ_CST);
+  return true;
+}
+
+// Records the end of an asynchronous call (ev) after its launches.
+int close_call(ns_solver *s, hipEvent_t ev, hipError_t e, const char *what) {
+  if (e == hipSuccess) e = hipEventRecord(ev, s->stream);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) {
+    s->ev_pool.push_back(ev);
+    return s->hipfail(e, what);
+  }
+  s->inflight.push_back(ev);
+  return NS_OK;
+}
+
+template <typename LT>
+ns::PersistArgsT<LT> persist_args(const ns_solver *s, const ns::StageArgsT<LT> &a,
+                                  int nsteps, double wait_s, int items_step,
+                                  const ns::PersistPlan &plan) {
+  ns::PersistArgsT<LT> P{};
+  P.A = a;
+  for (int b = 0; b < 3; ++b) P.S[b] = s->S[b];
+  P.cur = s->cur;
+  P.nsteps = nsteps;
+  P.cfl = s->prm.cfl;
+  P.tacc = s->tacc;
+  P.mblk = s->pmblk;
+  P.rblk = s->prblk;
+  P.sblk = s->psblk;
+  P.mslip = s->pmslip;
+  P.slip_idx = s->slip_idx;
+  P.slip_n = s->slip_n;
+  P.nslip = s->nslip;
+  P.pcnt = s->pcnt;
+  P.done = s->pdone;
+  P.ticket = s->pticket;
+  P.stop = s->pstop;
+  P.give_up = s->give_up;
+  P.items_step = (uint32_t)items_step;
+  P.items = (uint32_t)((int64_t)nsteps * items_step);
+  int dev = s->device, khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    khz = 100000;  // the 100 MHz constant clock of the CDNA parts
+  }
+  P.wait_ticks = (uint64_t)std::min(wait_s * 1e3 * khz, 1.8e19);
+  P.plan = plan;
+  return P;
+}
+}  // namespace
+}  // extern "C++"
+
 int ns_step_cfl_async(ns_solver *s, int nsteps) {
   if (!s || nsteps < 0) return NS_EINVAL;
   if (!s->has_state) return s->fail(NS_ESTATE, "no state set");
   hipEvent_t ev = nullptr;
-  if (!s->ev_pool.empty()) {
-    ev = s->ev_pool.back();
-    s->ev_pool.pop_back();
-  } else {
-    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-    if (e != hipSuccess) return s->hipfail(e, "event create");
-  }
-  if (!s->async_open) {  // a new run: the sticky status and the time start at 0
-    ns::launch_clear_flags(s->flags, s->stream, s->nmem);
-    ns::launch_set_scalar(s->tacc, 0.0, s->stream, s->nmem);
-    s->async_open = true;
-  }
+  int rc = take_event(s, &ev);
+  if (rc != NS_OK) return rc;
+  open_async(s);
   hipError_t e = hipSuccess;
   for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
     const hipGraphExec_t g = step_graph(s);
@@ -1398,13 +1553,60 @@ int ns_step_cfl_async(ns_solver *s, int nsteps) {
     s->last_out = o1;
     s->cur = o1;
   }
-  if (e == hipSuccess) e = hipEventRecord(ev, s->stream);
-  if (e == hipSuccess) e = hipGetLastError();
-  if (e != hipSuccess) {
-    s->ev_pool.push_back(ev);
-    return s->hipfail(e, "asynchronous step launch");
+  return close_call(s, ev, e, "asynchronous step launch");
+}
+
+int ns_step_cfl_persistent(ns_solver *s, int nsteps, double wait_s) {
+  if (!s || nsteps < 0 || !(wait_s > 0.0) || !std::isfinite(wait_s)) return NS_EINVAL;
+  if (!s->has_state) return s->fail(NS_ESTATE, "no state set");
+  if (s->prm.indicator != NS_IND_ENTROPY || s->prm.limiter != NS_LIM_CONVEX ||
+      s->prm.passes != 2)
+    return s->fail(NS_EINVAL, "persistent steps need the entropy indicator and convex "
+                              "limiting with two passes");
+  if (s->nnr > 0)
+    return s->fail(NS_EINVAL, "persistent steps do not treat non-reflecting boundaries");
+  if (!s->give_up && !(s->give_up = take_give_up_word()))
+    return s->fail(NS_ENOMEM, "no give-up word left (pinned host memory)");
+  if (s->pgrid <= 0) {
+    s->pgrid = ns::persist_grid(s->dim, s->gas.seven != 0, s->mixed);
+    if (s->pgrid <= 0) return s->fail(NS_EHIP, "occupancy query of the persistent kernel");
   }
-  s->inflight.push_back(ev);
+  ns::PersistPlan plan;
+  ns::persist_plan(s->dim, s->rows_tot, s->roots_tot, s->slips_tot, s->nmem, &plan);
+  const int64_t items_step = plan.off[plan.nph];
+  if ((int64_t)nsteps * items_step > (int64_t)INT32_MAX)
+    return s->fail(NS_EINVAL, "too many steps for one persistent launch");
+  hipEvent_t ev = nullptr;
+  int rc = take_event(s, &ev);
+  if (rc != NS_OK) return rc;
+  open_async(s);
+  if (nsteps > 0) {
+    const int64_t items = (int64_t)nsteps * items_step;
+    // twice the widest phase: the next phase's items are taken while one
+    // ends, without many more workgroups waiting
+    const int grid =
+        (int)std::min<int64_t>(std::min<int64_t>(s->pgrid, items), 2 * s->rows_tot + 8);
+    ns::launch_persist_reset(s->pdone, s->pcnt, s->pticket, s->pstop, s->nmem, false,
+                             s->stream);
+    if (s->mixed)
+      ns::launch_persistent(s->dim, s->gas, s->devgraph32(),
+                            persist_args(s, s->args32(s->cur, s->cur, 0.0, 1.0, 0), nsteps,
+                                         wait_s, (int)items_step, plan),
+                            grid, s->stream);
+    else
+      ns::launch_persistent(s->dim, s->gas, s->devgraph(),
+                            persist_args(s, s->args(s->cur, s->cur, 0.0, 1.0, 0), nsteps,
+                                         wait_s, (int)items_step, plan),
+                            grid, s->stream);
+    for (int k = 0; k < nsteps; ++k) s->cur = others(s->cur, 0);
+    s->last_out = s->cur;
+  }
+  return close_call(s, ev, hipSuccess, "persistent step launch");
+}
+
+int ns_cancel(ns_solver *s) {
+  if (!s) return NS_EINVAL;
+  if (s->give_up) __atomic_store_n(s->give_up, 1, __ATOMIC_SEQ_CST);
   return NS_OK;
 }
 
@@ -1549,14 +1751,27 @@ int ns_pack_finish(ns_pack *k, int *status, double *t) {
   if (e == hipSuccess)
     e = hipMemcpyAsync(ta.data(), s->tacc, nm * sizeof(double), hipMemcpyDeviceToHost,
                        s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->hpstop, s->pstop, 4 * sizeof(int), hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e == hipSuccess) e = hipGetLastError();
   if (e != hipSuccess) return s->hipfail(e, "asynchronous step status");
+  const bool gave_up = persistent_gave_up(s);
   for (int r = 0; r < nm; ++r) {
-    status[r] = fl[4 * r] ? NS_ECFL : fl[4 * r + 1] ? NS_EBOUNDS : NS_OK;
+    status[r] = gave_up ? NS_EABORT : fl[4 * r] ? NS_ECFL : fl[4 * r + 1] ? NS_EBOUNDS : NS_OK;
     t[r] = ta[r];
   }
   return NS_OK;
+}
+
+int ns_pack_step_cfl_persistent(ns_pack *k, int nsteps, double wait_s) {
+  if (!k) return NS_EINVAL;
+  return ns_step_cfl_persistent(k->s, nsteps, wait_s);
+}
+
+int ns_pack_cancel(ns_pack *k) {
+  if (!k) return NS_EINVAL;
+  return ns_cancel(k->s);
 }
 
 const char *ns_pack_error(const ns_pack *k) {
@@ -1573,11 +1788,16 @@ int ns_async_finish(ns_solver *s, double *t) {
   double tt = 0.0;
   if (e == hipSuccess)
     e = hipMemcpyAsync(s->htau, s->tacc, sizeof(double), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->hpstop, s->pstop, 4 * sizeof(int), hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e == hipSuccess) e = hipGetLastError();
   if (e != hipSuccess) return s->hipfail(e, "asynchronous step status");
   tt = *s->htau;
   if (t) *t = tt;
+  if (persistent_gave_up(s))
+    return s->fail(NS_EABORT, s->hpstop[2] & 4 ? "persistent steps gave up: give-up word set"
+                                               : "persistent steps gave up: wait limit reached");
   if (s->hflags[0]) return s->fail(NS_ECFL, "a step exceeded the stage CFL limit");
   if (s->hflags[1]) return s->fail(NS_EBOUNDS, "a stage produced an inadmissible state");
   return NS_OK;

@@ -109,10 +109,29 @@ const char *unit_error(const Unit *u) {
   return u->k ? ns_pack_error(u->k) : u->s ? ns_last_error(u->s) : ns_create_error();
 }
 
-// enqueue the next chunk of steps
+// rows of a unit: its mesh, or its members padded to whole workgroups
+int64_t unit_rows(const Unit *u) {
+  if (u->mem.size() == 1) return u->mem[0]->N;
+  int64_t n = 0;
+  for (const Request *r : u->mem) n += r->rows;
+  return n;
+}
+
+// Wait limit of the persistent launches: far above any chunk's run time, so
+// that it only ends a launch that can no longer progress.
+constexpr double kPersistWaitS = 10.0;
+
+// enqueue the next chunk of steps: one persistent launch for a unit of at
+// most persistent_rows rows, else the captured step graphs
 int top_up(ns_server *sv, Unit *u) {
   const int k = std::min(sv->prm.chunk, u->steps - u->enqueued);
-  const int rc = u->k ? ns_pack_step_cfl_async(u->k, k) : ns_step_cfl_async(u->s, k);
+  const bool pers = unit_rows(u) <= sv->prm.persistent_rows;
+  int rc;
+  if (pers)
+    rc = u->k ? ns_pack_step_cfl_persistent(u->k, k, kPersistWaitS)
+              : ns_step_cfl_persistent(u->s, k, kPersistWaitS);
+  else
+    rc = u->k ? ns_pack_step_cfl_async(u->k, k) : ns_step_cfl_async(u->s, k);
   if (rc == NS_OK) u->enqueued += k;
   return rc;
 }
@@ -179,7 +198,7 @@ void finish(ns_server *sv, Unit *u, int rc) {
     Request *r = u->mem[m];
     r->t_sim = t[m];
     int s = st[m];
-    if (s == NS_OK || s == NS_ECFL || s == NS_EBOUNDS) {
+    if (s == NS_OK || s == NS_ECFL || s == NS_EBOUNDS) {  // (not NS_EABORT)
       r->out.resize((size_t)(r->dim + 2) * r->N);
       const int rg = u->k ? ns_pack_get_state(u->k, (int)m, r->out.data())
                           : ns_get_state(u->s, r->out.data(), 0);
@@ -240,7 +259,13 @@ extern "C" {
 
 int ns_server_create(const ns_server_params *p, ns_server **out) {
   if (!p || !out || p->mem_bytes <= 0 || p->max_running < 1 || p->chunk < 1 ||
-      p->depth < 1 || p->pack_nodes < 0 || (p->pack_nodes > 0 && p->pack_max < 2))
+      p->depth < 1 || p->pack_nodes < 0 || (p->pack_nodes > 0 && p->pack_max < 2) ||
+      p->persistent_rows < 0)
+    return NS_EINVAL;
+  // persistent launches run the entropy indicator and two-pass convex limiting
+  if (p->persistent_rows > 0 &&
+      (p->solver.indicator != NS_IND_ENTROPY || p->solver.limiter != NS_LIM_CONVEX ||
+       p->solver.passes != 2))
     return NS_EINVAL;
   ns_server *sv = new (std::nothrow) ns_server;
   if (!sv) return NS_ENOMEM;

@@ -74,9 +74,10 @@ def test_graph_replays_equal_eager_steps(dim, precision):
 
 
 def run_server(reqs, mem_bytes, max_running, precision=abi.PREC_FP64, stagger=0.0,
-               pack_nodes=0, pack_max=64):
+               pack_nodes=0, pack_max=64, persistent_rows=0):
     sv = abi.Server(mem_bytes, max_running=max_running, precision=precision,
-                    pack_nodes=pack_nodes, pack_max=pack_max)
+                    pack_nodes=pack_nodes, pack_max=pack_max,
+                    persistent_rows=persistent_rows)
     ids = []
     for mesh, U, steps in reqs:
         ids.append(sv.submit(mesh, U, steps))
