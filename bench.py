@@ -318,7 +318,7 @@ def serve_bench(args, mixed: bool):
     warm.close()
     sv = abi.Server(mem, max_running=args.max_running, precision=prec,
                     chunk=args.serve_chunk, depth=2, pack_nodes=args.pack_nodes,
-                    pack_max=args.pack_max)
+                    pack_max=args.pack_max, persistent_rows=args.persistent_rows)
     t0 = time.perf_counter()
     pending = list(range(len(reqs)))
     ids, info = {}, {}
@@ -359,8 +359,11 @@ def serve_bench(args, mixed: bool):
                     f"of at most {args.pack_nodes // 2} rows packed "
                     f"(consecutive, same step count, up to "
                     f"{args.pack_nodes} rows and {args.pack_max} members "
-                    f"per pack), chunks of {args.serve_chunk} steps, "
-                    f"{args.hw_queues} hardware queues",
+                    f"per pack), chunks of {args.serve_chunk} steps "
+                    + (f"(one persistent launch per chunk for units of at most "
+                       f"{args.persistent_rows} rows, captured step graphs above), "
+                       if args.persistent_rows > 0 else "(captured step graphs), ")
+                    + f"{args.hw_queues} hardware queues",
         "requests": args.requests,
         "latency_ms": {"p50": float(np.percentile(lat, 50)),
                        "p99": float(np.percentile(lat, 99)),
@@ -537,12 +540,18 @@ def full_run(args):
                            "limited_steps": sum(c[3] for c in res["cg"])}})
     del g3, U3
 
-    # C5: serving, FP64 and mixed precision
+    # C5: serving, FP64 and mixed precision (captured step graphs), and FP64
+    # with every unit stepped by persistent launches (one per chunk)
     if not args.no_serve:
         for mixed in (False, True):
             r = serve_bench(args, mixed)
             say(f"serving {'mixed' if mixed else 'fp64'} p50 {r['latency_ms']['p50']:.0f} ms")
             configs["serving_mixed" if mixed else "serving_fp64"] = r
+        pa = argparse.Namespace(**vars(args))
+        pa.persistent_rows = max(args.pack_nodes, 1 << 20)
+        r = serve_bench(pa, False)
+        say(f"serving fp64 persistent p50 {r['latency_ms']['p50']:.0f} ms")
+        configs["serving_fp64_persistent"] = r
     out["configs"] = configs
     if not args.no_cpu_baseline:
         say("oracle baseline")
@@ -594,6 +603,10 @@ def main():
                          "every request gets its own solver)")
     ap.add_argument("--pack-max", type=int, default=64,
                     help="serving: members of a pack at most")
+    ap.add_argument("--persistent-rows", type=int, default=0,
+                    help="serving: units (solvers or packs) of at most this many rows "
+                         "are stepped by one persistent launch per chunk; larger ones "
+                         "by captured step graphs (0: none)")
     ap.add_argument("--hw-queues", type=int, default=16,
                     help="hardware queues for the serving streams (GPU_MAX_HW_QUEUES, "
                          "at most 32)")

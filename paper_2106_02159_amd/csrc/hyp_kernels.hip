@@ -1263,55 +1263,81 @@ __device__ __forceinline__ bool persist_give_up(const PersistArgsT<LT> &P) {
 }
 
 // Wave 0: waits until *ctr >= need (every lane polls the same word, so
-// every branch is uniform over the wave).  The counter is polled with
-// relaxed loads (an acquire per poll would invalidate the caches the working
-// workgroups read, on every poll of every waiting workgroup); the acquire
-// follows once, after the wait.  The wait is bounded by wait_ticks of the
-// wall clock and ends early when the launch is stopped or the give-up word
-// is set; then it returns false (after stopping the launch).
+// every branch is uniform over the wave) and returns the value it saw, or
+// 0 if the launch stops first.  The counter is polled with relaxed loads (an
+// acquire per poll would invalidate the caches the working workgroups read,
+// on every poll of every waiting workgroup); the acquire follows once,
+// after the wait.  The wait is bounded by wait_ticks of the wall clock and
+// ends early when the launch is stopped or the give-up word is set (which
+// then stops the launch).
 template <typename LT>
-__device__ bool persist_wait(const PersistArgsT<LT> &P, const uint32_t *ctr, uint32_t need) {
-  auto done = [&] {
+__device__ uint32_t persist_wait(const PersistArgsT<LT> &P, const uint32_t *ctr,
+                                 uint32_t need) {
+  auto seen = [&] {
     return __builtin_amdgcn_readfirstlane(
-               __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >= need;
+        __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
   };
-  if (!done()) {
+  uint32_t v = seen();
+  if (v < need) {
     const uint64_t t0 = wall_clock64();
     for (uint32_t it = 0;; ++it) {
-      if (__builtin_amdgcn_readfirstlane(persist_stopped(P))) return false;
+      if (__builtin_amdgcn_readfirstlane(persist_stopped(P))) return 0;
       if ((it & 63u) == 0) {
         if (__builtin_amdgcn_readfirstlane(persist_give_up(P))) {
           if (threadIdx.x == 0) persist_raise(P, 2);
-          return false;
+          return 0;
         }
         if (__builtin_amdgcn_readfirstlane(wall_clock64() - t0 >= P.wait_ticks)) {
           if (threadIdx.x == 0) persist_raise(P, 1);
-          return false;
+          return 0;
         }
       }
       __builtin_amdgcn_s_sleep(8);
-      if (done()) break;
+      v = seen();
+      if (v >= need) break;
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  return true;
+  return v;
 }
 
-// The control path (ticket, wait, completion) runs on wave 0 with conditions
-// uniform over the wave, and only the atomics themselves on lane 0: a
-// barrier reached under a condition the compiler takes as divergent within
-// a wave -- e.g. thread 0 alone on both sides of the loop's back edge --
-// lets the structurizer nest the loop so that the other lanes repeat the
-// barriers and the item on their own.
+// The control path (ticket, wait, publication) runs on wave 0 with
+// conditions uniform over the wave, and only the atomics themselves on lane
+// 0: a barrier reached under a condition the compiler takes as divergent
+// within a wave -- e.g. thread 0 alone on both sides of the loop's back
+// edge -- lets the structurizer nest the loop so that the other lanes repeat
+// the barriers and the item on their own.
+//
+// Cache maintenance at device scope (write-back before a completion is
+// published, invalidation after a wait) is paid per phase, not per item:
+// a workgroup keeps its completed items pending and publishes them (one
+// release, one counter update) only before it has to wait or moves to
+// another member, and it skips the wait and the acquire when an earlier
+// wait already saw the member's counter at or above the item's need.  A
+// workgroup never waits while it holds pending items, so every pending item
+// is published before anything can depend on it in a wait.
 template <int DIM, int SEV, typename LT>
 __global__ __launch_bounds__(kBlock) void k_persist(DevGraphT<LT> G, PersistArgsT<LT> P,
                                                     Gas g) {
   constexpr int W = DIM == 2 ? 9 : 27;
-  __shared__ uint32_t s_item;
-  __shared__ int s_go, s_ok;
+  __shared__ uint32_t s_item, s_seen;
+  __shared__ int s_go;
   const int tid = threadIdx.x;
   const bool wave0 = __builtin_amdgcn_readfirstlane(tid) == 0;
   const PersistPlan &pl = P.plan;
+  // uniform state, identical in every wave: the member and counter value of
+  // the last acquire; the member and number of the pending completions
+  int acq_m = -1, pend_m = -1;
+  uint32_t acq_v = 0, pend_n = 0;
+  auto publish = [&] {
+    if (pend_n == 0) return;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (wave0 && tid == 0)
+      __hip_atomic_fetch_add(P.done + pend_m, pend_n, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    pend_n = 0;
+  };
   for (;;) {
     if (wave0) {
       int go = 0;
@@ -1336,7 +1362,10 @@ __global__ __launch_bounds__(kBlock) void k_persist(DevGraphT<LT> G, PersistArgs
       }
     }
     __syncthreads();
-    if (!__builtin_amdgcn_readfirstlane(s_go)) return;
+    if (!__builtin_amdgcn_readfirstlane(s_go)) {
+      publish();
+      return;
+    }
     const uint32_t t = __builtin_amdgcn_readfirstlane(s_item);
     // item -> step, phase, member, item within the member's phase
     const uint32_t step = t / P.items_step;
@@ -1370,12 +1399,19 @@ __global__ __launch_bounds__(kBlock) void k_persist(DevGraphT<LT> G, PersistArgs
              (uint32_t)pl.pre[q][PK_ONE];
     };
     const uint32_t need = step * before(pl.nph) + before(p);
-    if (wave0) {
-      const bool ok = persist_wait(P, P.done + m, need);
-      if (tid == 0) s_ok = ok;
+    if (m != pend_m) publish();
+    if (m != acq_m || need > acq_v) {
+      publish();
+      if (wave0) {
+        const uint32_t v = persist_wait(P, P.done + m, need);
+        if (tid == 0) s_seen = v;
+      }
+      __syncthreads();  // (the acquire of wave 0 covers the workgroup's CU)
+      const uint32_t v = __builtin_amdgcn_readfirstlane(s_seen);
+      if (v < need) return;  // the launch stopped
+      acq_m = m;
+      acq_v = v;
     }
-    __syncthreads();  // (the acquire of wave 0 covers the workgroup's CU)
-    if (!__builtin_amdgcn_readfirstlane(s_ok)) return;
     // buffers of the stage (as the launch path rotates them)
     int c = P.cur;
     for (uint32_t k = 0; k < step; ++k) c = other_buf(c, 0);
@@ -1416,12 +1452,8 @@ __global__ __launch_bounds__(kBlock) void k_persist(DevGraphT<LT> G, PersistArgs
         break;
       default: break;
     }
-    // every wave's stores complete and reach the device-coherent level
-    // before the barrier, so the counter moves after all of them
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (wave0 && tid == 0)
-      __hip_atomic_fetch_add(P.done + m, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    pend_m = m;
+    ++pend_n;
   }
 }
 
