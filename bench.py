@@ -139,11 +139,14 @@ def workload_name(dim, n, seed, mixed=False, ns=False, mu=1e-4, precond="jacobi"
             f"CFL 0.5")
 
 
+PRECISIONS = (abi.PREC_FP64, abi.PREC_MIXED, abi.PREC_MIXED_FP32)
+
+
 def run_steps(graph, U, dim, mixed, steps, warmup, ns=False, mu=1e-4, precond="jacobi"):
     """Time `steps` CFL steps (Strang steps with `ns`) of one solver on the
-    state U after `warmup` untimed ones.  Returns a dict of results."""
-    solver = abi.Solver(graph, gamma=1.4, cfl=0.5,
-                        precision=abi.PREC_MIXED if mixed else abi.PREC_FP64)
+    state U after `warmup` untimed ones; mixed: 0 FP64, 1 FP32 storage, 2
+    FP32 storage and FP32 evaluation.  Returns a dict of results."""
+    solver = abi.Solver(graph, gamma=1.4, cfl=0.5, precision=PRECISIONS[int(mixed)])
     solver.set_state(U)
     if ns:
         solver.set_viscous(mu=mu, lam=0.0, kappa=1.4 * mu, cv=1.0 / 0.4, cg_rtol=1e-10,
@@ -411,12 +414,12 @@ def summary(res, dim, tag, extra=None):
     return d
 
 
-def mixed_error(graph, U0, steps, dim):
+def mixed_error(graph, U0, steps, dim, precision=abi.PREC_MIXED):
     """Mixed precision against the FP64 path (itself parity-tested against
     the oracle) after `steps` CFL steps from the same state with the mixed
     run's time steps: L1 relative difference of rho, m, E; admissibility of
     the mixed result."""
-    mp = abi.Solver(graph, gamma=1.4, cfl=0.5, precision=abi.PREC_MIXED)
+    mp = abi.Solver(graph, gamma=1.4, cfl=0.5, precision=precision)
     mp.set_state(U0)
     taus = [mp.step_cfl() for _ in range(steps)]
     U_mp = mp.get_state()
@@ -434,6 +437,7 @@ def mixed_error(graph, U0, steps, dim):
             "E": nrm(U_mp[dim + 1] - U_64[dim + 1]) / nrm(U_64[dim + 1]),
             "steps": steps, "norm": "L1 relative",
             "positivity_violations": int(not (st.min_rho > 0 and st.min_eps > 0)),
+            "fp64_redo_steps": st.fp64_redo,
             "min_rho": st.min_rho, "min_eps": st.min_eps,
             "reference": "the FP64 path of this library (parity-tested against the "
                          "oracle) from the same state with the same time steps"}
@@ -447,17 +451,21 @@ def single_mode(args):
     mesh, U = workload(dim, n, args.seed)
     t0 = time.perf_counter()
     graph = abi.Graph(mesh)
-    res = run_steps(graph, U, dim, args.mixed, args.steps, args.warmup, ns=args.ns,
+    mixed = 2 if args.fp32_eval else int(args.mixed)
+    res = run_steps(graph, U, dim, mixed, args.steps, args.warmup, ns=args.ns,
                     mu=args.mu, precond=args.precond)
     setup_s = time.perf_counter() - t0 - res["elapsed"]
     cb = copy_bandwidth(res["solver"])
     res["solver"].close()
-    tag = f"{dim}d_{n}" + ("_mixed" if args.mixed else "") + ("_ns" if args.ns else "")
+    tag = f"{dim}d_{n}" + ("_mixed" if mixed else "") + ("_ns" if args.ns else "")
     out = base_line("DoF-updates/s per SSP-RK stage", res["value"], args.steps,
                     args.warmup, res["ms_per_step"],
-                    "f64 (f32 storage)" if args.mixed else "f64",
-                    {"workload": workload_name(dim, n, args.seed, args.mixed, args.ns,
-                                               args.mu, args.precond),
+                    ("f64 (f32 storage, f32 graph-viscosity arithmetic)" if mixed == 2
+                     else "f64 (f32 storage)" if mixed else "f64"),
+                    {"workload": workload_name(dim, n, args.seed, bool(mixed), args.ns,
+                                               args.mu, args.precond)
+                     + (", FP32 evaluation of lambda_max, |c_ij| and the entropy indicator"
+                        if mixed == 2 else ""),
                      "nodes": res["N"], "stages_per_step": 6 if args.ns else 3})
     s = summary(res, dim, tag)
     out["roofline"] = s.pop("roofline")
@@ -470,8 +478,8 @@ def single_mode(args):
                                 "energy": [c[1] for c in res["cg"]],
                                 "low_order": [c[2] for c in res["cg"]],
                                 "limited_steps": sum(c[3] for c in res["cg"])}
-    if args.mixed:
-        out["error_vs_fp64"] = mixed_error(graph, U, 50, dim)
+    if mixed:
+        out["error_vs_fp64"] = mixed_error(graph, U, 50, dim, PRECISIONS[mixed])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(
             dim, args.cpu_sample or (1024 if dim == 2 else (64 if args.ns else 96)),
@@ -516,6 +524,20 @@ def full_run(args):
          "dtype": "f64 (f32 storage)", "speedup_vs_fp64": res["value"] / out["value"],
          "error_vs_fp64": mixed_error(g2, U2, 50, 2)})
     say("2D mixed error", configs["mixed_2d"]["error_vs_fp64"]["rho"])
+    # C4 with FP32 evaluation of the graph-viscosity sweep
+    res = run_steps(g2, U2, 2, 2, args.steps, args.warmup)
+    res["solver"].close()
+    say(f"2D mixed fp32-eval {res['ms_per_step']:.2f} ms/step")
+    configs["mixed_fp32_2d"] = summary(
+        res, 2, f"2d_{n2}_mixed",
+        {"workload": workload_name(2, n2, args.seed, mixed=True) + ", FP32 evaluation of "
+                     "lambda_max, |c_ij| and the entropy indicator",
+         "dtype": "f64 (f32 storage, f32 graph-viscosity arithmetic)",
+         "speedup_vs_fp64": res["value"] / out["value"],
+         "speedup_vs_mixed": res["ms_per_step"] and
+         configs["mixed_2d"]["ms_per_step"] / res["ms_per_step"],
+         "error_vs_fp64": mixed_error(g2, U2, 50, 2, abi.PREC_MIXED_FP32)})
+    say("2D mixed fp32-eval error", configs["mixed_fp32_2d"]["error_vs_fp64"]["rho"])
     del g2, U2
 
     # C3: 3D shock tube, hyperbolic step and Navier-Stokes Strang step
@@ -586,6 +608,9 @@ def main():
     ap.add_argument("--mixed", action="store_true",
                     help="alone: mixed precision (FP32 storage of alpha, d_ij, F^H and "
                          "the limiter coefficients)")
+    ap.add_argument("--fp32-eval", action="store_true",
+                    help="alone: mixed precision with FP32 evaluation of lambda_max, "
+                         "|c_ij| and the entropy indicator")
     ap.add_argument("--serve", action="store_true",
                     help="alone: the serving workload (FP64, or mixed with --mixed)")
     ap.add_argument("--no-serve", action="store_true",
@@ -630,7 +655,7 @@ def main():
                         r.pop("value"), args.serve_steps, 1, None, r.pop("dtype"),
                         {"workload": r.pop("workload"), "requests": r.pop("requests")})
         out.update(r)
-    elif args.only or args.dim == 3 or args.ns or args.mixed:
+    elif args.only or args.dim == 3 or args.ns or args.mixed or args.fp32_eval:
         out = single_mode(args)
     else:
         out = full_run(args)

@@ -118,7 +118,8 @@ typedef struct ns_params {
                      rho in [(1-r_i) rho_min, (1+r_i) rho_max] and
                      Phi >= (1-r_i) Phi_min, r_i = r0 (m_i/|Omega|)^(3/(2d));
                      0 = the strict bounds of Sec. 3.3                      */
-  int precision;  /* NS_PREC_FP64, or NS_PREC_MIXED: the intermediates
+  int precision;  /* NS_PREC_FP64, NS_PREC_MIXED_FP32 (below), or
+                     NS_PREC_MIXED: the intermediates
                      alpha_i, d^L_ij, F^H_i and the limiter coefficients are
                      stored in FP32 (d_ij rounded up, so it stays an upper
                      bound of the wave-speed term; limiter coefficients
@@ -127,7 +128,20 @@ typedef struct ns_params {
                      (m_ij and c_ij are computed, never stored)             */
 } ns_params;
 
-enum { NS_PREC_FP64 = 0, NS_PREC_MIXED = 1 };
+/* NS_PREC_MIXED_FP32: the storage of NS_PREC_MIXED, and the graph-viscosity
+ * sweep (Sec. 3.1, 3.2) evaluated in FP32 for gamma = 7/5: the normal
+ * velocities, pressures, |c_ij|, lambda_max and the entropy indicator.
+ * lambda_max is used only where its FP32 rounding error is certified below
+ * 2^-16 relative (no cancellation beyond fixed factors), and is then
+ * inflated by 2^-16 and rounded up, so d^L_ij stays an upper bound; on the
+ * other entries it is evaluated in FP64.  Every stage re-checks U^L of every
+ * row in FP64 (rho > 0, internal energy > 0); a synchronous step whose
+ * re-check fails is redone from the unchanged state in FP64 arithmetic
+ * (counted in ns_stats_t.fp64_redo), an asynchronous one reports
+ * NS_EBOUNDS; persistent steps are not offered (NS_EINVAL).  Other gamma:
+ * as NS_PREC_MIXED.  The limiter, the bounds, the line search and the state
+ * stay FP64. */
+enum { NS_PREC_FP64 = 0, NS_PREC_MIXED = 1, NS_PREC_MIXED_FP32 = 2 };
 
 typedef struct ns_solver ns_solver;
 
@@ -515,6 +529,8 @@ typedef struct ns_stats_t {
                                      step: velocity, energy, low-order    */
   int fct;             /* 1 if that step used the limited internal energy   */
   double min_eH;       /* its minimum Crank-Nicolson internal energy        */
+  int fp64_redo;       /* NS_PREC_MIXED_FP32: synchronous steps redone in
+                          FP64 arithmetic after a failed FP64 re-check     */
 } ns_stats_t;
 /* Computes the statistics on the device (a reduction over all rows) and
  * waits for it; device scratch for the partial results (about 57 KB) is

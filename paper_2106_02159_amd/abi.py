@@ -20,7 +20,7 @@ NS_OK, NS_EINVAL, NS_ENOMEM, NS_EHIP = 0, -1, -2, -3
 NS_ENOTADMISSIBLE, NS_ECFL, NS_EBOUNDS, NS_ESTATE, NS_ECG = -4, -5, -6, -7, -8
 NS_EABORT = -9
 FCT_AUTO, FCT_ALWAYS = 0, 1
-PREC_FP64, PREC_MIXED = 0, 1
+PREC_FP64, PREC_MIXED, PREC_MIXED_FP32 = 0, 1, 2
 IND_ENTROPY, IND_ONE, IND_ZERO = 0, 1, 2
 LIM_CONVEX, LIM_LOW, LIM_HIGH = 0, 1, 2
 ON_DEVICE, NO_PROJECT = 1, 2
@@ -237,7 +237,7 @@ class Stats(C.Structure):
                 ("edges", C.c_int64), ("limited1", C.c_int64), ("limited2", C.c_int64),
                 ("roots1", C.c_int64), ("roots2", C.c_int64),
                 ("cg_it_v", C.c_int), ("cg_it_e", C.c_int), ("cg_it_l", C.c_int),
-                ("fct", C.c_int), ("min_eH", C.c_double)]
+                ("fct", C.c_int), ("min_eH", C.c_double), ("fp64_redo", C.c_int)]
 
 
 class Boundary(C.Structure):

@@ -49,6 +49,51 @@ __device__ __forceinline__ double lambda_max(const Gas &g, double uL, double pL,
   return fmax(fmax(-l1, 0.0), fmax(l3, 0.0));
 }
 
+// ---------------------------------------------------------------------------
+// FP32 evaluation of the same bound for gamma = 7/5 (mixed-precision mode
+// with FP32 arithmetic).  Approximate reciprocal and square root (1 ulp) are
+// enough: the caller inflates the result by 2^-16 relative
+// (kLambdaInflate) and uses it only where the rounding error is provably
+// below that, i.e. where
+//   (a) neither extreme speed u_L - a_L S_L, u_R + a_R S_R cancels by more
+//       than a factor 3: max(|u| + a S) over both sides <= 3 lambda, and
+//   (b) where a side is in the shock branch (S > 1), the star-pressure
+//       numerator a_L + a_R - (gamma-1)/2 (u_R - u_L) cancels by at most a
+//       factor 2 against a_L + a_R + (gamma-1)/2 (|u_L| + |u_R|) (its
+//       relative error is amplified 7-fold by the power).
+// With u = 2^-24 (the inputs rounded to FP32, the normal velocities formed
+// in FP32): the numerator carries <= 8u relative, the quotient by b_L + b_R
+// <= 12u, the 7th power <= 88u, p*/p <= 91u, each S <= 49u (dS/S <=
+// d(p*/p)/2 since 1 - (gamma+1)/(2 gamma) > 0), each a S <= 51u, so each
+// extreme speed is off by <= 52u (|u| + a S) <= 156u lambda, and with |c_ij|
+// (3u) the product lambda |c_ij| by <= 160u < 2^-16 = 256u.  Elsewhere *ok
+// is false and the caller evaluates lambda_max in FP64.
+constexpr double kLambdaInflate = 1.0 + 1.0 / 65536.0;
+
+__device__ __forceinline__ float lambda_max_f32(const Gas &g, float uL, float pL, float aL,
+                                               float bL, float uR, float pR, float aR,
+                                               float bR, bool *ok) {
+  const float gm1 = (float)g.gm1, cg = (float)g.cg;
+  const float num = aL + aR - 0.5f * gm1 * (uR - uL);
+  float ptr = 0.0f;
+  if (num > 0.0f) {
+    const float x = num * __builtin_amdgcn_rcpf(bL + bR);
+    const float x2 = x * x;
+    const float x4 = x2 * x2;
+    ptr = x4 * x2 * x;  // x^(2 gamma/(gamma-1)) = x^7
+  }
+  const float rL = ptr * __builtin_amdgcn_rcpf(pL), rR = ptr * __builtin_amdgcn_rcpf(pR);
+  const float SL = __builtin_amdgcn_sqrtf(1.0f + cg * fmaxf(rL - 1.0f, 0.0f));
+  const float SR = __builtin_amdgcn_sqrtf(1.0f + cg * fmaxf(rR - 1.0f, 0.0f));
+  const float eL = aL * SL, eR = aR * SR;
+  const float lam = fmaxf(fmaxf(eL - uL, 0.0f), fmaxf(uR + eR, 0.0f));
+  const float M = fmaxf(fabsf(uL) + eL, fabsf(uR) + eR);
+  const bool shock = rL > 0.999f || rR > 0.999f;
+  *ok = M <= 3.0f * lam &&
+        (!shock || aL + aR + 0.5f * gm1 * (fabsf(uL) + fabsf(uR)) <= 2.0f * num);
+  return lam;
+}
+
 // psi(l) = eps(u + l P) - phi_min rho(u + l P)^gamma and its derivative.
 template <int DIM>
 __device__ __forceinline__ double psi_eval(const Gas &g, const double *u,

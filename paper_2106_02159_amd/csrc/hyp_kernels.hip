@@ -335,6 +335,174 @@ __device__ __forceinline__ void visc_row(const DevGraphT<LT> &G,
   else alpha[i] = LT(0);
 }
 
+// FP32 evaluation (mixed-precision mode with FP32 arithmetic, entropy
+// indicator, gamma = 7/5): the same quantities as visc_row with the
+// velocities, pressures, |c_ij|, the fluxes and commutator terms of the
+// indicator and lambda_max in FP32.  d_ij = lambda |c_ij| (1 + 2^-16) rounded
+// up stays an upper bound of the FP64 value where lambda_max_f32 certifies
+// its error; on the other entries (and for a padding row) lambda_max is
+// evaluated in FP64 from the FP64 state, as in visc_row.
+template <int DIM>
+__device__ __forceinline__ float vel_pres_f(float gm1, const float *u, float *v, float &p) {
+  const float ir = __builtin_amdgcn_rcpf(u[0]);
+  float m2 = 0.0f;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) m2 += u[1 + k] * u[1 + k];
+  const float eps = u[DIM + 1] - 0.5f * m2 * ir;
+  p = gm1 * eps;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) v[k] = u[1 + k] * ir;
+  return eps;
+}
+
+template <int DIM, typename LT>
+__device__ __forceinline__ void visc_row_f32(const DevGraphT<LT> &G,
+                                             const double *__restrict__ U,
+                                             const double *__restrict__ aux,
+                                             LT *__restrict__ d, LT *__restrict__ alpha,
+                                             const Gas &g, uint32_t blk, int64_t i) {
+  using X = Aux<DIM>;
+  using C = Cfg<DIM, NS_CH_VISC>;
+  constexpr int NC = C::NC;
+  const int64_t N = G.N;
+  if (i >= N) return;
+  BoxNbr<DIM> jv = block_nbr<DIM>(G, blk, i);
+  const float gm1 = (float)g.gm1;
+  double ui[NC], vi[DIM], pi;
+  load_state<NC>(U, N, i, ui);
+  const double eps_i = vel_pres<DIM>(g, ui, vi, pi);  // FP64 (the fallback needs it)
+  const double ai = aux[X::A * N + i], bi = aux[X::B * N + i];
+  const bool wall_i = G.wall[i] != 0;
+  // entropy variables of row i, formed in FP64 once per row
+  float etap[NC], vif[DIM];
+  {
+    double m2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) m2 += ui[1 + k] * ui[1 + k];
+    const double s = -aux[X::ETA * N + i] / ui[0];
+    const double ie = 1.0 / eps_i;
+    etap[0] = (float)(g.gamma - s - m2 / (2.0 * ui[0] * eps_i));
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      etap[1 + k] = (float)(ui[1 + k] * ie);
+      vif[k] = (float)vi[k];
+    }
+    etap[NC - 1] = (float)(-ui[0] * ie);
+  }
+  const float pif = (float)pi, aif = (float)ai, bif = (float)bi;
+  float num = 0.0f, den = 0.0f, scl = 0.0f;
+#pragma unroll
+  for (int ch = 0; ch < C::NCH; ++ch) {
+    jv.fence();
+    double c[C::CH][DIM], uj[C::CH][NC], aj[C::CH], bj[C::CH], etaj[C::CH];
+    int32_t jc[C::CH];
+#pragma unroll
+    for (int kk = 0; kk < C::CH; ++kk) {
+      const int k = ch * C::CH + kk;
+      jc[kk] = jv[k];
+      const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
+      jv.grad(k, c[kk]);
+      aj[kk] = aux[X::A * N + js];
+      bj[kk] = aux[X::B * N + js];
+      load_state<NC>(U, N, js, uj[kk]);
+      etaj[kk] = aux[X::ETA * N + js];
+    }
+#pragma unroll
+    for (int kk = 0; kk < C::CH; ++kk) {
+      const int k = ch * C::CH + kk;
+      const int32_t j = jc[kk];
+      if (j < 0) continue;
+      float cf[DIM], ujf[NC], vjf[DIM], pjf;
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) cf[q] = (float)c[kk][q];
+#pragma unroll
+      for (int q = 0; q < NC; ++q) ujf[q] = (float)uj[kk][q];
+      vel_pres_f<DIM>(gm1, ujf, vjf, pjf);
+      float c2 = 0.0f, vc = 0.0f;
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) {
+        c2 += cf[q] * cf[q];
+        vc += vjf[q] * cf[q];
+      }
+      const float cn = __builtin_amdgcn_sqrtf(c2);
+      {
+        // commutator term of the indicator: eta_j (v_j.c) - eta'(U_i).f(U_j) c
+        const float etajf = (float)etaj[kk];
+        float t = etajf * vc;
+        t -= etap[0] * (ujf[0] * vc);
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) t -= etap[1 + q] * (ujf[1 + q] * vc + pjf * cf[q]);
+        t -= etap[NC - 1] * (vc * (ujf[NC - 1] + pjf));
+        num += t;
+        den += fabsf(t);
+        scl += cn * (float)aj[kk] * (ujf[0] + fabsf(etajf));
+      }
+      if (j > i) {
+        const int64_t e = eidx<DIM>(k, i);
+        const int kt = tslot<DIM>(k);
+        const int64_t et = eidx<DIM>(kt, j);
+        const float icn = __builtin_amdgcn_rcpf(cn);
+        float uL = 0.0f, uR = 0.0f;
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) {
+          uL += vif[q] * cf[q];
+          uR += vjf[q] * cf[q];
+        }
+        bool ok;
+        const float lam = lambda_max_f32(g, uL * icn, pif, aif, bif, uR * icn, pjf,
+                                         (float)aj[kk], (float)bj[kk], &ok);
+        double dij = (double)lam * (double)cn * kLambdaInflate;
+        double vj[DIM], pj;
+        if (!ok || wall_i) vel_pres<DIM>(g, uj[kk], vj, pj);
+        if (!ok) {  // FP64, as visc_row
+          double c2d = 0.0;
+#pragma unroll
+          for (int q = 0; q < DIM; ++q) c2d += c[kk][q] * c[kk][q];
+          const double cnd = sqrt(c2d), icnd = 1.0 / cnd;
+          double uLd = 0.0, uRd = 0.0;
+#pragma unroll
+          for (int q = 0; q < DIM; ++q) {
+            uLd += vi[q] * c[kk][q] * icnd;
+            uRd += vj[q] * c[kk][q] * icnd;
+          }
+          dij = lambda_max<1>(g, uLd, pi, ai, bi, uRd, pj, aj[kk], bj[kk]) * cnd;
+        }
+        if (wall_i) {
+          // both ends may be on the wall: c_ji != -c_ij, take both
+          // directions (the transposed one in FP64: walls are a thin set)
+          double ct[DIM];
+          grad_transposed<DIM>(k, c[kk], ct);
+          double ct2 = 0.0;
+#pragma unroll
+          for (int q = 0; q < DIM; ++q) ct2 += ct[q] * ct[q];
+          const double ctn = sqrt(ct2);
+          const double ictn = 1.0 / ctn;
+          double uLt = 0.0, uRt = 0.0;
+#pragma unroll
+          for (int q = 0; q < DIM; ++q) {
+            uLt += vj[q] * ct[q] * ictn;
+            uRt += vi[q] * ct[q] * ictn;
+          }
+          dij = fmax(dij, lambda_max<1>(g, uLt, pj, aj[kk], bj[kk], uRt, pi, ai, bi) * ctn);
+        }
+        const LT dst = to_lt_up<LT>(dij);
+        st_once(&d[e], dst);
+        st_once(&d[et], dst);
+      }
+    }
+  }
+  alpha[i] = to_lt<LT>(den + scl > 0.0f ? fabsf(num) / (den + 1e-2f * scl) : 0.0f);
+}
+
+template <int DIM, typename LT>
+__global__ __launch_bounds__(kBlock) void k_visc_f32(DevGraphT<LT> G,
+                                                     const double *__restrict__ U,
+                                                     const double *__restrict__ aux,
+                                                     LT *__restrict__ d,
+                                                     LT *__restrict__ alpha, Gas g) {
+  visc_row_f32<DIM, LT>(G, U, aux, d, alpha, g, blockIdx.x, row_id());
+}
+
 template <int DIM, int IND, int SEV, typename LT>
 __global__ __launch_bounds__(kBlock) void k_visc(DevGraphT<LT> G,
                                                  const double *__restrict__ U,
@@ -1490,7 +1658,16 @@ void stage_impl(const Gas &gas, const DevGraphT<LT> &G, const StageArgsT<LT> &A,
   else
     NS_LAUNCH("prim", hipLaunchKernelGGL((k_prim<DIM, true>), grid, block, 0, s, G.N, A.U,
                                          A.aux, gas));
-  if (indicator == 0)
+  bool f32 = false;
+  if constexpr (SEV == 1 && sizeof(LT) == 4) {
+    if (indicator == 0 && A.fp32_eval) {
+      f32 = true;
+      NS_LAUNCH("visc", hipLaunchKernelGGL((k_visc_f32<DIM, LT>), grid, block, 0, s, G, A.U,
+                                           A.aux, A.d, A.alpha, gas));
+    }
+  }
+  if (f32) {
+  } else if (indicator == 0)
     NS_LAUNCH("visc", hipLaunchKernelGGL((k_visc<DIM, 0, SEV, LT>), grid, block, 0, s, G,
                                          A.U, A.aux, A.d, A.alpha, gas));
   else if (indicator == 1)

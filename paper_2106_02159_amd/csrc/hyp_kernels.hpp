@@ -77,6 +77,9 @@ struct StageArgsT {
   // adaptive CFL steps: flags[3] (of the member) is set where the low-order
   // update U^L is not admissible
   int check_low = 0;
+  // (host side) mixed precision with FP32 arithmetic: the graph viscosity
+  // sweep evaluates lambda_max, |c_ij| and the indicator in FP32
+  int fp32_eval = 0;
   // Work list of the edges (sliced ELL index) whose line search needs the
   // root of the entropy bound; W*Np entries, so that it holds every edge.
   // Pass 1 fills it and k_root<1> drains it before pass 2 fills it again;

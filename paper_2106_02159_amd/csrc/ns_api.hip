@@ -132,6 +132,11 @@ struct ns_solver {
   // mixed precision: FP32 storage of alpha, d_ij, F^H and the limiter
   // coefficients (the FP64 arrays stay null)
   bool mixed = false;
+  // NS_PREC_MIXED_FP32: the graph viscosity sweep evaluates in FP32, U^L is
+  // re-checked in FP64 every stage; redo_fp64 while a synchronous step is
+  // redone in FP64 arithmetic after a failed re-check (fp64_redo counts them)
+  bool fp32_eval = false, redo_fp64 = false;
+  int fp64_redo = 0;
   float *alphaf = nullptr, *df = nullptr, *FHf = nullptr, *lt1f = nullptr,
         *lt2f = nullptr;
   double *mi = nullptr, *rmi = nullptr, *lfac = nullptr, *rrel = nullptr;
@@ -220,6 +225,7 @@ struct ns_solver {
     b.sa = a.sa; b.sb = a.sb; b.check_cfl = a.check_cfl; b.q = a.q; b.qcnt = a.qcnt;
     b.seg = a.seg; b.mblk = a.mblk; b.nmem = a.nmem; b.check_low = a.check_low;
     b.alpha = alphaf; b.d = df; b.FH = FHf; b.lt1 = lt1f; b.lt2 = lt2f;
+    b.fp32_eval = fp32_eval && !redo_fp64;
     return b;
   }
   ns::StageArgs args(int in, int out, double sa, double sb, int check) const {
@@ -228,7 +234,7 @@ struct ns_solver {
     a.aux = aux; a.alpha = alpha; a.d = d; a.UL = UL; a.FH = FH; a.bnds = bnds;
     a.lt1 = lt1; a.lt2 = lt2; a.U1 = U1; a.partial = partial; a.tau = tau;
     a.flags = flags; a.sa = sa; a.sb = sb; a.check_cfl = adaptive ? 0 : check;
-    a.check_low = adaptive ? 1 : 0;
+    a.check_low = adaptive || fp32_eval ? 1 : 0;
     a.q = q; a.qcnt = qcnt;
     a.seg = seg; a.mblk = mblk; a.nmem = nmem;
     return a;
@@ -398,9 +404,20 @@ int ssprk3_enqueue(ns_solver *s, double dt, bool auto_dt) {
 int ssprk3(ns_solver *s, double dt, bool auto_dt, double *dt_out) {
   if (!s->has_state) return s->fail(NS_ESTATE, "no state set");
   ns::launch_clear_flags(s->flags, s->stream);
-  const int o1 = ssprk3_enqueue(s, dt, auto_dt);
+  int o1 = ssprk3_enqueue(s, dt, auto_dt);
   int rc = read_flags(s);
   if (rc != NS_OK) return rc;
+  if (s->fp32_eval && (s->hflags[3] || s->hflags[1])) {
+    // the FP64 re-check found an inadmissible U^L (or stage result) in some
+    // row: the step again from the unchanged S[cur], in FP64 arithmetic
+    ++s->fp64_redo;
+    s->redo_fp64 = true;
+    ns::launch_clear_flags(s->flags, s->stream);
+    o1 = ssprk3_enqueue(s, dt, auto_dt);
+    s->redo_fp64 = false;
+    rc = read_flags(s);
+    if (rc != NS_OK) return rc;
+  }
   if (dt_out) *dt_out = *s->htau;
   if (s->hflags[0]) {
     char buf[160];
@@ -718,7 +735,7 @@ int64_t slip_count(const ns::MeshGraph &m) {
 int64_t footprint(const Layout &Lt, const ns_params *p) {
   const ns::MeshGraph &m = *Lt.mgs[0];
   const int64_t N = Lt.N, Np = Lt.Np, W = m.W, dim = m.dim, nc = dim + 2;
-  const int64_t L = p->precision == NS_PREC_MIXED ? 4 : 8;
+  const int64_t L = p->precision != NS_PREC_FP64 ? 4 : 8;
   const int64_t nblocks = (N + ns::kBlock - 1) / ns::kBlock;
   const int64_t nm = (int64_t)Lt.mgs.size();
   int64_t nslip = 0;
@@ -775,10 +792,11 @@ int create_impl(const Layout &Lt, const ns_params *p, void *stream, ns_solver **
       !(p->cfl > 0.0 && p->cfl <= 1.0) || p->indicator < 0 || p->indicator > 2 ||
       p->limiter < 0 || p->limiter > 2 || (p->passes != 1 && p->passes != 2) ||
       !(p->relax >= 0.0) || !std::isfinite(p->relax) ||
-      (p->precision != NS_PREC_FP64 && p->precision != NS_PREC_MIXED)) {
+      (p->precision != NS_PREC_FP64 && p->precision != NS_PREC_MIXED &&
+       p->precision != NS_PREC_MIXED_FP32)) {
     g_create_error = "invalid parameters (need 1 < gamma <= 5/3, 0 < cfl <= 1, "
                      "indicator/limiter in range, passes 1 or 2, relax >= 0, "
-                     "precision NS_PREC_FP64 or NS_PREC_MIXED)";
+                     "precision NS_PREC_FP64, NS_PREC_MIXED or NS_PREC_MIXED_FP32)";
     return NS_EINVAL;
   }
   const ns::MeshGraph &m0 = *Lt.mgs[0];
@@ -791,7 +809,8 @@ int create_impl(const Layout &Lt, const ns_params *p, void *stream, ns_solver **
   keep_pool_memory();
   s->mg = m0;
   s->prm = *p;
-  s->mixed = p->precision == NS_PREC_MIXED;
+  s->mixed = p->precision != NS_PREC_FP64;
+  s->fp32_eval = p->precision == NS_PREC_MIXED_FP32;
   s->dim = m0.dim;
   s->nc = s->dim + 2;
   s->N = Lt.N;
@@ -1565,6 +1584,8 @@ int ns_step_cfl_persistent(ns_solver *s, int nsteps, double wait_s) {
                               "limiting with two passes");
   if (s->nnr > 0)
     return s->fail(NS_EINVAL, "persistent steps do not treat non-reflecting boundaries");
+  if (s->fp32_eval)
+    return s->fail(NS_EINVAL, "persistent steps run FP64 or FP32-storage arithmetic only");
   if (!s->give_up && !(s->give_up = take_give_up_word()))
     return s->fail(NS_ENOMEM, "no give-up word left (pinned host memory)");
   if (s->pgrid <= 0) {
@@ -1758,7 +1779,10 @@ int ns_pack_finish(ns_pack *k, int *status, double *t) {
   if (e != hipSuccess) return s->hipfail(e, "asynchronous step status");
   const bool gave_up = persistent_gave_up(s);
   for (int r = 0; r < nm; ++r) {
-    status[r] = gave_up ? NS_EABORT : fl[4 * r] ? NS_ECFL : fl[4 * r + 1] ? NS_EBOUNDS : NS_OK;
+    status[r] = gave_up                                           ? NS_EABORT
+                : fl[4 * r]                                       ? NS_ECFL
+                : fl[4 * r + 1] || (s->fp32_eval && fl[4 * r + 3]) ? NS_EBOUNDS
+                                                                  : NS_OK;
     t[r] = ta[r];
   }
   return NS_OK;
@@ -1799,7 +1823,8 @@ int ns_async_finish(ns_solver *s, double *t) {
     return s->fail(NS_EABORT, s->hpstop[2] & 4 ? "persistent steps gave up: give-up word set"
                                                : "persistent steps gave up: wait limit reached");
   if (s->hflags[0]) return s->fail(NS_ECFL, "a step exceeded the stage CFL limit");
-  if (s->hflags[1]) return s->fail(NS_EBOUNDS, "a stage produced an inadmissible state");
+  if (s->hflags[1] || (s->fp32_eval && s->hflags[3]))
+    return s->fail(NS_EBOUNDS, "a stage produced an inadmissible state");
   return NS_OK;
 }
 
@@ -1905,6 +1930,7 @@ int stats_into(ns_solver *s, double *part, ns_stats_t *out) {
   out->cg_it_l = s->pinfo.it_l;
   out->fct = s->pinfo.fct;
   out->min_eH = s->pinfo.min_eH;
+  out->fp64_redo = s->fp64_redo;
   return NS_OK;
 }
 }  // namespace

@@ -119,3 +119,119 @@ def test_mixed_3d_and_invalid_precision():
     assert rho_e <= 1e-6
     with pytest.raises(abi.NSError):
         abi.Solver(abi.Graph(mesh), precision=7)
+
+
+# ---------------------------------------------------------------------------
+# NS_PREC_MIXED_FP32: lambda_max, |c_ij| and the indicator in FP32 (with the
+# certified inflation and the per-entry FP64 fallback), U^L re-checked in FP64.
+
+def test_fp32_eval_fifty_steps_against_fp64_oracle():
+    """The C4 bar at 256^2: L1 relative error in density <= 1e-6 after 50
+    steps of the oracle's time steps, every stage admissible, no FP64 redo,
+    mass and energy conserved (d_ij and alpha stay symmetric)."""
+    mesh, U0 = W.four_quadrant_state(256, seed=0)
+    og = O.Graph(2, mesh.n, mesh.lo, mesh.hi, mesh.periodic)
+    prm = O.params()
+    U = og.slip_bc(U0)
+    s = abi.Solver(abi.Graph(mesh), precision=abi.PREC_MIXED_FP32)
+    s.set_state(U, project=False)
+    ref = U.copy()
+    m = og.mi
+    mass0, ener0 = np.dot(m, U[0]), np.dot(m, U[3])
+    for step in range(50):
+        tau = og.compute_dt(prm, ref)
+        ref, st = og.ssprk3_step(prm, ref, tau)
+        assert st == 0
+        s.step(tau)
+        out = s.get_state()
+        eps = out[3] - 0.5 * (out[1] ** 2 + out[2] ** 2) / out[0]
+        assert np.all(out[0] > 0) and np.all(eps > 0), step
+    rho_e, mom_e, ene_e = l1_rel(out, ref)
+    say(f"FP32 evaluation, L1 relative error after 50 steps: rho {rho_e:.3e} "
+        f"m {mom_e:.3e} E {ene_e:.3e}")
+    assert rho_e <= 1e-6
+    assert mom_e <= 1e-5 and ene_e <= 1e-5
+    assert s.stats().fp64_redo == 0
+    assert np.dot(m, out[0]) == pytest.approx(mass0, rel=1e-13)
+    assert np.dot(m, out[3]) == pytest.approx(ener0, rel=1e-13)
+
+
+@pytest.mark.parametrize("case", ["quadrant", "vortex"])
+def test_fp32_eval_d_is_an_upper_bound(case):
+    """d_ij of one stage against the FP64 solver's: never below it (beyond
+    FP64 rounding), above it by at most the 2^-16 inflation plus FP32
+    rounding; alpha within 1e-5 of the FP64 value."""
+    mesh, U0 = (W.four_quadrant_state(96, seed=1) if case == "quadrant"
+                else W.vortex_state(80))
+    g = abi.Graph(mesh)
+    s32 = abi.Solver(g, precision=abi.PREC_MIXED_FP32, passes=2)
+    s64 = abi.Solver(g, passes=2)
+    for s in (s32, s64):
+        s.set_state(U0)
+    tau = s64.compute_dt()
+    assert s32.fe_stage(tau) == abi.NS_OK and s64.fe_stage(tau) == abi.NS_OK
+    d32, d64 = s32.debug("d"), s64.debug("d")
+    mask = d64 > 0
+    ratio = d32[mask] / d64[mask]
+    say(f"{case}: d32/d64 in [{ratio.min():.9f}, {ratio.max():.9f}]")
+    assert ratio.min() >= 1.0 - 1e-15
+    # inflation 2^-16 plus the certified FP32 error (< 160 units of 2^-24)
+    # and the upward rounding to FP32 storage
+    assert ratio.max() <= 1.0 + 2.0 ** -16 + 1e-5
+    a32, a64 = s32.debug("alpha"), s64.debug("alpha")
+    assert np.abs(a32 - a64).max() <= 1e-5
+
+
+def test_fp32_eval_recheck_redoes_the_step_in_fp64():
+    """A time step ten times the CFL limit on a strong expansion makes U^L
+    inadmissible: the FP64 re-check catches it, the step is redone in FP64
+    arithmetic (counted), and fails there too with the state unchanged."""
+    mesh = W.Mesh(2, (64, 8), (0.0, 0.0), (1.0, 0.125), (False, True))
+    x, _ = mesh.coords()
+    U = np.zeros((4, mesh.N))
+    U[0] = 1.0
+    U[1] = np.where(x < 0.5, -10.0, 10.0)
+    U[3] = 1.0 / 0.4 + 0.5 * U[1] ** 2
+    s = abi.Solver(abi.Graph(mesh), precision=abi.PREC_MIXED_FP32)
+    s.set_state(U, project=False)
+    before = s.get_state()
+    dt = 10.0 * s.compute_dt()
+    with pytest.raises(abi.NSError):
+        s.step(dt)
+    assert s.stats().fp64_redo == 1
+    assert np.array_equal(s.get_state(), before)
+
+
+def test_fp32_eval_async_equals_sync_and_no_persistent():
+    mesh, U = W.four_quadrant_state(100, seed=4)
+    g = abi.Graph(mesh)
+    a = abi.Solver(g, precision=abi.PREC_MIXED_FP32)
+    b = abi.Solver(g, precision=abi.PREC_MIXED_FP32)
+    a.set_state(U)
+    b.set_state(U)
+    t = sum(a.step_cfl() for _ in range(4))
+    b.step_cfl_async(4)
+    rc, tb = b.async_finish()
+    assert rc == abi.NS_OK and tb == t
+    assert np.array_equal(a.get_state(), b.get_state())
+    with pytest.raises(abi.NSError) as ei:
+        b.step_cfl_persistent(1)
+    assert ei.value.code == abi.NS_EINVAL
+
+
+def test_fp32_eval_3d_against_oracle():
+    mesh, U0 = W.shock_tube_state(20, seed=2)
+    og = O.Graph(3, mesh.n, mesh.lo, mesh.hi, mesh.periodic)
+    prm = O.params()
+    U = og.slip_bc(U0)
+    s = abi.Solver(abi.Graph(mesh), precision=abi.PREC_MIXED_FP32)
+    s.set_state(U, project=False)
+    ref = U.copy()
+    for _ in range(10):
+        tau = og.compute_dt(prm, ref)
+        ref, _ = og.ssprk3_step(prm, ref, tau)
+        s.step(tau)
+    rho_e, mom_e, ene_e = l1_rel(s.get_state(), ref)
+    say(f"FP32 evaluation 3D: L1 relative error after 10 steps: rho {rho_e:.3e}")
+    assert rho_e <= 1e-6
+    assert s.stats().fp64_redo == 0
