@@ -457,7 +457,8 @@ def single_mode(args):
     setup_s = time.perf_counter() - t0 - res["elapsed"]
     cb = copy_bandwidth(res["solver"])
     res["solver"].close()
-    tag = f"{dim}d_{n}" + ("_mixed" if mixed else "") + ("_ns" if args.ns else "")
+    tag = (f"{dim}d_{n}" + ("_mixed" if mixed else "") + ("_fp32" if mixed == 2 else "")
+           + ("_ns" if args.ns else ""))
     out = base_line("DoF-updates/s per SSP-RK stage", res["value"], args.steps,
                     args.warmup, res["ms_per_step"],
                     ("f64 (f32 storage, f32 graph-viscosity arithmetic)" if mixed == 2
@@ -478,7 +479,7 @@ def single_mode(args):
                                 "energy": [c[1] for c in res["cg"]],
                                 "low_order": [c[2] for c in res["cg"]],
                                 "limited_steps": sum(c[3] for c in res["cg"])}
-    if mixed:
+    if mixed and not args.no_error:
         out["error_vs_fp64"] = mixed_error(graph, U, 50, dim, PRECISIONS[mixed])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(
@@ -529,7 +530,7 @@ def full_run(args):
     res["solver"].close()
     say(f"2D mixed fp32-eval {res['ms_per_step']:.2f} ms/step")
     configs["mixed_fp32_2d"] = summary(
-        res, 2, f"2d_{n2}_mixed",
+        res, 2, f"2d_{n2}_mixed_fp32",
         {"workload": workload_name(2, n2, args.seed, mixed=True) + ", FP32 evaluation of "
                      "lambda_max, |c_ij| and the entropy indicator",
          "dtype": "f64 (f32 storage, f32 graph-viscosity arithmetic)",
@@ -640,6 +641,9 @@ def main():
                     help="oracle sample, nodes per direction (default 1024 in "
                          "2D, 96 in 3D)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-error", action="store_true",
+                    help="alone, mixed precision: skip the 50-step comparison with the "
+                         "FP64 path (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the hyperbolic step is benchmarked "
