@@ -1496,6 +1496,8 @@ void open_async(ns_solver *s) {
 // new one is set, and the give-up word is cleared for the next run.
 bool persistent_gave_up(ns_solver *s) {
   if (s->hpstop[2] == 0) return false;
+  s->err = s->hpstop[2] & 4 ? "persistent steps gave up: give-up word set"
+                            : "persistent steps gave up: wait limit reached";
   s->has_state = false;
   std::fill(s->mset.begin(), s->mset.end(), 0);
   if (s->give_up) __atomic_store_n(s->give_up, 0, __ATOMIC_SEQ_CST);
@@ -1819,9 +1821,7 @@ int ns_async_finish(ns_solver *s, double *t) {
   if (e != hipSuccess) return s->hipfail(e, "asynchronous step status");
   tt = *s->htau;
   if (t) *t = tt;
-  if (persistent_gave_up(s))
-    return s->fail(NS_EABORT, s->hpstop[2] & 4 ? "persistent steps gave up: give-up word set"
-                                               : "persistent steps gave up: wait limit reached");
+  if (persistent_gave_up(s)) return NS_EABORT;
   if (s->hflags[0]) return s->fail(NS_ECFL, "a step exceeded the stage CFL limit");
   if (s->hflags[1] || (s->fp32_eval && s->hflags[3]))
     return s->fail(NS_EBOUNDS, "a stage produced an inadmissible state");
