@@ -235,3 +235,49 @@ def test_fp32_eval_3d_against_oracle():
     say(f"FP32 evaluation 3D: L1 relative error after 10 steps: rho {rho_e:.3e}")
     assert rho_e <= 1e-6
     assert s.stats().fp64_redo == 0
+
+
+def test_fp32_eval_falls_back_to_fp64_at_high_mach():
+    """A Mach-10 flow (|u| >> a, so the star-pressure numerator is dominated
+    by the rounding of the normal velocities): the certificate fails on many
+    entries, which then carry the FP64 value rounded up to FP32 (ratio to
+    the FP64 solver's d_ij below 1 + 2^-23), the others the inflated FP32
+    value; none is below the FP64 value."""
+    mesh = W.Mesh(2, (48, 48), (0.0, 0.0), (1.0, 1.0), (True, True))
+    x, y = mesh.coords()
+    rng = np.random.default_rng(7)
+    rho = 1.0 + 0.2 * np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y) + 0.01 * rng.random(mesh.N)
+    p = 1.0 + 0.1 * np.cos(2 * np.pi * (x + y))
+    a = np.sqrt(1.4 * p / rho)
+    u = 10.0 * a.max() * (1.0 + 0.05 * np.sin(2 * np.pi * y))
+    v = 0.3 * np.sin(2 * np.pi * x)
+    U = np.stack([rho, rho * u, rho * v, p / 0.4 + 0.5 * rho * (u * u + v * v)])
+    g = abi.Graph(mesh)
+    s32 = abi.Solver(g, precision=abi.PREC_MIXED_FP32)
+    s64 = abi.Solver(g)
+    for s in (s32, s64):
+        s.set_state(U)
+    tau = s64.compute_dt()
+    assert s32.fe_stage(tau) == abi.NS_OK and s64.fe_stage(tau) == abi.NS_OK
+    d32, d64 = s32.debug("d"), s64.debug("d")
+    mask = d64 > 0
+    ratio = d32[mask] / d64[mask]
+    fell_back = ratio < 1.0 + 2.0 ** -20
+    say(f"Mach 10: {fell_back.mean():.3f} of the entries evaluated in FP64")
+    assert ratio.min() >= 1.0 - 1e-15
+    assert fell_back.any() and (~fell_back).any()
+    assert ratio[fell_back].max() <= 1.0 + 2.0 ** -22
+
+
+def test_fp32_eval_other_gamma_is_fp32_storage():
+    """For gamma != 7/5 the FP32 evaluation is not offered: the mode gives
+    the FP32-storage results bit for bit."""
+    mesh, U = W.four_quadrant_state(70, seed=6, gamma=5.0 / 3.0)
+    g = abi.Graph(mesh)
+    a = abi.Solver(g, gamma=5.0 / 3.0, precision=abi.PREC_MIXED)
+    b = abi.Solver(g, gamma=5.0 / 3.0, precision=abi.PREC_MIXED_FP32)
+    for s in (a, b):
+        s.set_state(U)
+    for _ in range(3):
+        assert a.step_cfl() == b.step_cfl()
+    assert np.array_equal(a.get_state(), b.get_state())
