@@ -281,3 +281,54 @@ def test_stage_cfl_flag():
     assert st == 0
     _, st = g.fe_stage(prm, U, tau * 1.0001)
     assert st == 1
+
+
+def _alpha(mesh, U):
+    g = graph_of(mesh)
+    _, _, dbg = g.fe_stage(O.params(cfl=0.5), U, 1e-4, debug=True)
+    return dbg["alpha"]
+
+
+def test_indicator_commutator_is_second_order_in_the_perturbation():
+    """Chain rule F'(U) = eta'(U) f'(U) (the entropy pair): for U_j = U_i +
+    delta_j, F(U_j) - eta'(U_i) f(U_j) = F(U_i) - eta'(U_i) f(U_i) + O(|delta|^2),
+    and sum_j c_ij = 0 removes the constant, so N_i = O(delta^2) while every
+    |t_ij| stays O(1) (the state moves).  On a uniform moving state with a
+    smooth perturbation of amplitude d, alpha therefore falls 100-fold per
+    decade of d; a wrong entropy variable or flux term leaves an O(d) part
+    (10-fold)."""
+    mesh = W.Mesh(2, (24, 24), (0.0, 0.0), (1.0, 1.0), (True, True))
+    x, y = mesh.coords()
+    f = [np.sin(2 * np.pi * x) * np.cos(4 * np.pi * y),
+         np.cos(2 * np.pi * (x + y)),
+         np.sin(4 * np.pi * x + 1.0) * np.sin(2 * np.pi * y),
+         np.cos(2 * np.pi * x - 0.5)]
+    amax = []
+    for d in (1e-2, 1e-3, 1e-4):
+        U = W.conserved(1.0 + d * f[0], (0.7 + d * f[1], -0.4 + d * f[2]),
+                        1.0 + d * f[3], 1.4)
+        amax.append(_alpha(mesh, U).max())
+    rates = np.log10(np.array(amax[:-1]) / np.array(amax[1:]))
+    assert np.all(np.abs(rates - 2.0) < 0.1), (amax, rates)
+
+
+def test_indicator_is_invariant_under_rotation():
+    """A 90-degree rotation of the periodic unit square maps nodes to nodes
+    ((x, y) -> (1 - y, x)) and velocities (u, v) -> (-v, u); alpha must move
+    with the nodes (a swapped or mis-signed component of c_ij, v or the
+    entropy variables breaks this)."""
+    n = 20
+    mesh = W.Mesh(2, (n, n), (0.0, 0.0), (1.0, 1.0), (True, True))
+    U = W.random_rough_state(mesh, seed=11)
+    a = _alpha(mesh, U).reshape(n, n)          # [j (y), i (x)]
+    rho, mx, my, E = (c.reshape(n, n) for c in U)
+    # node (i, j) goes to (i', j') = ((n - j) % n, i)
+    Ur = np.empty((4, n, n))
+    j, i = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    ip, jp = (n - j) % n, i
+    Ur[0][jp, ip] = rho[j, i]
+    Ur[1][jp, ip] = -my[j, i]
+    Ur[2][jp, ip] = mx[j, i]
+    Ur[3][jp, ip] = E[j, i]
+    ar = _alpha(mesh, Ur.reshape(4, -1)).reshape(n, n)
+    assert np.abs(ar[jp, ip] - a[j, i]).max() <= 1e-13
