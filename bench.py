@@ -85,14 +85,18 @@ def kernel_bytes(name: str, dim: int, mixed: bool = False) -> float:
 
 def source_sha() -> str:
     """sha256 (first 16 hex) of the device code and its launch code:
-    csrc/*.hip and *.hpp (the host-only *.cpp files -- graph and element
-    tables, the server -- do not change what a kernel moves)."""
+    csrc/*.hip and *.hpp except the host driver ns_api.hip (it allocates,
+    uploads and sequences the launches whose kernels and grids the other
+    files define; like the host-only *.cpp files -- graph and element
+    tables, the server -- it does not change what a kernel moves)."""
     import glob
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2106_02159_amd", "csrc")
     for ext in ("hip", "hpp"):
         for p in sorted(glob.glob(os.path.join(csrc, f"*.{ext}"))):
+            if os.path.basename(p) == "ns_api.hip":
+                continue
             h.update(open(p, "rb").read())
     return h.hexdigest()[:16]
 

@@ -279,7 +279,8 @@ namespace {
 // their first persistent step and return it when destroyed.
 constexpr int kGiveUpSlots = 1024;
 std::mutex g_give_up_mu;
-int *g_give_up_host = nullptr;
+int *g_give_up_host = nullptr;  // the slots as the host writes them
+int *g_give_up_dev = nullptr;   // the same slots as kernels address them
 std::vector<int> g_give_up_free;
 
 int *take_give_up_word() {
@@ -292,7 +293,14 @@ int *take_give_up_word() {
       (void)hipGetLastError();
       return nullptr;
     }
+    void *d = nullptr;
+    if (hipHostGetDevicePointer(&d, p, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipHostFree(p);
+      return nullptr;
+    }
     g_give_up_host = static_cast<int *>(p);
+    g_give_up_dev = static_cast<int *>(d);
     for (int k = kGiveUpSlots - 1; k >= 0; --k) g_give_up_free.push_back(k);
   }
   if (g_give_up_free.empty()) return nullptr;
@@ -300,6 +308,11 @@ int *take_give_up_word() {
   g_give_up_free.pop_back();
   __atomic_store_n(g_give_up_host + k, 0, __ATOMIC_SEQ_CST);
   return g_give_up_host + k;
+}
+
+// The device address of a host slot.
+const int *give_up_device(const int *w) {
+  return w ? g_give_up_dev + (w - g_give_up_host) : nullptr;
 }
 
 void return_give_up_word(int *w) {
@@ -1538,7 +1551,7 @@ ns::PersistArgsT<LT> persist_args(const ns_solver *s, const ns::StageArgsT<LT> &
   P.done = s->pdone;
   P.ticket = s->pticket;
   P.stop = s->pstop;
-  P.give_up = s->give_up;
+  P.give_up = give_up_device(s->give_up);
   P.items_step = (uint32_t)items_step;
   P.items = (uint32_t)((int64_t)nsteps * items_step);
   int dev = s->device, khz = 0;
