@@ -154,7 +154,7 @@ __device__ __forceinline__ double block_min(double v) {
 template <int DIM>
 __device__ __forceinline__ double vel_pres(const Gas &g, const double *u, double *v,
                                            double &p) {
-  const double ir = 1.0 / u[0];
+  const double ir = fast_rcp(u[0]);
   double m2 = 0.0;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) m2 += u[1 + k] * u[1 + k];
@@ -280,7 +280,7 @@ __device__ __forceinline__ void visc_row(const DevGraphT<LT> &G,
       double c2 = 0.0;
 #pragma unroll
       for (int q = 0; q < DIM; ++q) c2 += c[kk][q] * c[kk][q];
-      const double cn = sqrt(c2);
+      const double cn = fast_sqrt(c2);
       if constexpr (IND == 0) {
         double fc[NC], vc = 0.0;
 #pragma unroll
@@ -295,7 +295,7 @@ __device__ __forceinline__ void visc_row(const DevGraphT<LT> &G,
       }
       if (j > i) {
         const int64_t e = eidx<DIM>(k, i);
-        const double icn = 1.0 / cn;
+        const double icn = fast_rcp(cn);
         double uL = 0.0, uR = 0.0;
 #pragma unroll
         for (int q = 0; q < DIM; ++q) {
@@ -312,8 +312,8 @@ __device__ __forceinline__ void visc_row(const DevGraphT<LT> &G,
           double ct2 = 0.0;
 #pragma unroll
           for (int q = 0; q < DIM; ++q) ct2 += ct[q] * ct[q];
-          const double ctn = sqrt(ct2);
-          const double ictn = 1.0 / ctn;
+          const double ctn = fast_sqrt(ct2);
+          const double ictn = fast_rcp(ctn);
           double uLt = 0.0, uRt = 0.0;
 #pragma unroll
           for (int q = 0; q < DIM; ++q) {
@@ -458,7 +458,7 @@ __device__ __forceinline__ void visc_row_f32(const DevGraphT<LT> &G,
           double c2d = 0.0;
 #pragma unroll
           for (int q = 0; q < DIM; ++q) c2d += c[kk][q] * c[kk][q];
-          const double cnd = sqrt(c2d), icnd = 1.0 / cnd;
+          const double cnd = fast_sqrt(c2d), icnd = fast_rcp(cnd);
           double uLd = 0.0, uRd = 0.0;
 #pragma unroll
           for (int q = 0; q < DIM; ++q) {
@@ -475,8 +475,8 @@ __device__ __forceinline__ void visc_row_f32(const DevGraphT<LT> &G,
           double ct2 = 0.0;
 #pragma unroll
           for (int q = 0; q < DIM; ++q) ct2 += ct[q] * ct[q];
-          const double ctn = sqrt(ct2);
-          const double ictn = 1.0 / ctn;
+          const double ctn = fast_sqrt(ct2);
+          const double ictn = fast_rcp(ctn);
           double uLt = 0.0, uRt = 0.0;
 #pragma unroll
           for (int q = 0; q < DIM; ++q) {
@@ -646,7 +646,7 @@ __device__ __forceinline__ void lo_row(const DevGraphT<LT> &G, const StageArgsT<
       flux_dot<DIM>(uj[kk], vj, pj, c[kk], fcj);
       const double dk = dij[kk];
       // density of the bar state (eq. bar_state) for the local bounds
-      const double rbar = 0.5 * (ui[0] + uj[kk][0]) - (fcj[0] - fci[0]) / (2.0 * dk);
+      const double rbar = 0.5 * (ui[0] + uj[kk][0]) - (fcj[0] - fci[0]) * fast_rcp(2.0 * dk);
       rmin = fmin(rmin, rbar);
       rmax = fmax(rmax, rbar);
       phimin = fmin(phimin, phij[kk]);
