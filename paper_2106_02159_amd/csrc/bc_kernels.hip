@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_nonreflecting(int n, const int32_t *
   double u[NC], d[NC], nv[DIM], up[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    u[c] = U[c * N + i];
+    u[c] = U[node_at(NC, c, i, N)];
     d[c] = ud[(int64_t)c * n + t];
   }
 #pragma unroll
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_nonreflecting(int n, const int32_t *
   for (int k = 0; k < DIM; ++k) m2 += up[1 + k] * up[1 + k];
   if (!ok || !(up[0] > 0.0) || !(up[NC - 1] - 0.5 * m2 / up[0] > 0.0)) flags[1] = 1;
 #pragma unroll
-  for (int c = 0; c < NC; ++c) U[c * N + i] = up[c];
+  for (int c = 0; c < NC; ++c) U[node_at(NC, c, i, N)] = up[c];
 }
 
 }  // namespace

@@ -114,11 +114,37 @@ template <typename LT> __device__ __forceinline__ LT to_lt_down(double x) {
   else return x;
 }
 
+// Node vectors in the paired layout of node_layout.hpp: one 16-byte (FP32:
+// 8-byte) access per component pair.
+template <typename T> struct Pair2;
+template <> struct Pair2<double> { using type = double2; };
+template <> struct Pair2<float> { using type = float2; };
+
 template <int NC, typename T>
 __device__ __forceinline__ void load_state(const T *__restrict__ U,
                                            int64_t N, int64_t i, double *u) {
+  using T2 = typename Pair2<T>::type;
 #pragma unroll
-  for (int q = 0; q < NC; ++q) u[q] = U[q * N + i];
+  for (int p = 0; p < NC / 2; ++p) {
+    const T2 v = *reinterpret_cast<const T2 *>(U + 2 * p * N + 2 * i);
+    u[2 * p] = v.x;
+    u[2 * p + 1] = v.y;
+  }
+  if constexpr (NC & 1) u[NC - 1] = U[(NC - 1) * N + i];
+}
+
+template <int NC, typename T>
+__device__ __forceinline__ void store_state(T *__restrict__ U, int64_t N, int64_t i,
+                                            const T *u) {
+  using T2 = typename Pair2<T>::type;
+#pragma unroll
+  for (int p = 0; p < NC / 2; ++p) {
+    T2 v;
+    v.x = u[2 * p];
+    v.y = u[2 * p + 1];
+    *reinterpret_cast<T2 *>(U + 2 * p * N + 2 * i) = v;
+  }
+  if constexpr (NC & 1) U[(NC - 1) * N + i] = u[NC - 1];
 }
 
 // f(u) c = (rho v.c, m (v.c) + p c, (v.c)(E + p)) from primitives v, p.
@@ -662,16 +688,18 @@ __device__ __forceinline__ void lo_row(const DevGraphT<LT> &G, const StageArgsT<
   }
   const double rmi = G.rmi[i];
   const double tm = tau * rmi;
+  double ul[NC];
+  LT fs[NC];
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
-    A.UL[q * N + i] = ui[q] + tm * acc[q];
-    A.FH[q * N + i] = to_lt<LT>(fh[q] * rmi);
+    ul[q] = ui[q] + tm * acc[q];
+    fs[q] = to_lt<LT>(fh[q] * rmi);
   }
+  store_state<NC>(A.UL, N, i, ul);
+  store_state<NC>(A.FH, N, i, fs);
   if (A.check_cfl && tau > G.mi[i] / (2.0 * dsum)) A.flags[4 * mem] = 1;
   if (A.check_low) {
-    double ul[NC], m2 = 0.0;
-#pragma unroll
-    for (int q = 0; q < NC; ++q) ul[q] = ui[q] + tm * acc[q];
+    double m2 = 0.0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) m2 += ul[1 + k] * ul[1 + k];
     if (!(ul[0] > 0.0) || !(ul[NC - 1] - 0.5 * m2 / ul[0] > 0.0)) A.flags[4 * mem + 3] = 1;
@@ -768,8 +796,7 @@ __device__ __forceinline__ void finish(const DevGraphT<LT> &G, const StageArgsT<
   for (int k = 0; k < DIM; ++k) m2 += w[1 + k] * w[1 + k];
   const double eps = w[NC - 1] - 0.5 * m2 / w[0];
   if (!(w[0] > 0.0) || !(eps > 0.0)) A.flags[4 * member(A, i) + 1] = 1;
-#pragma unroll
-  for (int q = 0; q < NC; ++q) A.out[q * N + i] = w[q];
+  store_state<NC>(A.out, N, i, w);
 }
 
 struct Bounds {
@@ -930,13 +957,11 @@ __device__ __forceinline__ void lim2_row(const DevGraphT<LT> &G, const StageArgs
     }
   }
   if constexpr (MODE == 3) {
-#pragma unroll
-    for (int q = 0; q < NC; ++q) A.U1[q * N + i] = u1[q];
+    store_state<NC>(A.U1, N, i, u1);
   } else if constexpr (MODE != 0) {
     finish<DIM>(G, A, i, u1);
   } else {
-#pragma unroll
-    for (int q = 0; q < NC; ++q) A.U1[q * N + i] = u1[q];
+    store_state<NC>(A.U1, N, i, u1);
     const Bounds b = load_bounds(A, N, i);
     LT *__restrict__ lt2 = A.lt2;
     uint32_t slow = 0;
@@ -1219,10 +1244,10 @@ __device__ __forceinline__ void slip_one(int t, int end, const int32_t *__restri
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
     n[k] = nrm[(int64_t)k * stride + t];
-    mn += U[(1 + k) * N + i] * n[k];
+    mn += U[node_at(DIM + 2, 1 + k, i, N)] * n[k];
   }
 #pragma unroll
-  for (int k = 0; k < DIM; ++k) U[(1 + k) * N + i] -= mn * n[k];
+  for (int k = 0; k < DIM; ++k) U[node_at(DIM + 2, 1 + k, i, N)] -= mn * n[k];
 }
 
 template <int DIM>
@@ -1246,6 +1271,30 @@ __global__ __launch_bounds__(kBlock) void k_copy8(const double *__restrict__ src
                                                   int64_t n8) {
   const int64_t t = plain_id();
   if (t < n8) dst[t] = src[t];
+}
+
+// Component-major rows (component c of row t at c*ns + t) to and from rows
+// first .. first+count-1 of a node vector of N rows (node_layout.hpp).
+template <int NC>
+__global__ __launch_bounds__(kBlock) void k_nodes_from_cm(const double *__restrict__ src,
+                                                          int64_t ns, double *__restrict__ dst,
+                                                          int64_t N, int64_t first,
+                                                          int64_t count) {
+  const int64_t t = plain_id();
+  if (t >= count) return;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) dst[node_at(NC, c, first + t, N)] = src[c * ns + t];
+}
+
+template <int NC>
+__global__ __launch_bounds__(kBlock) void k_nodes_to_cm(const double *__restrict__ src,
+                                                        int64_t N, int64_t first,
+                                                        int64_t count, double *__restrict__ dst,
+                                                        int64_t ns) {
+  const int64_t t = plain_id();
+  if (t >= count) return;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) dst[c * ns + t] = src[node_at(NC, c, first + t, N)];
 }
 
 __global__ void k_set_scalar(double *p, double v, int n) {
@@ -1839,6 +1888,28 @@ void launch_copy(const void *src, void *dst, int64_t n16, int word,
     hipLaunchKernelGGL(k_copy, grid_for(n16), dim3(kBlock), 0, s,
                        static_cast<const double2 *>(src),
                        static_cast<double2 *>(dst), n16);
+}
+
+void launch_nodes_from_cm(int nc, const double *src, int64_t ns, double *dst, int64_t N,
+                          int64_t first, int64_t count, hipStream_t s) {
+  if (count <= 0) return;
+  if (nc == 4)
+    hipLaunchKernelGGL(k_nodes_from_cm<4>, grid_for(count), dim3(kBlock), 0, s, src, ns, dst,
+                       N, first, count);
+  else
+    hipLaunchKernelGGL(k_nodes_from_cm<5>, grid_for(count), dim3(kBlock), 0, s, src, ns, dst,
+                       N, first, count);
+}
+
+void launch_nodes_to_cm(int nc, const double *src, int64_t N, int64_t first, int64_t count,
+                        double *dst, int64_t ns, hipStream_t s) {
+  if (count <= 0) return;
+  if (nc == 4)
+    hipLaunchKernelGGL(k_nodes_to_cm<4>, grid_for(count), dim3(kBlock), 0, s, src, N, first,
+                       count, dst, ns);
+  else
+    hipLaunchKernelGGL(k_nodes_to_cm<5>, grid_for(count), dim3(kBlock), 0, s, src, N, first,
+                       count, dst, ns);
 }
 
 void persist_plan(int dim, int64_t rows_tot, int64_t roots_tot, int64_t slips_tot,

@@ -1,8 +1,9 @@
 // hyp_kernels.hpp -- HIP kernels of one forward-Euler stage of the
 // hyperbolic step (Algorithm 1 of arXiv:2106.02159), gfx950.
 //
-// Layout: node arrays are structure-of-arrays (component c of node i at
-// c*N + i); edge arrays are sliced ELL (rows in slices of 64, slot-major
+// Layout: node vectors (states, U^L, F^H, U^(1)) in component pairs
+// (node_layout.hpp), the other node arrays component-major (component c of
+// node i at c*N + i); edge arrays are sliced ELL (rows in slices of 64, slot-major
 // within a slice: slot k of row i at ((i/64) W + k) 64 + i%64), so lane i of
 // a wavefront reading slot k of its row produces one coalesced access.  One
 // lane owns one row; neighbour data are gathered through the L1/L2 caches.  Sweeps, in dependency order (each needs the
@@ -31,6 +32,7 @@
 
 #include "box_nbr.hpp"
 #include "euler.hpp"
+#include "node_layout.hpp"
 
 namespace ns {
 
@@ -202,6 +204,13 @@ void launch_slip(int dim, int64_t N, int nslip, const int32_t *idx,
 void launch_nonreflecting(int dim, const Gas &gas, int method, int n, const int32_t *idx,
                           const double *nrm, const double *ud, int64_t N, double *U,
                           int *flags, hipStream_t s);
+// Rows first .. first+count-1 of the node vector dst (N rows, nc = 4 or 5
+// components, node_layout.hpp) from the component-major array src
+// (component c of row t at c*ns + t), and back; both arrays on the device.
+void launch_nodes_from_cm(int nc, const double *src, int64_t ns, double *dst, int64_t N,
+                          int64_t first, int64_t count, hipStream_t s);
+void launch_nodes_to_cm(int nc, const double *src, int64_t N, int64_t first, int64_t count,
+                        double *dst, int64_t ns, hipStream_t s);
 void launch_set_scalar(double *p, double v, hipStream_t s, int n = 1);  // p[0..n) = v
 void launch_add_scalar(double *acc, const double *v, hipStream_t s,
                        int n = 1);  // acc[k] += v[k], k < n

@@ -272,6 +272,49 @@ struct ns_solver {
 
 namespace {
 
+// Host transfers of node vectors (states): the device holds them in the
+// paired layout of node_layout.hpp, the interface component-major.  Rows
+// first .. first+count-1 of the device vector dst (N rows, nc components)
+// from the component-major host array src (component c of row t at
+// c*ns + t): interleaved on the host, then one copy per component pair.
+// Synchronises the stream (the host buffer is released on return).
+hipError_t upload_nodes(double *dst, int64_t N, int nc, int64_t first, int64_t count,
+                        const double *src, int64_t ns, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  std::vector<double> tmp((size_t)nc * count);
+  for (int c = 0; c < nc; ++c)
+    for (int64_t t = 0; t < count; ++t)
+      tmp[ns::node_at(nc, c, t, count)] = src[c * ns + t];
+  hipError_t e = hipSuccess;
+  for (int c = 0; c < nc && e == hipSuccess; c += 2) {
+    const int64_t w = c + 1 < nc ? 2 : 1;  // components in this block
+    e = hipMemcpyAsync(dst + ns::node_at(nc, c, first, N), tmp.data() + c * count,
+                       w * count * sizeof(double), hipMemcpyHostToDevice, st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e;
+}
+
+// The reverse: rows first .. first+count-1 of the device vector src into
+// the component-major host array dst (component c of row t at c*ns + t).
+hipError_t download_nodes(const double *src, int64_t N, int nc, int64_t first,
+                          int64_t count, double *dst, int64_t ns, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  std::vector<double> tmp((size_t)nc * count);
+  hipError_t e = hipSuccess;
+  for (int c = 0; c < nc && e == hipSuccess; c += 2) {
+    const int64_t w = c + 1 < nc ? 2 : 1;
+    e = hipMemcpyAsync(tmp.data() + c * count, src + ns::node_at(nc, c, first, N),
+                       w * count * sizeof(double), hipMemcpyDeviceToHost, st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  for (int c = 0; c < nc; ++c)
+    for (int64_t t = 0; t < count; ++t)
+      dst[c * ns + t] = tmp[ns::node_at(nc, c, t, count)];
+  return hipSuccess;
+}
+
 // Give-up words of the persistent steps: one int per solver in pinned host
 // memory, which the host writes and the kernel polls across the bus.  One
 // block of slots is allocated per process and kept until it ends (releasing
@@ -1040,9 +1083,7 @@ int create_impl(const Layout &Lt, const ns_params *p, void *stream, ns_solver **
         const int64_t first = Lt.base[r] + Lt.mgs[r]->N, count = mend(r) - first;
         if (count <= 0) continue;
         for (int b = 0; b < 3 && e == hipSuccess; ++b)
-          e = hipMemcpy2DAsync(s->S[b] + first, N * sizeof(double), pad.data(),
-                               ns::kBlock * sizeof(double), count * sizeof(double), nc,
-                               hipMemcpyHostToDevice, s->stream);
+          e = upload_nodes(s->S[b], N, nc, first, count, pad.data(), ns::kBlock, s->stream);
       }
       if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
       if (e != hipSuccess) return bail(NS_EHIP, "padding upload failed");
@@ -1078,11 +1119,13 @@ void ns_solver_destroy(ns_solver *s) {
 int ns_set_state(ns_solver *s, const double *U, int flags) {
   if (!s || !U) return NS_EINVAL;
   const int tgt = others(s->cur, 0);
-  const size_t bytes = (size_t)s->nc * s->N * sizeof(double);
-  hipError_t e = hipMemcpyAsync(s->S[tgt], U, bytes,
-                                (flags & NS_ON_DEVICE) ? hipMemcpyDeviceToDevice
-                                                       : hipMemcpyHostToDevice,
-                                s->stream);
+  hipError_t e = hipSuccess;
+  if (flags & NS_ON_DEVICE) {
+    ns::launch_nodes_from_cm(s->nc, U, s->N, s->S[tgt], s->N, 0, s->N, s->stream);
+    e = hipGetLastError();
+  } else {
+    e = upload_nodes(s->S[tgt], s->N, s->nc, 0, s->N, U, s->N, s->stream);
+  }
   if (e != hipSuccess) return s->hipfail(e, "state upload");
   ns::launch_clear_flags(s->flags, s->stream);
   ns::launch_check_state(s->dim, s->N, s->S[tgt], s->flags, s->stream);
@@ -1107,14 +1150,15 @@ int ns_set_state(ns_solver *s, const double *U, int flags) {
 int ns_get_state(ns_solver *s, double *U, int flags) {
   if (!s || !U) return NS_EINVAL;
   if (!s->has_state) return s->fail(NS_ESTATE, "no state set");
-  const size_t bytes = (size_t)s->nc * s->N * sizeof(double);
-  hipError_t e = hipMemcpyAsync(U, s->S[s->cur], bytes,
-                                (flags & NS_ON_DEVICE) ? hipMemcpyDeviceToDevice
-                                                       : hipMemcpyDeviceToHost,
-                                s->stream);
+  hipError_t e = hipSuccess;
+  if (flags & NS_ON_DEVICE) {
+    ns::launch_nodes_to_cm(s->nc, s->S[s->cur], s->N, 0, s->N, U, s->N, s->stream);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  } else {
+    e = download_nodes(s->S[s->cur], s->N, s->nc, 0, s->N, U, s->N, s->stream);
+  }
   if (e != hipSuccess) return s->hipfail(e, "state download");
-  e = hipStreamSynchronize(s->stream);
-  if (e != hipSuccess) return s->hipfail(e, "stream synchronize");
   return NS_OK;
 }
 
@@ -1735,9 +1779,7 @@ int ns_pack_set_state(ns_pack *k, int r, const double *U) {
       return s->fail(NS_ENOTADMISSIBLE, buf);
     }
   }
-  double *dst = s->S[s->cur] + b0;
-  hipError_t e = hipMemcpy2DAsync(dst, s->N * sizeof(double), U, Nr * sizeof(double),
-                                  Nr * sizeof(double), nc, hipMemcpyHostToDevice, s->stream);
+  hipError_t e = upload_nodes(s->S[s->cur], s->N, (int)nc, b0, Nr, U, Nr, s->stream);
   if (e != hipSuccess) return s->hipfail(e, "state upload");
   const int64_t t0 = s->mslip[r], t1 = s->mslip[r + 1];
   ns::launch_slip(s->dim, s->N, (int)(t1 - t0), s->slip_idx + t0, s->slip_n + t0,
@@ -1756,10 +1798,7 @@ int ns_pack_get_state(ns_pack *k, int r, double *U) {
   if (r < 0 || r >= s->nmem) return s->fail(NS_EINVAL, "no such pack member");
   if (!s->mset[r]) return s->fail(NS_ESTATE, "no state set");
   const int64_t Nr = s->mgs[r].N;
-  hipError_t e = hipMemcpy2DAsync(U, Nr * sizeof(double), s->S[s->cur] + s->mbase[r],
-                                  s->N * sizeof(double), Nr * sizeof(double), s->nc,
-                                  hipMemcpyDeviceToHost, s->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  hipError_t e = download_nodes(s->S[s->cur], s->N, s->nc, s->mbase[r], Nr, U, Nr, s->stream);
   if (e != hipSuccess) return s->hipfail(e, "state download");
   return NS_OK;
 }
@@ -1863,17 +1902,17 @@ int ns_get_debug(ns_solver *s, int what, double *out) {
   const double *src = nullptr;
   const float *srcf = nullptr;  // FP32 storage in the mixed-precision mode
   int64_t count = 0;
-  bool edge = false;
+  bool edge = false, node = false;  // node: a node vector (node_layout.hpp)
   switch (what) {
-    case NS_DBG_STAGE_OUT: src = s->S[s->last_out]; count = nc * N; break;
+    case NS_DBG_STAGE_OUT: src = s->S[s->last_out]; count = nc * N; node = true; break;
     case NS_DBG_D: src = s->d; srcf = s->df; count = W * Np; edge = true; break;
     case NS_DBG_ALPHA: src = s->alpha; srcf = s->alphaf; count = N; break;
-    case NS_DBG_UL: src = s->UL; count = nc * N; break;
-    case NS_DBG_FH: src = s->FH; srcf = s->FHf; count = nc * N; break;
+    case NS_DBG_UL: src = s->UL; count = nc * N; node = true; break;
+    case NS_DBG_FH: src = s->FH; srcf = s->FHf; count = nc * N; node = true; break;
     case NS_DBG_BOUNDS: src = s->bnds; count = 3 * N; break;
     case NS_DBG_LT1: src = s->lt1; srcf = s->lt1f; count = W * Np; edge = true; break;
     case NS_DBG_LT2: src = s->lt2; srcf = s->lt2f; count = W * Np; edge = true; break;
-    case NS_DBG_U1: src = s->U1; count = nc * N; break;
+    case NS_DBG_U1: src = s->U1; count = nc * N; node = true; break;
     case NS_DBG_ROOTS: {
       uint32_t c[2];
       hipError_t e = hipMemcpyAsync(c, s->qcnt, sizeof(c), hipMemcpyDeviceToHost, s->stream);
@@ -1886,22 +1925,26 @@ int ns_get_debug(ns_solver *s, int what, double *out) {
     default: return s->fail(NS_EINVAL, "unknown debug array");
   }
   const bool f32 = s->mixed && srcf != nullptr;
-  std::vector<double> tmp(edge || f32 ? count : 0);
+  const bool raw = edge || node || f32;  // downloaded to tmp, then rearranged
+  std::vector<double> tmp(raw ? count : 0);
   std::vector<float> tmpf(f32 ? count : 0);
   hipError_t e = f32 ? hipMemcpyAsync(tmpf.data(), srcf, count * sizeof(float),
                                       hipMemcpyDeviceToHost, s->stream)
-                     : hipMemcpyAsync(edge ? tmp.data() : out, src, count * sizeof(double),
+                     : hipMemcpyAsync(raw ? tmp.data() : out, src, count * sizeof(double),
                                       hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return s->hipfail(e, "debug download");
-  if (f32) {
+  if (f32)
     for (int64_t t = 0; t < count; ++t) tmp[t] = tmpf[t];
-    if (!edge) std::copy(tmp.begin(), tmp.end(), out);
-  }
   if (edge) {
     for (int k = 0; k < W; ++k)
       for (int64_t i = 0; i < N; ++i)
         out[k * N + i] = tmp[((i >> 6) * W + k) * 64 + (i & 63)];
+  } else if (node) {
+    for (int c = 0; c < nc; ++c)
+      for (int64_t i = 0; i < N; ++i) out[c * N + i] = tmp[ns::node_at((int)nc, c, i, N)];
+  } else if (raw) {
+    std::copy(tmp.begin(), tmp.end(), out);
   }
   return NS_OK;
 }

@@ -3,6 +3,7 @@
 
 #include <cmath>
 
+#include "node_layout.hpp"
 #include "par_ops.hpp"
 
 namespace ns {
@@ -46,7 +47,8 @@ __global__ __launch_bounds__(kParBlock) void k_prep(ParGrid G, ParBufs B,
   if (i >= N) return;
   int64_t c[3];
   decode(G, i, c);
-  const double rho = U[i];
+  constexpr int NC = DIM + 2;  // U: a node vector (node_layout.hpp)
+  const double rho = U[node_at(NC, 0, i, N)];
   const double m = B.mi[i];
   const double rm = rho * m;
   const bool fx = B.fixed[i] != 0;
@@ -54,7 +56,7 @@ __global__ __launch_bounds__(kParBlock) void k_prep(ParGrid G, ParBufs B,
   double v2 = 0.0;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
-    const double M = U[(1 + k) * N + i];
+    const double M = U[node_at(NC, 1 + k, i, N)];
     const double V = M / rho;
     v2 += V * V;
     B.Vn[k * N + i] = V;
@@ -62,7 +64,7 @@ __global__ __launch_bounds__(kParBlock) void k_prep(ParGrid G, ParBufs B,
     B.x[k * N + i] = fx ? 0.0 : V;
     B.diag[k * N + i] = fx ? 1.0 : rm + 0.5 * dt * op_diag<DIM, DIM>(G, B.tab, c, k);
   }
-  B.en[i] = U[(DIM + 1) * N + i] / rho - 0.5 * v2;
+  B.en[i] = U[node_at(NC, DIM + 1, i, N)] / rho - 0.5 * v2;
 }
 
 // residual and first direction from the start value x; partial r.z, r.r, b.b
@@ -392,12 +394,12 @@ __global__ __launch_bounds__(kParBlock) void k_vel_done(ParGrid G, ParBufs B,
   int64_t c[3];
   decode(G, i, c);
   const bool fx = B.fixed[i] != 0;
-  const double rho = U[i];
+  const double rho = U[node_at(DIM + 2, 0, i, N)];
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
     const double vn = fx ? 0.0 : 2.0 * B.x[k * N + i] - B.Vn[k * N + i];
     B.Vn[k * N + i] = vn;
-    out[(1 + k) * N + i] = rho * vn;
+    out[node_at(DIM + 2, 1 + k, i, N)] = rho * vn;
   }
   double K = 0.0;
 #pragma unroll
@@ -549,7 +551,7 @@ __global__ __launch_bounds__(kParBlock) void k_par_finish(ParGrid G, ParBufs B,
   const int64_t i = gid();
   const int64_t N = G.N;
   if (i >= N) return;
-  const double rho = U[i];
+  const double rho = U[node_at(DIM + 2, 0, i, N)];
   double v2 = 0.0;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
@@ -557,8 +559,8 @@ __global__ __launch_bounds__(kParBlock) void k_par_finish(ParGrid G, ParBufs B,
     v2 += v * v;
   }
   const double ei = e[i];
-  out[i] = rho;
-  out[(DIM + 1) * N + i] = rho * ei + 0.5 * rho * v2;
+  out[node_at(DIM + 2, 0, i, N)] = rho;
+  out[node_at(DIM + 2, DIM + 1, i, N)] = rho * ei + 0.5 * rho * v2;
   if (!(ei > 0.0) || !isfinite(ei)) B.flags[1] = 1;
 }
 
