@@ -555,6 +555,7 @@ __device__ __forceinline__ void dt_partial_blk(const DevGraphT<LT> &G,
     BoxNbr<DIM> jv = block_nbr<DIM>(G, blk, i);
 #pragma unroll
     for (int k = 0; k < C::W; ++k) {
+      if (k == C::W / 2) continue;  // the diagonal
       const int64_t e = eidx<DIM>(k, i);
       const int32_t j = jv[k];
       const double v = d[e];  // absent entries hold 0
@@ -861,6 +862,7 @@ __device__ __forceinline__ void lim1_row(const DevGraphT<LT> &G, const StageArgs
     for (int kk = 0; kk < C::CH; ++kk) {
       const int k = ch * C::CH + kk;
       jc[kk] = jv[k];
+      if (k == C::W / 2) continue;  // the diagonal has no P
       gather_P<DIM>(G, A, eidx<DIM>(k, i), jc[kk] >= 0 ? jc[kk] : i, jv.mass(k), x[kk]);
     }
 #pragma unroll
@@ -927,6 +929,7 @@ __device__ __forceinline__ void lim2_row(const DevGraphT<LT> &G, const StageArgs
       const int k = ch * C::CH + kk;
       const int64_t e = eidx<DIM>(k, i);
       jc[kk] = colk[k];
+      if (k == C::W / 2) continue;  // the diagonal has no P
       const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
       gather_P<DIM>(G, A, e, js, colk.mass(k), x[kk]);
       if constexpr (MODE != 2) {
@@ -999,6 +1002,7 @@ __device__ __forceinline__ void lim2_row(const DevGraphT<LT> &G, const StageArgs
           const int k = ch * C::CH + kk;
           const int64_t e = eidx<DIM>(k, i);
           jc[kk] = colk[k];
+          if (k == C::W / 2) continue;  // the diagonal has no P
           const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
           gather_P<DIM>(G, A, e, js, colk.mass(k), x[kk]);
           la[kk] = lt1[e];
@@ -1006,6 +1010,7 @@ __device__ __forceinline__ void lim2_row(const DevGraphT<LT> &G, const StageArgs
         }
 #pragma unroll
         for (int kk = 0; kk < C::CH; ++kk) {
+          if (ch * C::CH + kk == C::W / 2) continue;
           make_P<DIM>(R, x[kk], P[kk]);
           l[kk] = fmin(la[kk], lb[kk]);
         }
@@ -1080,6 +1085,7 @@ __device__ __forceinline__ void lim2b_row(const DevGraphT<LT> &G, const StageArg
       const int k = ch * C::CH + kk;
       const int64_t e = eidx<DIM>(k, i);
       jc[kk] = jv[k];
+      if (k == C::W / 2) continue;  // the diagonal
       const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
       la[kk] = lt1[e];
       lb[kk] = lt1[eidx<DIM>(tslot<DIM>(k), js)];
@@ -1192,6 +1198,7 @@ __device__ __forceinline__ void fin_row(const DevGraphT<LT> &G, const StageArgsT
       const int k = ch * C::CH + kk;
       const int64_t e = eidx<DIM>(k, i);
       jc[kk] = jv[k];
+      if (k == C::W / 2) continue;  // the diagonal
       const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
       l2a[kk] = lt2[e];
       l2b[kk] = lt2[eidx<DIM>(tslot<DIM>(k), js)];
