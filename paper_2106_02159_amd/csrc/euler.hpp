@@ -159,6 +159,9 @@ template <int DIM, int SEV>
 __device__ __forceinline__ bool entropy_ok(const Gas &g, const double *u,
                                            const double *P, double l,
                                            double phi_min, double pmin5) {
+  // no fused multiply-adds of the compiler's choosing: a pair's two rows
+  // evaluate the same test in different kernels and must agree bit for bit
+#pragma clang fp contract(off)
   const double r = u[0] + l * P[0];
   double m2 = 0.0;
 #pragma unroll

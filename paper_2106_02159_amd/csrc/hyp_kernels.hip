@@ -623,6 +623,7 @@ __device__ __forceinline__ void lo_row(const DevGraphT<LT> &G, const StageArgsT<
   if (first) {
     A.qcnt[0] = 0;
     A.qcnt[1] = 0;
+    if (A.drow) A.qcnt[2] = 0;
   }
   if (i >= N) return;
   const double *__restrict__ U = A.U;
@@ -761,6 +762,7 @@ __device__ __forceinline__ void gather_P(const DevGraphT<LT> &G, const StageArgs
 template <int DIM>
 __device__ __forceinline__ void make_P(const RowCtx<DIM> &R, const PIn<DIM> &x,
                                        double *P) {
+#pragma clang fp contract(off)  // the same bits in every kernel (k_lim2 MODE 4)
   constexpr int NC = DIM + 2;
   const double dH = 0.5 * (R.ali + x.al) * x.d;
 #pragma unroll
@@ -827,6 +829,7 @@ template <int DIM, int SEV>
 __device__ __forceinline__ int limit_fast(const Gas &g, const double *u,
                                           const double *P, const Bounds &b,
                                           double *l) {
+#pragma clang fp contract(off)  // the same bits in every kernel (k_lim2 MODE 4)
   double lr;
   if (P[0] > 0.0) lr = (b.rmax - u[0]) / P[0];
   else if (P[0] < 0.0) lr = (b.rmin - u[0]) / P[0];
@@ -841,6 +844,7 @@ __device__ __forceinline__ int limit_fast(const Gas &g, const double *u,
 template <int DIM, int SEV, typename LT>
 __device__ __forceinline__ void lim1_row(const DevGraphT<LT> &G, const StageArgsT<LT> &A,
                                          const Gas &g, uint32_t blk, int64_t i) {
+#pragma clang fp contract(off)  // the same bits as k_lim2 MODE 4
   using C = Cfg<DIM, NS_CH_LIM1>;
   constexpr int NC = C::NC;
   const int64_t N = G.N;
@@ -893,10 +897,25 @@ __global__ __launch_bounds__(kBlock) void k_lim1(DevGraphT<LT> G, StageArgsT<LT>
 // MODE 0: convex, pass-1 update + pass-2 line search; 1: convex with one
 // pass, final; 2: l = 1 (unlimited high order), final; 3: convex, pass-1
 // update only (3D: the pass-2 search is k_lim2b, since both in one kernel
-// need more registers than a SIMD lane has).
+// need more registers than a SIMD lane has); 4: MODE 0 with the pass-1 line
+// searches in the same sweep (2D, replaces k_lim1).
+//
+// MODE 4: for every entry the row runs both line searches of the pair --
+// its own on P_ij from its U^L and bounds, and the neighbour's on P_ji from
+// the neighbour's, with P_ji formed from the same operands in the same
+// order as the neighbour's row forms it -- so the two rows obtain the same
+// l_ij = min(l~_ij, l~_ji) without a sweep storing l~ in between.  The own
+// search is still stored in lt1 (a deferred neighbour reads it).  Where
+// either search of a pair needs the root of the entropy bound, both rows of
+// the pair are deferred: the own entries go to the pass-1 work list as in
+// k_lim1, the row to the deferred list, and k_lim2_rows completes it with
+// MODE 0 once k_root has solved the list.
 template <int DIM, int MODE, int SEV, typename LT>
 __device__ __forceinline__ void lim2_row(const DevGraphT<LT> &G, const StageArgsT<LT> &A,
                                          const Gas &g, uint32_t blk, int64_t i) {
+  // no fused multiply-adds of the compiler's choosing: MODE 0 and MODE 4
+  // must give the same bits (the persistent steps run MODE 0 throughout)
+#pragma clang fp contract(off)
   using C = Cfg<DIM, NS_CH_LIM2>;
   constexpr int NC = C::NC;
   const int64_t N = G.N;
@@ -904,14 +923,25 @@ __device__ __forceinline__ void lim2_row(const DevGraphT<LT> &G, const StageArgs
   const LT *__restrict__ lt1 = A.lt1;
   BoxNbr<DIM> colk = block_nbr<DIM>(G, blk, i);
   RowCtx<DIM> R;
-  load_row<DIM>(G, A, i, A.tau[member(A, i)], R);
+  const double tau = A.tau[member(A, i)];
+  load_row<DIM>(G, A, i, tau, R);
   const double lam = 1.0 / G.lfac[i];
   double u1[NC];
   load_state<NC>(A.UL, N, i, u1);
+  constexpr bool BOTH = MODE == 4;  // both pass-1 searches of every pair here
+  double ul[BOTH ? NC : 1];
+  Bounds bi{};
+  uint32_t slow1 = 0;
+  bool defer = false;
+  if constexpr (BOTH) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q) ul[q] = u1[q];
+    bi = load_bounds(A, N, i);
+  }
   // 2D: the row's P_ij and l_ij stay for the pass-2 search: the P of the
   // first NS_LIM2_LDS off-diagonal slots in the lane's own LDS words (no
   // sharing between lanes, so no barrier), the rest in registers
-  constexpr bool CACHE = DIM == 2 && MODE == 0;
+  constexpr bool CACHE = DIM == 2 && (MODE == 0 || MODE == 4);
   constexpr int NLDS = CACHE ? NS_LIM2_LDS : 0;
   __shared__ double Ps[NLDS > 0 ? NLDS : 1][NC][kBlock];
   const int lane = threadIdx.x;
@@ -923,6 +953,8 @@ __device__ __forceinline__ void lim2_row(const DevGraphT<LT> &G, const StageArgs
     if constexpr (!CACHE) colk.fence();
     PIn<DIM> x[C::CH];
     double la[C::CH], lb[C::CH];
+    double ulj[BOTH ? C::CH : 1][NC], cj[C::CH];
+    Bounds bj[BOTH ? C::CH : 1];
     int32_t jc[C::CH];
 #pragma unroll
     for (int kk = 0; kk < C::CH; ++kk) {
@@ -932,7 +964,11 @@ __device__ __forceinline__ void lim2_row(const DevGraphT<LT> &G, const StageArgs
       if (k == C::W / 2) continue;  // the diagonal has no P
       const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
       gather_P<DIM>(G, A, e, js, colk.mass(k), x[kk]);
-      if constexpr (MODE != 2) {
+      if constexpr (BOTH) {
+        load_state<NC>(A.UL, N, js, ulj[kk]);
+        bj[kk] = load_bounds(A, N, js);
+        cj[kk] = tau * G.lfac[js] * G.rmi[js];  // as load_row forms it
+      } else if constexpr (MODE != 2) {
         la[kk] = lt1[e];
         lb[kk] = lt1[eidx<DIM>(tslot<DIM>(k), js)];
       }
@@ -941,9 +977,39 @@ __device__ __forceinline__ void lim2_row(const DevGraphT<LT> &G, const StageArgs
     for (int kk = 0; kk < C::CH; ++kk) {
       const int k = ch * C::CH + kk;
       if (jc[kk] < 0 || jc[kk] == i) continue;
-      const double l = MODE != 2 ? fmin(la[kk], lb[kk]) : 1.0;
       double P[NC];
       make_P<DIM>(R, x[kk], P);
+      double l;
+      if constexpr (BOTH) {
+        double l1, l2;
+        if (limit_fast<DIM, SEV>(g, ul, P, bi, &l1)) {
+          slow1 |= 1u << k;
+          defer = true;
+        }
+        st_once(&A.lt1[eidx<DIM>(k, i)], to_lt_down<LT>(l1));
+        // the neighbour's search on P_ji, formed as its row forms it
+        RowCtx<DIM> Rj;
+        PIn<DIM> xi;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+          Rj.ui[q] = x[kk].u[q];
+          Rj.fi[q] = x[kk].f[q];
+          xi.u[q] = R.ui[q];
+          xi.f[q] = R.fi[q];
+        }
+        Rj.ali = x[kk].al;
+        Rj.coef = cj[kk];
+        xi.al = R.ali;
+        xi.d = x[kk].d;
+        xi.m = x[kk].m;
+        double Pj[NC];
+        make_P<DIM>(Rj, xi, Pj);
+        if (limit_fast<DIM, SEV>(g, ulj[kk], Pj, bj[kk], &l2)) defer = true;
+        // as stored and reloaded by the two-sweep form
+        l = fmin((double)to_lt_down<LT>(l1), (double)to_lt_down<LT>(l2));
+      } else {
+        l = MODE != 2 ? fmin(la[kk], lb[kk]) : 1.0;
+      }
 #pragma unroll
       for (int q = 0; q < NC; ++q) u1[q] += lam * l * P[q];
       if constexpr (CACHE) {
@@ -959,13 +1025,27 @@ __device__ __forceinline__ void lim2_row(const DevGraphT<LT> &G, const StageArgs
       }
     }
   }
+  if constexpr (BOTH) {
+    if (slow1) {
+      uint32_t t = atomicAdd(&A.qcnt[0], (uint32_t)__builtin_popcount(slow1));
+      while (slow1) {
+        const int k = __builtin_ctz(slow1);
+        slow1 &= slow1 - 1;
+        A.q[t++] = (uint32_t)eidx<DIM>(k, i);
+      }
+    }
+    if (defer) {
+      A.drow[atomicAdd(&A.qcnt[2], 1u)] = (uint32_t)i;
+      return;
+    }
+  }
   if constexpr (MODE == 3) {
     store_state<NC>(A.U1, N, i, u1);
-  } else if constexpr (MODE != 0) {
+  } else if constexpr (MODE == 1 || MODE == 2) {
     finish<DIM>(G, A, i, u1);
   } else {
     store_state<NC>(A.U1, N, i, u1);
-    const Bounds b = load_bounds(A, N, i);
+    const Bounds b = BOTH ? bi : load_bounds(A, N, i);
     LT *__restrict__ lt2 = A.lt2;
     uint32_t slow = 0;
     if constexpr (!CACHE) {
@@ -1033,11 +1113,12 @@ __device__ __forceinline__ void lim2_row(const DevGraphT<LT> &G, const StageArgs
       }
     }
     if (slow) {
+      uint32_t *__restrict__ q2 = A.q2 ? A.q2 : A.q;
       uint32_t t = atomicAdd(&A.qcnt[1], (uint32_t)__builtin_popcount(slow));
       while (slow) {
         const int k = __builtin_ctz(slow);
         slow &= slow - 1;
-        A.q[t++] = (uint32_t)eidx<DIM>(k, i);
+        q2[t++] = (uint32_t)eidx<DIM>(k, i);
       }
     }
   }
@@ -1046,6 +1127,18 @@ __device__ __forceinline__ void lim2_row(const DevGraphT<LT> &G, const StageArgs
 template <int DIM, int MODE, int SEV, typename LT>
 __global__ __launch_bounds__(kBlock) void k_lim2(DevGraphT<LT> G, StageArgsT<LT> A, Gas g) {
   lim2_row<DIM, MODE, SEV, LT>(G, A, g, blockIdx.x, row_id());
+}
+
+// The rows that MODE 4 deferred (A.drow, qcnt[2] of them), completed with
+// MODE 0 after k_root<1>; grid-stride over the list.
+template <int DIM, int SEV, typename LT>
+__global__ __launch_bounds__(kBlock) void k_lim2_rows(DevGraphT<LT> G, StageArgsT<LT> A,
+                                                      Gas g) {
+  const uint32_t n = A.qcnt[2];
+  for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < n; t += gridDim.x * kBlock) {
+    const int64_t i = A.drow[t];
+    lim2_row<DIM, 0, SEV, LT>(G, A, g, (uint32_t)(i / kBlock), i);
+  }
 }
 
 // 3D: at most 4 waves per SIMD.  The 3D pass-1 update needs 82 VGPRs and
@@ -1111,11 +1204,12 @@ __device__ __forceinline__ void lim2b_row(const DevGraphT<LT> &G, const StageArg
     }
   }
   if (slow) {
+    uint32_t *__restrict__ q2 = A.q2 ? A.q2 : A.q;
     uint32_t t = atomicAdd(&A.qcnt[1], (uint32_t)__builtin_popcount(slow));
     while (slow) {
       const int k = __builtin_ctz(slow);
       slow &= slow - 1;
-      A.q[t++] = (uint32_t)eidx<DIM>(k, i);
+      q2[t++] = (uint32_t)eidx<DIM>(k, i);
     }
   }
 }
@@ -1143,7 +1237,7 @@ __device__ __forceinline__ void root_range(const DevGraphT<LT> &G, const StageAr
   constexpr int NC = DIM + 2;
   const int64_t N = G.N;
   const uint32_t n = A.qcnt[PASS - 1];
-  const uint32_t *__restrict__ q = A.q;
+  const uint32_t *__restrict__ q = PASS == 2 && A.q2 ? A.q2 : A.q;
   LT *__restrict__ lt = PASS == 1 ? A.lt1 : A.lt2;
   for (uint32_t t = start; t < n; t += stride) {
     const int64_t e = q[t];
@@ -1661,6 +1755,8 @@ __global__ __launch_bounds__(kBlock) void k_persist(DevGraphT<LT> G, PersistArgs
     }
     // the member's own work lists: its slice of q and its two counters
     A.q = P.A.q + (int64_t)W * kBlock * mb0;
+    A.q2 = A.q;  // root1 empties the list before lim2 fills it again
+    A.drow = nullptr;
     A.qcnt = P.pcnt + 2 * m;
     const uint32_t blk = kind == PK_ROW ? (uint32_t)mb0 + r : 0u;
     const int64_t i = (int64_t)blk * kBlock + tid;
@@ -1765,6 +1861,24 @@ void stage_impl(const Gas &gas, const DevGraphT<LT> &G, const StageArgsT<LT> &A,
     // 3D shock tube); up to 4M lanes cover a list without striding, and
     // blocks past its end exit at once
     const dim3 rgrid(std::min<unsigned>(grid.x, 16384u));
+    bool merged = false;
+    if constexpr (DIM == 2) {
+      if (passes != 1 && A.drow && A.q2) {
+        // both pass-1 searches, the update and the pass-2 search in one
+        // sweep; the deferred rows after the pass-1 roots
+        merged = true;
+        NS_LAUNCH("lim12", hipLaunchKernelGGL((k_lim2<DIM, 4, SEV, LT>), grid, block, 0, s,
+                                              G, A, gas));
+        NS_LAUNCH("root1", hipLaunchKernelGGL((k_root<DIM, 1, SEV, LT>), rgrid, block, 0, s,
+                                              G, A, gas));
+        NS_LAUNCH("lim2d", hipLaunchKernelGGL((k_lim2_rows<DIM, SEV, LT>), rgrid, block, 0, s,
+                                              G, A, gas));
+        NS_LAUNCH("root2", hipLaunchKernelGGL((k_root<DIM, 2, SEV, LT>), rgrid, block, 0, s,
+                                              G, A, gas));
+        NS_LAUNCH("fin", hipLaunchKernelGGL((k_fin<DIM, LT>), grid, block, 0, s, G, A, gas));
+      }
+    }
+    if (!merged) {
     NS_LAUNCH("lim1", hipLaunchKernelGGL((k_lim1<DIM, SEV, LT>), grid, block, 0, s, G, A, gas));
     NS_LAUNCH("root1", hipLaunchKernelGGL((k_root<DIM, 1, SEV, LT>), rgrid, block, 0, s, G,
                                           A, gas));
@@ -1784,6 +1898,7 @@ void stage_impl(const Gas &gas, const DevGraphT<LT> &G, const StageArgsT<LT> &A,
       NS_LAUNCH("root2", hipLaunchKernelGGL((k_root<DIM, 2, SEV, LT>), rgrid, block, 0, s, G,
                                             A, gas));
       NS_LAUNCH("fin", hipLaunchKernelGGL((k_fin<DIM, LT>), grid, block, 0, s, G, A, gas));
+    }
     }
   }
 #undef NS_LAUNCH

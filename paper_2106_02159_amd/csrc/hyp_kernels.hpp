@@ -88,6 +88,12 @@ struct StageArgsT {
   // qcnt[p] counts the entries of pass p+1 (reset by k_lo).
   uint32_t *q;
   uint32_t *qcnt;
+  // 2D two-pass limiting in one sweep (k_lim2 MODE 4): the pass-2 work list
+  // q2 (W*Np entries; null: q, filled after q is emptied) and the deferred
+  // rows drow (Np entries, qcnt[2] of them; null: not used, qcnt has two
+  // counters)
+  uint32_t *q2 = nullptr;
+  uint32_t *drow = nullptr;
   // A pack of several meshes stepped together: member of every 256-row
   // workgroup (each member's rows start at a workgroup boundary; padding
   // rows are isolated nodes), member count and workgroup offsets of the

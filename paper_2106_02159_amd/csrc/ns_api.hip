@@ -223,6 +223,7 @@ struct ns_solver {
     b.U = a.U; b.Un = a.Un; b.out = a.out; b.aux = a.aux; b.UL = a.UL; b.bnds = a.bnds;
     b.U1 = a.U1; b.partial = a.partial; b.tau = a.tau; b.flags = a.flags;
     b.sa = a.sa; b.sb = a.sb; b.check_cfl = a.check_cfl; b.q = a.q; b.qcnt = a.qcnt;
+    b.q2 = a.q2; b.drow = a.drow;
     b.seg = a.seg; b.mblk = a.mblk; b.nmem = a.nmem; b.check_low = a.check_low;
     b.alpha = alphaf; b.d = df; b.FH = FHf; b.lt1 = lt1f; b.lt2 = lt2f;
     b.fp32_eval = fp32_eval && !redo_fp64;
@@ -236,6 +237,8 @@ struct ns_solver {
     a.flags = flags; a.sa = sa; a.sb = sb; a.check_cfl = adaptive ? 0 : check;
     a.check_low = adaptive || fp32_eval ? 1 : 0;
     a.q = q; a.qcnt = qcnt;
+    a.q2 = q + (int64_t)W * Np;  // the pass-2 list and the deferred rows
+    a.drow = q + 2 * (int64_t)W * Np;
     a.seg = seg; a.mblk = mblk; a.nmem = nmem;
     return a;
   }
@@ -803,7 +806,7 @@ int64_t footprint(const Layout &Lt, const ns_params *p) {
   b += N * L + W * Np * L + nc * N * 8 + nc * N * L;  // alpha, d, U^L, F^H
   b += 3 * N * 8 + 2 * W * Np * L + nc * N * 8;      // bounds, l~ (2), U^(1)
   b += nblocks * 8 + nm * (8 + 4 * 4 + 8);           // partial, tau, flags, time
-  b += W * Np * 4 + 2 * 4;                           // root work list
+  b += (2 * W * Np + Np) * 4 + 4 * 4;                // root work lists, deferred rows
   b += nslip * 4 + dim * nslip * 8;                  // slip list
   if (Lt.pack) b += nblocks * 4 + (nm + 1) * 4;      // member of each workgroup
   b += 4 * (nm + 1) * 4 + 3 * nm * 4 + 4 + 4 * 4;    // persistent-step tables
@@ -946,8 +949,8 @@ int create_impl(const Layout &Lt, const ns_params *p, void *stream, ns_solver **
     NS_ALLOC(s->mblk, s->nmem + 1);
   }
   // limiter root work list, large enough for every edge
-  NS_ALLOC(s->q, W * Np);
-  NS_ALLOC(s->qcnt, 2);
+  NS_ALLOC(s->q, 2 * W * Np + Np);  // pass-1 and pass-2 lists, deferred rows
+  NS_ALLOC(s->qcnt, 4);
   NS_ALLOC(s->pmblk, s->nmem + 1);
   NS_ALLOC(s->prblk, s->nmem + 1);
   NS_ALLOC(s->psblk, s->nmem + 1);
