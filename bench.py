@@ -75,6 +75,11 @@ def kernel_bytes(name: str, dim: int, mixed: bool = False) -> float:
                  if dim == 2 else  # 3D: pass-1 update only
                  2 * eL + rows + nL + 2 * n8 + nc * n8),
         "lim2b": 2 * eL + rows + nL + 2 * n8 + 3 * n8 + eL,
+        # 2D: both pass-1 searches, the update and the pass-2 search in one
+        # sweep (d, the row's U, U^L, F^H, alpha, m_i, lambda_i, bounds in;
+        # l~, U^(1), l~' out); the deferred rows are a small fraction
+        "lim12": 3 * eL + rows + nL + 2 * n8 + 3 * n8 + nc * n8,
+        "lim2d": 0.0,
         "fin": 2 * eL + nc * (3 * n8 + nL) + nL + 2 * n8 + nc * n8,
         "combine": 2 * nc * n8 + nc * n8,
         "slip": 0.0,

@@ -707,9 +707,8 @@ __device__ __forceinline__ void lo_row(const DevGraphT<LT> &G, const StageArgsT<
     if (!(ul[0] > 0.0) || !(ul[NC - 1] - 0.5 * m2 / ul[0] > 0.0)) A.flags[4 * mem + 3] = 1;
   }
   const double r = G.rrel[i];
-  A.bnds[i] = (1.0 - r) * rmin;
-  A.bnds[N + i] = (1.0 + r) * rmax;
-  A.bnds[2 * N + i] = (1.0 - r) * phimin;
+  const double bv[3] = {(1.0 - r) * rmin, (1.0 + r) * rmax, (1.0 - r) * phimin};
+  store_state<3>(A.bnds, N, i, bv);
 }
 
 template <int DIM, typename LT>
@@ -736,7 +735,7 @@ __device__ __forceinline__ void load_row(const DevGraphT<LT> &G, const StageArgs
   load_state<NC>(A.U, N, i, R.ui);
   load_state<NC>(A.FH, N, i, R.fi);
   R.ali = A.alpha[i];
-  R.coef = tau * G.lfac[i] * G.rmi[i];
+  R.coef = tau * G.crm[i];
 }
 
 // Neighbour data entering P_ij, gathered unconditionally (absent entries
@@ -810,9 +809,11 @@ template <typename LT>
 __device__ __forceinline__ Bounds load_bounds(const StageArgsT<LT> &A, int64_t N,
                                               int64_t i) {
   Bounds b;
-  b.rmin = A.bnds[i];
-  b.rmax = A.bnds[N + i];
-  b.pmin = A.bnds[2 * N + i];
+  double bv[3];
+  load_state<3>(A.bnds, N, i, bv);  // (rho_min, rho_max) in one load
+  b.rmin = bv[0];
+  b.rmax = bv[1];
+  b.pmin = bv[2];
   const double p2 = b.pmin * b.pmin;
   b.pmin5 = p2 * p2 * b.pmin;
   return b;
@@ -967,7 +968,7 @@ __device__ __forceinline__ void lim2_row(const DevGraphT<LT> &G, const StageArgs
       if constexpr (BOTH) {
         load_state<NC>(A.UL, N, js, ulj[kk]);
         bj[kk] = load_bounds(A, N, js);
-        cj[kk] = tau * G.lfac[js] * G.rmi[js];  // as load_row forms it
+        cj[kk] = tau * G.crm[js];  // as load_row forms it
       } else if constexpr (MODE != 2) {
         la[kk] = lt1[e];
         lb[kk] = lt1[eidx<DIM>(tslot<DIM>(k), js)];

@@ -53,6 +53,7 @@ struct DevGraphT {
   const double *mi;     // N
   const double *rmi;    // N: 1 / m_i
   const double *lfac;   // N: |I(i)| - 1 = 1 / lambda_i
+  const double *crm;    // N: (|I(i)| - 1) / m_i = 1 / (lambda_i m_i)
   const double *rrel;   // N: bound relaxation r_i
   const uint8_t *wall;  // N
 };
@@ -67,7 +68,8 @@ struct StageArgsT {
   LT *d;             // W*Np (FP32: rounded up, still an upper bound)
   double *UL;        // nc*N
   LT *FH;            // nc*N
-  double *bnds;      // 3*N
+  double *bnds;      // 3*N: rho_min, rho_max, Phi_min (a node vector,
+                     // node_layout.hpp)
   LT *lt1;           // W*Np (FP32: rounded down, still feasible)
   LT *lt2;           // W*Np: l~'_ij (1 - l_ij) (FP32: rounded down)
   double *U1;        // nc*N

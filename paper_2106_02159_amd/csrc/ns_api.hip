@@ -139,7 +139,7 @@ struct ns_solver {
   int fp64_redo = 0;
   float *alphaf = nullptr, *df = nullptr, *FHf = nullptr, *lt1f = nullptr,
         *lt2f = nullptr;
-  double *mi = nullptr, *rmi = nullptr, *lfac = nullptr, *rrel = nullptr;
+  double *mi = nullptr, *rmi = nullptr, *lfac = nullptr, *crm = nullptr, *rrel = nullptr;
   uint8_t *wall = nullptr;
   int nslip = 0;
   int32_t *slip_idx = nullptr;
@@ -208,13 +208,13 @@ struct ns_solver {
   ns::DevGraph devgraph() const {
     ns::DevGraph g;
     g.N = N; g.W = W; g.geo = geo; g.seg = seg;
-    g.mi = mi; g.rmi = rmi; g.lfac = lfac; g.rrel = rrel; g.wall = wall;
+    g.mi = mi; g.rmi = rmi; g.lfac = lfac; g.crm = crm; g.rrel = rrel; g.wall = wall;
     return g;
   }
   ns::DevGraphT<float> devgraph32() const {
     ns::DevGraphT<float> g;
     g.N = N; g.W = W; g.geo = geo; g.seg = seg;
-    g.mi = mi; g.rmi = rmi; g.lfac = lfac; g.rrel = rrel; g.wall = wall;
+    g.mi = mi; g.rmi = rmi; g.lfac = lfac; g.crm = crm; g.rrel = rrel; g.wall = wall;
     return g;
   }
   ns::StageArgsT<float> args32(int in, int out, double sa, double sb, int check) const {
@@ -801,7 +801,7 @@ int64_t footprint(const Layout &Lt, const ns_params *p) {
   for (const ns::MeshGraph *g : Lt.mgs) nslip += slip_count(*g);
   int64_t b = 0;
   b += nm * (int64_t)sizeof(ns::BoxGeom);             // box geometry
-  b += 4 * N * 8 + N;                                // m_i, 1/m_i, lfac, r_i, wall
+  b += 5 * N * 8 + N;                                // m_i, 1/m_i, lfac, lfac/m_i, r_i, wall
   b += 3 * nc * N * 8 + (dim + 5) * N * 8;           // states, aux
   b += N * L + W * Np * L + nc * N * 8 + nc * N * L;  // alpha, d, U^L, F^H
   b += 3 * N * 8 + 2 * W * Np * L + nc * N * 8;      // bounds, l~ (2), U^(1)
@@ -920,6 +920,7 @@ int create_impl(const Layout &Lt, const ns_params *p, void *stream, ns_solver **
   NS_ALLOC(s->mi, N);
   NS_ALLOC(s->rmi, N);
   NS_ALLOC(s->lfac, N);
+  NS_ALLOC(s->crm, N);
   NS_ALLOC(s->rrel, N);
   NS_ALLOC(s->wall, N);
   for (int b = 0; b < 3; ++b) NS_ALLOC(s->S[b], nc * N);
@@ -989,7 +990,7 @@ int create_impl(const Layout &Lt, const ns_params *p, void *stream, ns_solver **
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return bail(NS_EHIP, "graph upload failed");
     // node data; padding rows: m_i = 1, |I(i)| - 1 := 1, r_i = 0, no wall
-    std::vector<double> mi(N, 1.0), rmi(N, 1.0), lfac(N, 1.0), rrel(N, 0.0);
+    std::vector<double> mi(N, 1.0), rmi(N, 1.0), lfac(N, 1.0), crm(N, 1.0), rrel(N, 0.0);
     std::vector<uint8_t> wall(N, 0);
     std::vector<int32_t> sidx;
     std::vector<double> nrm;  // unit normals of the slip nodes, node by node
@@ -1006,6 +1007,7 @@ int create_impl(const Layout &Lt, const ns_params *p, void *stream, ns_solver **
         mi[b0 + i] = mr[i];
         rmi[b0 + i] = 1.0 / mr[i];
         lfac[b0 + i] = (double)(cnt[b0 + i] - 1);
+        crm[b0 + i] = lfac[b0 + i] * rmi[b0 + i];
         rrel[b0 + i] = p->relax * std::pow(mr[i] / vol, 1.5 / dim);
         wall[b0 + i] = wr[i];
         if (!wr[i]) continue;
@@ -1058,6 +1060,7 @@ int create_impl(const Layout &Lt, const ns_params *p, void *stream, ns_solver **
         {s->mi, mi.data(), N * sizeof(double)},
         {s->rmi, rmi.data(), N * sizeof(double)},
         {s->lfac, lfac.data(), N * sizeof(double)},
+        {s->crm, crm.data(), N * sizeof(double)},
         {s->rrel, rrel.data(), N * sizeof(double)},
         {s->wall, wall.data(), (size_t)N},
         {s->slip_idx, sidx.data(), sidx.size() * sizeof(int32_t)},
@@ -1906,13 +1909,14 @@ int ns_get_debug(ns_solver *s, int what, double *out) {
   const float *srcf = nullptr;  // FP32 storage in the mixed-precision mode
   int64_t count = 0;
   bool edge = false, node = false;  // node: a node vector (node_layout.hpp)
+  int K = (int)nc;                   // its components
   switch (what) {
     case NS_DBG_STAGE_OUT: src = s->S[s->last_out]; count = nc * N; node = true; break;
     case NS_DBG_D: src = s->d; srcf = s->df; count = W * Np; edge = true; break;
     case NS_DBG_ALPHA: src = s->alpha; srcf = s->alphaf; count = N; break;
     case NS_DBG_UL: src = s->UL; count = nc * N; node = true; break;
     case NS_DBG_FH: src = s->FH; srcf = s->FHf; count = nc * N; node = true; break;
-    case NS_DBG_BOUNDS: src = s->bnds; count = 3 * N; break;
+    case NS_DBG_BOUNDS: src = s->bnds; count = 3 * N; node = true; K = 3; break;
     case NS_DBG_LT1: src = s->lt1; srcf = s->lt1f; count = W * Np; edge = true; break;
     case NS_DBG_LT2: src = s->lt2; srcf = s->lt2f; count = W * Np; edge = true; break;
     case NS_DBG_U1: src = s->U1; count = nc * N; node = true; break;
@@ -1944,8 +1948,8 @@ int ns_get_debug(ns_solver *s, int what, double *out) {
       for (int64_t i = 0; i < N; ++i)
         out[k * N + i] = tmp[((i >> 6) * W + k) * 64 + (i & 63)];
   } else if (node) {
-    for (int c = 0; c < nc; ++c)
-      for (int64_t i = 0; i < N; ++i) out[c * N + i] = tmp[ns::node_at((int)nc, c, i, N)];
+    for (int c = 0; c < K; ++c)
+      for (int64_t i = 0; i < N; ++i) out[c * N + i] = tmp[ns::node_at(K, c, i, N)];
   } else if (raw) {
     std::copy(tmp.begin(), tmp.end(), out);
   }
