@@ -1049,6 +1049,7 @@ __device__ __forceinline__ void lim2_row(const DevGraphT<LT> &G, const StageArgs
     const Bounds b = BOTH ? bi : load_bounds(A, N, i);
     LT *__restrict__ lt2 = A.lt2;
     uint32_t slow = 0;
+    uint32_t nzm = 0;  // slots whose stored product may be nonzero (k_fin)
     if constexpr (!CACHE) {
       // reload the neighbour data rather than keep a whole row of it live
       asm volatile("" ::: "memory");
@@ -1110,9 +1111,12 @@ __device__ __forceinline__ void lim2_row(const DevGraphT<LT> &G, const StageArgs
           if (limit_fast<DIM, SEV>(g, u1, P[kk], b, &l2)) slow |= 1u << k;
           else l2 *= s1;
         }
-        st_once(&lt2[eidx<DIM>(k, i)], to_lt_down<LT>(l2));
+        const LT sv = to_lt_down<LT>(l2);
+        st_once(&lt2[eidx<DIM>(k, i)], sv);
+        if (sv != LT(0) || ((slow >> k) & 1u)) nzm |= 1u << k;
       }
     }
+    if constexpr (DIM == 2) A.nzm[i] = nzm;
     if (slow) {
       uint32_t *__restrict__ q2 = A.q2 ? A.q2 : A.q;
       uint32_t t = atomicAdd(&A.qcnt[1], (uint32_t)__builtin_popcount(slow));
@@ -1284,8 +1288,8 @@ __device__ __forceinline__ void fin_row(const DevGraphT<LT> &G, const StageArgsT
   // (1 - l_ij) >= 0 and equal at ij and ji, and rounding is monotone, so the
   // smaller stored product is min(l~'_ij, l~'_ji) (1 - l_ij) itself.  It is
   // 0 wherever pass 1 took the whole P_ij (most entries away from shocks).
-  // 2D: first the entries with a weight, then -- only in rows that have one,
-  // a few in a hundred -- the row's own data and the P_ij of those entries.
+  // 2D: only rows with such an entry, a few in a hundred, load their own
+  // data and the P_ij of those entries.
   // 3D, where most rows behind the shock have such entries, keeps one
   // unrolled pass (the entry-by-entry loop doubled the sweep's time there).
   if constexpr (DIM == 3) {
@@ -1324,29 +1328,9 @@ __device__ __forceinline__ void fin_row(const DevGraphT<LT> &G, const StageArgsT
     finish<DIM>(G, A, i, u2);
     return;
   }
-  uint32_t nz = 0;
-#pragma unroll
-  for (int ch = 0; ch < C::NCH; ++ch) {
-    jv.fence();
-    double l2a[C::CH], l2b[C::CH];
-    int32_t jc[C::CH];
-#pragma unroll
-    for (int kk = 0; kk < C::CH; ++kk) {
-      const int k = ch * C::CH + kk;
-      const int64_t e = eidx<DIM>(k, i);
-      jc[kk] = jv[k];
-      if (k == C::W / 2) continue;  // the diagonal
-      const int64_t js = jc[kk] >= 0 ? jc[kk] : i;
-      l2a[kk] = lt2[e];
-      l2b[kk] = lt2[eidx<DIM>(tslot<DIM>(k), js)];
-    }
-#pragma unroll
-    for (int kk = 0; kk < C::CH; ++kk) {
-      const int k = ch * C::CH + kk;
-      if (jc[kk] < 0 || jc[kk] == i) continue;
-      if (fmin(l2a[kk], l2b[kk]) != 0.0) nz |= 1u << k;
-    }
-  }
+  // the row's slots whose stored product may be nonzero, from k_lim2 (an
+  // entry needs its own product nonzero)
+  uint32_t nz = A.nzm[i];
   if (nz) {
     RowCtx<DIM> R;
     load_row<DIM>(G, A, i, A.tau[member(A, i)], R);

@@ -96,6 +96,9 @@ struct StageArgsT {
   // counters)
   uint32_t *q2 = nullptr;
   uint32_t *drow = nullptr;
+  // 2D: per row, bit k set where the stored pass-2 product of slot k may be
+  // nonzero (written by the pass-2 search, read by k_fin); N entries
+  uint32_t *nzm = nullptr;
   // A pack of several meshes stepped together: member of every 256-row
   // workgroup (each member's rows start at a workgroup boundary; padding
   // rows are isolated nodes), member count and workgroup offsets of the

@@ -165,6 +165,7 @@ struct ns_solver {
          *U1 = nullptr, *partial = nullptr, *tau = nullptr;
   int *flags = nullptr;
   uint32_t *q = nullptr, *qcnt = nullptr;
+  uint32_t *nzm = nullptr;  // 2D: slots with a pass-2 weight, per row
   // host copies of device scalars (pageable: no pinned allocation, whose
   // release would synchronize the whole device)
   int hflags[4] = {0, 0, 0, 0};
@@ -223,7 +224,7 @@ struct ns_solver {
     b.U = a.U; b.Un = a.Un; b.out = a.out; b.aux = a.aux; b.UL = a.UL; b.bnds = a.bnds;
     b.U1 = a.U1; b.partial = a.partial; b.tau = a.tau; b.flags = a.flags;
     b.sa = a.sa; b.sb = a.sb; b.check_cfl = a.check_cfl; b.q = a.q; b.qcnt = a.qcnt;
-    b.q2 = a.q2; b.drow = a.drow;
+    b.q2 = a.q2; b.drow = a.drow; b.nzm = a.nzm;
     b.seg = a.seg; b.mblk = a.mblk; b.nmem = a.nmem; b.check_low = a.check_low;
     b.alpha = alphaf; b.d = df; b.FH = FHf; b.lt1 = lt1f; b.lt2 = lt2f;
     b.fp32_eval = fp32_eval && !redo_fp64;
@@ -239,6 +240,7 @@ struct ns_solver {
     a.q = q; a.qcnt = qcnt;
     a.q2 = q + (int64_t)W * Np;  // the pass-2 list and the deferred rows
     a.drow = q + 2 * (int64_t)W * Np;
+    a.nzm = nzm;
     a.seg = seg; a.mblk = mblk; a.nmem = nmem;
     return a;
   }
@@ -805,6 +807,7 @@ int64_t footprint(const Layout &Lt, const ns_params *p) {
   b += 3 * nc * N * 8 + (dim + 5) * N * 8;           // states, aux
   b += N * L + W * Np * L + nc * N * 8 + nc * N * L;  // alpha, d, U^L, F^H
   b += 3 * N * 8 + 2 * W * Np * L + nc * N * 8;      // bounds, l~ (2), U^(1)
+  b += N * 4;                                        // pass-2 weight mask
   b += nblocks * 8 + nm * (8 + 4 * 4 + 8);           // partial, tau, flags, time
   b += (2 * W * Np + Np) * 4 + 4 * 4;                // root work lists, deferred rows
   b += nslip * 4 + dim * nslip * 8;                  // slip list
@@ -941,6 +944,7 @@ int create_impl(const Layout &Lt, const ns_params *p, void *stream, ns_solver **
   NS_ALLOC(s->UL, nc * N);
   NS_ALLOC(s->bnds, 3 * N);
   NS_ALLOC(s->U1, nc * N);
+  NS_ALLOC(s->nzm, N);
   NS_ALLOC(s->partial, nblocks);
   NS_ALLOC(s->tau, s->nmem);
   NS_ALLOC(s->flags, 4 * s->nmem);
