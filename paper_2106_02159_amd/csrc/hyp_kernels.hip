@@ -698,7 +698,17 @@ __device__ __forceinline__ void lo_row(const DevGraphT<LT> &G, const StageArgsT<
     fs[q] = to_lt<LT>(fh[q] * rmi);
   }
   store_state<NC>(A.UL, N, i, ul);
-  store_state<NC>(A.FH, N, i, fs);
+  if constexpr (DIM == 3) {
+    // alpha_i beside F^H's fifth component: a neighbour's F^H and alpha come
+    // in three 16-byte loads in the limiter sweeps
+    LT f6[NC + 1];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) f6[q] = fs[q];
+    f6[NC] = alpha[i];
+    store_state<NC + 1>(A.FH, N, i, f6);
+  } else {
+    store_state<NC>(A.FH, N, i, fs);
+  }
   if (A.check_cfl && tau > G.mi[i] / (2.0 * dsum)) A.flags[4 * mem] = 1;
   if (A.check_low) {
     double m2 = 0.0;
@@ -733,8 +743,16 @@ __device__ __forceinline__ void load_row(const DevGraphT<LT> &G, const StageArgs
   constexpr int NC = DIM + 2;
   const int64_t N = G.N;
   load_state<NC>(A.U, N, i, R.ui);
-  load_state<NC>(A.FH, N, i, R.fi);
-  R.ali = A.alpha[i];
+  if constexpr (DIM == 3) {
+    double f6[NC + 1];
+    load_state<NC + 1>(A.FH, N, i, f6);  // F^H / m_i and alpha_i
+#pragma unroll
+    for (int q = 0; q < NC; ++q) R.fi[q] = f6[q];
+    R.ali = f6[NC];
+  } else {
+    load_state<NC>(A.FH, N, i, R.fi);
+    R.ali = A.alpha[i];
+  }
   R.coef = tau * G.crm[i];
 }
 
@@ -752,8 +770,16 @@ __device__ __forceinline__ void gather_P(const DevGraphT<LT> &G, const StageArgs
   constexpr int NC = DIM + 2;
   const int64_t N = G.N;
   load_state<NC>(A.U, N, js, x.u);
-  load_state<NC>(A.FH, N, js, x.f);
-  x.al = A.alpha[js];
+  if constexpr (DIM == 3) {
+    double f6[NC + 1];
+    load_state<NC + 1>(A.FH, N, js, f6);  // F^H / m_j and alpha_j
+#pragma unroll
+    for (int q = 0; q < NC; ++q) x.f[q] = f6[q];
+    x.al = f6[NC];
+  } else {
+    load_state<NC>(A.FH, N, js, x.f);
+    x.al = A.alpha[js];
+  }
   x.d = ld_once(&A.d[e]);
   x.m = mij;
 }

@@ -67,7 +67,8 @@ struct StageArgsT {
   LT *alpha;         // N
   LT *d;             // W*Np (FP32: rounded up, still an upper bound)
   double *UL;        // nc*N
-  LT *FH;            // nc*N
+  LT *FH;            // nc*N: F^H_i / m_i, a node vector (3D: (nc+1)*N, with
+                     // alpha_i as component nc)
   double *bnds;      // 3*N: rho_min, rho_max, Phi_min (a node vector,
                      // node_layout.hpp)
   LT *lt1;           // W*Np (FP32: rounded down, still feasible)

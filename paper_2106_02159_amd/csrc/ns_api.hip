@@ -805,7 +805,7 @@ int64_t footprint(const Layout &Lt, const ns_params *p) {
   b += nm * (int64_t)sizeof(ns::BoxGeom);             // box geometry
   b += 5 * N * 8 + N;                                // m_i, 1/m_i, lfac, lfac/m_i, r_i, wall
   b += 3 * nc * N * 8 + (dim + 5) * N * 8;           // states, aux
-  b += N * L + W * Np * L + nc * N * 8 + nc * N * L;  // alpha, d, U^L, F^H
+  b += N * L + W * Np * L + nc * N * 8 + (nc + (dim == 3)) * N * L;  // alpha, d, U^L, F^H
   b += 3 * N * 8 + 2 * W * Np * L + nc * N * 8;      // bounds, l~ (2), U^(1)
   b += N * 4;                                        // pass-2 weight mask
   b += nblocks * 8 + nm * (8 + 4 * 4 + 8);           // partial, tau, flags, time
@@ -931,13 +931,13 @@ int create_impl(const Layout &Lt, const ns_params *p, void *stream, ns_solver **
   if (s->mixed) {
     NS_ALLOC(s->alphaf, N);
     NS_ALLOC(s->df, W * Np);
-    NS_ALLOC(s->FHf, nc * N);
+    NS_ALLOC(s->FHf, (nc + (dim == 3)) * N);  // 3D: alpha beside F^H
     NS_ALLOC(s->lt1f, W * Np);
     NS_ALLOC(s->lt2f, W * Np);
   } else {
     NS_ALLOC(s->alpha, N);
     NS_ALLOC(s->d, W * Np);
-    NS_ALLOC(s->FH, nc * N);
+    NS_ALLOC(s->FH, (nc + (dim == 3)) * N);
     NS_ALLOC(s->lt1, W * Np);
     NS_ALLOC(s->lt2, W * Np);
   }
@@ -1913,14 +1913,16 @@ int ns_get_debug(ns_solver *s, int what, double *out) {
   const float *srcf = nullptr;  // FP32 storage in the mixed-precision mode
   int64_t count = 0;
   bool edge = false, node = false;  // node: a node vector (node_layout.hpp)
-  int K = (int)nc;                   // its components
+  int K = (int)nc, Kout = (int)nc;   // its components, the first Kout exported
   switch (what) {
     case NS_DBG_STAGE_OUT: src = s->S[s->last_out]; count = nc * N; node = true; break;
     case NS_DBG_D: src = s->d; srcf = s->df; count = W * Np; edge = true; break;
     case NS_DBG_ALPHA: src = s->alpha; srcf = s->alphaf; count = N; break;
     case NS_DBG_UL: src = s->UL; count = nc * N; node = true; break;
-    case NS_DBG_FH: src = s->FH; srcf = s->FHf; count = nc * N; node = true; break;
-    case NS_DBG_BOUNDS: src = s->bnds; count = 3 * N; node = true; K = 3; break;
+    case NS_DBG_FH:
+      src = s->FH; srcf = s->FHf; count = (nc + (s->dim == 3)) * N; node = true;
+      K = (int)nc + (s->dim == 3); break;
+    case NS_DBG_BOUNDS: src = s->bnds; count = 3 * N; node = true; K = Kout = 3; break;
     case NS_DBG_LT1: src = s->lt1; srcf = s->lt1f; count = W * Np; edge = true; break;
     case NS_DBG_LT2: src = s->lt2; srcf = s->lt2f; count = W * Np; edge = true; break;
     case NS_DBG_U1: src = s->U1; count = nc * N; node = true; break;
@@ -1952,7 +1954,7 @@ int ns_get_debug(ns_solver *s, int what, double *out) {
       for (int64_t i = 0; i < N; ++i)
         out[k * N + i] = tmp[((i >> 6) * W + k) * 64 + (i & 63)];
   } else if (node) {
-    for (int c = 0; c < K; ++c)
+    for (int c = 0; c < Kout; ++c)  // out holds Kout*N values
       for (int64_t i = 0; i < N; ++i) out[c * N + i] = tmp[ns::node_at(K, c, i, N)];
   } else if (raw) {
     std::copy(tmp.begin(), tmp.end(), out);
