@@ -461,6 +461,17 @@ class Solver:
         self._check(lib().ns_get_state(self.h, _ptr(out), 0))
         return out
 
+    def set_state_device(self, ptr: int, project=True):
+        """State from a component-major nc*N FP64 array in device memory at
+        address ptr (complete before the call)."""
+        self._check(lib().ns_set_state(self.h, C.c_void_p(ptr),
+                                       ON_DEVICE | (0 if project else NO_PROJECT)))
+
+    def get_state_device(self, ptr: int):
+        """State into a component-major nc*N FP64 array in device memory at
+        address ptr (complete on return)."""
+        self._check(lib().ns_get_state(self.h, C.c_void_p(ptr), ON_DEVICE))
+
     def compute_dt(self) -> float:
         dt = C.c_double()
         self._check(lib().ns_compute_dt(self.h, C.byref(dt)))
