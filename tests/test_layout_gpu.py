@@ -20,28 +20,62 @@ def say(*a):
     print(*a, flush=True)
 
 
+class _Hip:
+    """Device buffers for the test through the HIP runtime the library uses
+    (hipMalloc / hipMemcpy / hipFree via ctypes)."""
+
+    def __init__(self):
+        import ctypes
+
+        self.C = ctypes
+        self.lib = ctypes.CDLL("/opt/rocm/lib/libamdhip64.so", mode=ctypes.RTLD_GLOBAL)
+
+    def alloc(self, nbytes):
+        p = self.C.c_void_p()
+        assert self.lib.hipMalloc(self.C.byref(p), self.C.c_size_t(nbytes)) == 0
+        return p.value
+
+    def h2d(self, ptr, a):
+        assert self.lib.hipMemcpy(self.C.c_void_p(ptr), a.ctypes.data_as(self.C.c_void_p),
+                                  self.C.c_size_t(a.nbytes), 1) == 0  # host to device
+
+    def d2h(self, a, ptr):
+        assert self.lib.hipMemcpy(a.ctypes.data_as(self.C.c_void_p), self.C.c_void_p(ptr),
+                                  self.C.c_size_t(a.nbytes), 2) == 0  # device to host
+
+    def free(self, ptr):
+        assert self.lib.hipFree(self.C.c_void_p(ptr)) == 0
+
+
 @pytest.mark.parametrize("dim,n", [(2, 37), (3, 9)])
 def test_state_through_device_pointers(dim, n):
-    torch = pytest.importorskip("torch")
     mesh, U = W.four_quadrant_state(n, seed=2) if dim == 2 else W.shock_tube_state(n, seed=2)
+    U = np.ascontiguousarray(U, np.float64)
     say("device-pointer state transfer", dim, n)
     s = abi.Solver(abi.Graph(mesh))
-    dU = torch.from_numpy(np.ascontiguousarray(U)).to("cuda")
-    out = torch.empty_like(dU)
-    torch.cuda.synchronize()
-    s.set_state_device(dU.data_ptr(), project=False)
-    assert np.array_equal(s.get_state(), U)
-    s.get_state_device(out.data_ptr())
-    assert np.array_equal(out.cpu().numpy(), U)
-    # after a step: the device copy equals the host copy
-    s.step(s.compute_dt())
-    h = s.get_state()
-    s.get_state_device(out.data_ptr())
-    assert np.array_equal(out.cpu().numpy(), h)
-    # host upload of the device copy's values gives the same state back
-    s2 = abi.Solver(abi.Graph(mesh))
-    s2.set_state(h, project=False)
-    assert np.array_equal(s2.get_state(), h)
+    hip = _Hip()
+    dU, dout = hip.alloc(U.nbytes), hip.alloc(U.nbytes)
+    try:
+        hip.h2d(dU, U)
+        s.set_state_device(dU, project=False)
+        assert np.array_equal(s.get_state(), U)
+        out = np.empty_like(U)
+        s.get_state_device(dout)
+        hip.d2h(out, dout)
+        assert np.array_equal(out, U)
+        # after a step: the device copy equals the host copy
+        s.step(s.compute_dt())
+        h = s.get_state()
+        s.get_state_device(dout)
+        hip.d2h(out, dout)
+        assert np.array_equal(out, h)
+        # host upload of those values gives the same state back
+        s2 = abi.Solver(abi.Graph(mesh))
+        s2.set_state(h, project=False)
+        assert np.array_equal(s2.get_state(), h)
+    finally:
+        hip.free(dU)
+        hip.free(dout)
 
 
 def finish(s):
