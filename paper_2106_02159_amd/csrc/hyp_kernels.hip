@@ -641,6 +641,13 @@ __device__ __forceinline__ void lo_row(const DevGraphT<LT> &G, const StageArgsT<
 #pragma unroll
   for (int q = 0; q < NC; ++q) { acc[q] = 0.0; fh[q] = 0.0; }
   double rmin = ui[0], rmax = ui[0], phimin = aux[X::PHI * N + i], dsum = 0.0;
+  // sum_j (f(U_j) - f(U_i)) c_ij: the row's own flux enters once, against
+  // the sum of c_ij over the off-diagonal entries (only its density
+  // component is needed entry by entry, for the bar states)
+  double csum[DIM];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) csum[k] = 0.0;
+  double vci = 0.0;  // v_i . c_ij of the current entry
 #pragma unroll
   for (int ch = 0; ch < C::NCH; ++ch) {
     jv.fence();
@@ -662,19 +669,25 @@ __device__ __forceinline__ void lo_row(const DevGraphT<LT> &G, const StageArgsT<
     for (int kk = 0; kk < C::CH; ++kk) {
       const int32_t j = jc[kk];
       if (j < 0) continue;
-      double fci[NC];
-      flux_dot<DIM>(ui, vi, pi, c[kk], fci);
       if (j == i) {
+        double fci[NC];
+        flux_dot<DIM>(ui, vi, pi, c[kk], fci);
 #pragma unroll
         for (int q = 0; q < NC; ++q) fh[q] -= fci[q];
         continue;
+      }
+      vci = 0.0;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        vci += vi[k] * c[kk][k];
+        csum[k] += c[kk][k];
       }
       double fcj[NC], vj[DIM], pj;
       vel_pres<DIM>(g, uj[kk], vj, pj);
       flux_dot<DIM>(uj[kk], vj, pj, c[kk], fcj);
       const double dk = dij[kk];
       // density of the bar state (eq. bar_state) for the local bounds
-      const double rbar = 0.5 * (ui[0] + uj[kk][0]) - (fcj[0] - fci[0]) * fast_rcp(2.0 * dk);
+      const double rbar = 0.5 * (ui[0] + uj[kk][0]) - (fcj[0] - ui[0] * vci) * fast_rcp(2.0 * dk);
       rmin = fmin(rmin, rbar);
       rmax = fmax(rmax, rbar);
       phimin = fmin(phimin, phij[kk]);
@@ -682,11 +695,17 @@ __device__ __forceinline__ void lo_row(const DevGraphT<LT> &G, const StageArgsT<
 #pragma unroll
       for (int q = 0; q < NC; ++q) {
         const double du = uj[kk][q] - ui[q];
-        acc[q] += dk * du - (fcj[q] - fci[q]);
+        acc[q] += dk * du - fcj[q];
         fh[q] += -fcj[q] + dH * du;
       }
       dsum += dk;
     }
+  }
+  {
+    double fcs[NC];
+    flux_dot<DIM>(ui, vi, pi, csum, fcs);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) acc[q] += fcs[q];
   }
   const double rmi = G.rmi[i];
   const double tm = tau * rmi;
