@@ -825,8 +825,8 @@ int ns_solver_footprint(const ns_graph *g, const ns_params *p, int64_t *bytes) {
 
 namespace {
 // Keep memory freed by hipFreeAsync in the device's default pool instead of
-// returning it to the driver, so that solvers created after others were
-// destroyed reuse it without new driver allocations.
+// returning it to the GPU kernel driver, so that solvers created after
+// others were destroyed reuse it without new allocations from the system.
 // (solvers may be created from several threads: once per device)
 void keep_pool_memory() {
   static std::mutex mu;
