@@ -21,7 +21,10 @@
  *   - Status codes: NS_OK (0) or a negative NS_E* value.  No call throws.
  *   - A state is structure-of-arrays double precision: U[c*N + i] is
  *     component c of node i; c = 0 density rho, 1..dim momentum m,
- *     dim+1 total energy E; nc = dim+2 components.
+ *     dim+1 total energy E; nc = dim+2 components.  (On the device the
+ *     library keeps node vectors with components 2p and 2p+1 of a node side
+ *     by side; the state and debug calls convert, host buffers on the host,
+ *     device buffers by a kernel on the solver's stream.)
  *   - Nodes are numbered lexicographically, x fastest:
  *     i = ix + nx*(iy + ny*iz).
  *   - All device work of a solver is ordered on one HIP stream.  Calls on
